@@ -1,0 +1,220 @@
+/*
+ * libmfs -- MI355X (gfx950) implementation of the hot path of the
+ * axisymmetric method-of-fundamental-solutions (MFS) solver for acoustic
+ * scattering from doubly-periodic arrays of axisymmetric obstacles
+ * (Liu & Barnett, J. Comput. Phys. 2016).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns mfs_status; no C++ exception crosses this ABI.  On a
+ *    non-zero status mfs_last_error() returns a thread-local message.
+ *  - Complex numbers are mfs_c128 = two doubles (re, im), the layout of
+ *    torch.complex128 and of C99 double _Complex.
+ *  - "host" pointers are read (or written) during the call; the caller keeps
+ *    ownership.  "dev" pointers are caller-owned device memory on the
+ *    context's GPU, 16-byte aligned and contiguous; work on them is queued on
+ *    `stream` (a hipStream_t, NULL = the legacy default stream) and they must
+ *    stay valid until that stream has been synchronised.
+ *  - Library-owned objects (mfs_ctx, mfs_op) hold all factor storage and are
+ *    released with the matching mfs_destroy_* call.
+ *  - Mode arrays use FFT bin order: bin b (0 <= b < P) holds the azimuthal
+ *    mode n = b for b <= P/2 and n = b - P above, n = -P/2+1..P/2 (Sec. 3,
+ *    after eq. (fhat)).  A mode-n coefficient multiplies a field varying as
+ *    e^{+i n phi}.  Angles are phi_l = 2 pi l / P, l = 0..P-1.
+ *  - Calls on one context are not thread safe; use one context per thread
+ *    or an external lock.
+ */
+#ifndef MFS_H
+#define MFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFS_OK = 0,
+  MFS_EINVAL = 1,   /* bad argument; nothing was written                     */
+  MFS_ENOMEM = 2,   /* device or host allocation failed                       */
+  MFS_EDEVICE = 3,  /* a HIP call failed                                      */
+  MFS_ENOTCONV = 4, /* GMRES hit maxit; results hold the last iterate         */
+  MFS_ESTATE = 5,   /* call out of order (e.g. apply before factor)          */
+  MFS_EBUSY = 6
+} mfs_status;
+
+typedef struct { double re, im; } mfs_c128;
+
+typedef struct mfs_ctx mfs_ctx;
+typedef struct mfs_op mfs_op;
+
+/* One axisymmetric body and its one-body discretisation (Sec. 3).
+ * M collocation points (rho_m, z_m) on the generating curve with outward unit
+ * normals (nrho_m, nz_m); N MFS sources (srho_j > 0, sz_j) inside the body;
+ * P azimuthal modes (even, >= 2); q trapezoid nodes for the ring-kernel fill
+ * (eq. (ptr); even, q >= P); k > 0 the wavenumber.  M >= N. */
+typedef struct {
+  int32_t M, N, P, q;
+  double k;
+  const double *rho, *z, *nrho, *nz; /* host [M] */
+  const double *srho, *sz;           /* host [N] */
+} mfs_body;
+
+/* Polar generating curve r(t) = a (1 + eps cos(j t)), rho = r sin t,
+ * z = r cos t, t in [0, pi] (Sec. 3); sources at t_j = pi (j - 1/2)/N moved
+ * into the body by complexification Z(t_j - i tau), Z = rho + i z (Sec. 3.2,
+ * method (c)); collocation colloc = 0: t_m = pi (m - 1/2)/M,
+ * colloc = 1: Gauss-Legendre nodes in t. */
+typedef struct {
+  double a, eps;
+  int32_t j;
+  int32_t colloc;
+  int32_t M, N;
+  double tau;
+} mfs_polar_spec;
+
+/* Rectangular lattice e_x, e_y; unit cell |z| <= z0; periodizer: harmonic
+ * degree p, Rayleigh-Bloch cutoff kappa_x^2 + kappa_y^2 <= (pi N0)^2, M1 x M1
+ * Gauss nodes per wall (M1 even) (Sec. 4, Sec. 4.1). */
+typedef struct {
+  double ex, ey, z0;
+  int32_t p;
+  double N0;
+  int32_t M1;
+} mfs_lattice;
+
+/* Incident plane wave from above, k_vec = k (sin th cos ph, sin th sin ph,
+ * -cos th) (eq. (ui)). */
+typedef struct { double theta, phi; } mfs_wave;
+
+/* Per-wave result of mfs_solve_incident.  The caller provides the arrays
+ * and their capacities; the library fills them.  Bragg orders are listed by
+ * m, then n (m, n, kappa_z as in eqs. (rb1)-(rb2)). */
+typedef struct {
+  int32_t iters;          /* GMRES iterations                                 */
+  double resid;           /* final relative residual of eq. (iter)            */
+  int32_t norders;        /* number of Bragg orders kept                      */
+  int32_t cap_orders;     /* capacity of m, n, kz, a, b                       */
+  int32_t *m, *n;         /* host [cap_orders]                                */
+  mfs_c128 *kz;           /* host [cap_orders] kappa_z (+real or +imag)      */
+  mfs_c128 *a, *b;        /* host [cap_orders] upward / downward amplitudes   */
+  mfs_c128 *field;        /* host [ntargets] scattered field u at targets     */
+  double eps_flux;        /* energy-flux defect (Sec. 5)                     */
+  int32_t q_rank;         /* numerical rank kept in Q^+                       */
+  int32_t nq_cols;        /* columns of Q                                     */
+} mfs_result;
+
+/* Timing of the last mfs_solve_incident stages, milliseconds (HIP events). */
+typedef struct {
+  double rhs, periodizer, gmres, recover, total;
+  double nsum_avg;        /* mean duration of one neighbour-sum launch       */
+  int32_t nsum_launches;
+} mfs_solve_timing;
+
+const char *mfs_last_error(void);
+const char *mfs_version(void);
+
+/* Create a context on HIP device `device`.  Allocates nothing large. */
+mfs_status mfs_create(int device, mfs_ctx **out);
+void mfs_destroy(mfs_ctx *ctx);
+
+/* Host helper: geometry of a polar body, written into caller arrays
+ * rho, z, nrho, nz [spec->M] and srho, sz [spec->N] (Sec. 3, Sec. 3.2). */
+mfs_status mfs_polar_geometry(const mfs_polar_spec *spec, double *rho, double *z,
+                              double *nrho, double *nz, double *srho, double *sz);
+
+/* (a) Modal fill (eqs. (ringkernelderiv), (ptr)): for each body, the P/2+1
+ * distinct blocks A'_n, n = 0..P/2 (A'_{-n} = A'_n) of size M x N,
+ *   A'_n[m, j] = (1/q) sum_{l=0}^{q-1} dG/dn_x((rho_m,0,z_m); y_j(2 pi l/q)) e^{-i n 2 pi l/q},
+ * G = e^{ikR}/(4 pi R) (eq. (G)).  Host arrays are copied; the operator owns
+ * the blocks.  Returns EINVAL for P odd, q < P, q odd, M < N, srho <= 0 or
+ * non-finite input. */
+mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbodies,
+                              void *stream, mfs_op **out);
+void mfs_destroy_op(mfs_op *op);
+
+/* Copy the filled blocks of one body, before factorisation, to dev
+ * out [P/2+1][N][M] (column-major M x N per mode n = 0..P/2).  ESTATE after
+ * mfs_factor_modes (the blocks are overwritten in place). */
+mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *stream);
+
+/* (b) Per-mode factorisation (Sec. 3 and Sec. 4.2): blocked Householder QR
+ * A'_n = Q_n R_n, SVD of R_n by one-sided Jacobi, singular values below
+ * rel_cutoff * s_max dropped; keeps U_n = Q_n W_n (M x r) and V_n S_n^+
+ * (N x r) so that A'_n^+ x = V_n S_n^+ (U_n^* x) is applied without forming
+ * the pseudoinverse.  Blocking until done.  ranks (host, optional) receives
+ * the kept rank of each distinct block, [sum over bodies of P/2+1]. */
+mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks);
+
+/* Singular values (descending) of the distinct blocks of one body, host
+ * out [P/2+1][N].  ESTATE before mfs_factor_modes. */
+mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out);
+
+/* (c) Solution-operator apply: c_n = A'_n^+ x_n for every mode of nrhs
+ * right-hand sides.  in: dev [nrhs][P][M] mode coefficients (FFT bin order);
+ * out: dev [nrhs][P][N].  ESTATE before mfs_factor_modes. */
+mfs_status mfs_apply_solution_op(const mfs_op *op, int32_t body, int32_t nrhs,
+                                 const mfs_c128 *in, mfs_c128 *out, void *stream);
+
+/* Right-hand side of eq. (linsys): f = -du^i/dn at the P x M surface points
+ * then f_hat_n = (1/P) sum_l f(phi_l) e^{-i n phi_l} (eq. (fhatquad), q = P).
+ * kvec: host [nwaves][3] wave vectors; out: dev [nwaves][P][M]. */
+mfs_status mfs_rhs_modes(const mfs_op *op, int32_t body, int32_t nwaves, const double *kvec,
+                         mfs_c128 *out, void *stream);
+
+/* Point-source form (Sec. 4.1): sigma_{jl} = (1/qs) sum_n c_{nj} e^{+i n 2 pi l/qs}
+ * for qs >= P.  c: dev [nrhs][P][N]; sigma: dev [nrhs][qs][N]. */
+mfs_status mfs_point_strengths(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
+                               const mfs_c128 *c, mfs_c128 *sigma, void *stream);
+
+/* Target sets of mfs_neighbour_sum. */
+enum {
+  MFS_TARGETS_SURFACE = 0, /* the P x M surface nodes, normal derivative, the
+                              8 non-central images (A_else before its FFT)  */
+  MFS_TARGETS_WALLS = 1,   /* the 8 M1^2 wall rows of C (eq. (full)), with the
+                              3x3 cancellation of Sec. 4.1                  */
+  MFS_TARGETS_USER = 2     /* user points, all 9 near copies                */
+};
+
+/* (c) Direct phased 3x3-neighbour Helmholtz sum (eqs. (A), (Phinear)) of the
+ * qs x N point sources y_{jl} + a e_x + b e_y with strengths sigma and
+ * weights alpha^a beta^b.
+ *   sigma: dev [nrhs][qs][N] (qs = P for SURFACE and WALLS);
+ *   ab:    host [nrhs][2] Bloch phases (alpha, beta);
+ *   user:  host [nuser][6] (x, y, z, dx, dy, dz) for USER targets: the output
+ *          is the value (want = 0) or the derivative along (dx,dy,dz)
+ *          (want = 1);
+ *   out:   dev [nrhs][ntargets] with ntargets = P*M (SURFACE, [l][m] order),
+ *          8*M1*M1 (WALLS, row order of eq. (full)) or nuser (USER). */
+mfs_status mfs_neighbour_sum(const mfs_op *op, int32_t body, const mfs_lattice *lat,
+                             int32_t nrhs, int32_t qs, const mfs_c128 *sigma, const mfs_c128 *ab,
+                             int32_t target_set, const double *user, int32_t nuser, int32_t want,
+                             mfs_c128 *out, void *stream);
+
+/* Free-space field u(x) = sum_{j,l} G(x, y_{jl}) sigma_{jl} of the qs-node
+ * point form of mode coefficients c (dev [nrhs][P][N]) at host targets
+ * [ntargets][3]; out: dev [nrhs][ntargets]. */
+mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
+                          const mfs_c128 *c, const double *targets, int32_t ntargets,
+                          mfs_c128 *out, void *stream);
+
+/* (c) Periodic solve for nwaves incident waves (Sec. 4.2): per wave, fill and
+ * factor Q = [S, -W] (SVD truncated at rel_cutoff relative), then GMRES on
+ * eq. (iter) (I + A_else A_0^+ - B Q^+ C A_0^+) eta~ = f_hat, unrestarted from
+ * zero, CGS2 orthogonalisation, stopping at ||r|| <= tol ||f_hat||;
+ * eta = A_0^+ eta~, xi = -Q^+ C eta; the Bragg amplitudes a, b; the field
+ * u at the host targets [ntargets][3] from eq. (urep) with q_field-node
+ * point sources; eps_flux.  Blocking.  Returns ENOTCONV if some wave hit
+ * maxit (its result holds the last iterate), EINVAL if a result's
+ * cap_orders is too small (norders is set so the caller can retry).
+ * timing (optional) receives stage times. */
+mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t body,
+                              const mfs_lattice *lat, int32_t nwaves, const mfs_wave *waves,
+                              double tol, int32_t maxit, double rel_cutoff,
+                              const double *targets, int32_t ntargets, int32_t q_field,
+                              mfs_result *res, mfs_solve_timing *timing);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFS_H */
