@@ -1,0 +1,357 @@
+"""Python binding of libmfs, the MI355X implementation of the axisymmetric
+MFS scattering solver (Liu & Barnett, doubly-periodic arrays of axisymmetric
+objects).  Argument marshalling only: every step of the computation runs in
+the HIP kernels of libmfs.so; PyTorch provides device memory and streams.
+
+The library must have been built (``python -m paper_1506_05083_amd.build``);
+importing the computational entry points without it raises RuntimeError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfs.so")
+_lib = None
+
+MFS_OK, MFS_EINVAL, MFS_ENOMEM, MFS_EDEVICE, MFS_ENOTCONV, MFS_ESTATE, MFS_EBUSY = range(7)
+TARGETS_SURFACE, TARGETS_WALLS, TARGETS_USER = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class C128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+_cp = C.POINTER(C128)
+
+
+class Body(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("P", C.c_int32), ("q", C.c_int32),
+                ("k", C.c_double), ("rho", _dp), ("z", _dp), ("nrho", _dp), ("nz", _dp),
+                ("srho", _dp), ("sz", _dp)]
+
+
+class PolarSpec(C.Structure):
+    _fields_ = [("a", C.c_double), ("eps", C.c_double), ("j", C.c_int32), ("colloc", C.c_int32),
+                ("M", C.c_int32), ("N", C.c_int32), ("tau", C.c_double)]
+
+
+class Lattice(C.Structure):
+    _fields_ = [("ex", C.c_double), ("ey", C.c_double), ("z0", C.c_double), ("p", C.c_int32),
+                ("N0", C.c_double), ("M1", C.c_int32)]
+
+
+class Wave(C.Structure):
+    _fields_ = [("theta", C.c_double), ("phi", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("resid", C.c_double), ("norders", C.c_int32),
+                ("cap_orders", C.c_int32), ("m", _ip), ("n", _ip), ("kz", _cp), ("a", _cp),
+                ("b", _cp), ("field", _cp), ("eps_flux", C.c_double), ("q_rank", C.c_int32),
+                ("nq_cols", C.c_int32)]
+
+
+class SolveTiming(C.Structure):
+    _fields_ = [("rhs", C.c_double), ("periodizer", C.c_double), ("gmres", C.c_double),
+                ("recover", C.c_double), ("total", C.c_double), ("nsum_avg", C.c_double),
+                ("nsum_launches", C.c_int32)]
+
+
+_SIGS = {
+    "mfs_last_error": (C.c_char_p, []),
+    "mfs_version": (C.c_char_p, []),
+    "mfs_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    "mfs_destroy": (None, [C.c_void_p]),
+    "mfs_polar_geometry": (C.c_int, [C.POINTER(PolarSpec), _dp, _dp, _dp, _dp, _dp, _dp]),
+    "mfs_build_operator": (C.c_int, [C.c_void_p, C.POINTER(Body), C.c_int32, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    "mfs_destroy_op": (None, [C.c_void_p]),
+    "mfs_op_blocks": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mfs_factor_modes": (C.c_int, [C.c_void_p, C.c_double, _ip]),
+    "mfs_op_singular_values": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
+    "mfs_rhs_modes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_void_p, C.c_void_p]),
+    "mfs_point_strengths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
+    "mfs_neighbour_sum": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Lattice), C.c_int32, C.c_int32,
+                                    C.c_void_p, _cp, C.c_int32, _dp, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.c_void_p]),
+    "mfs_field_free": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp,
+                                 C.c_int32, C.c_void_p, C.c_void_p]),
+    "mfs_solve_incident": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Lattice),
+                                     C.c_int32, C.POINTER(Wave), C.c_double, C.c_int32, C.c_double,
+                                     _dp, C.c_int32, C.c_int32, C.POINTER(Result),
+                                     C.POINTER(SolveTiming)]),
+}
+
+
+def lib():
+    """Load libmfs.so (raises RuntimeError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1506_05083_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MfsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libmfs status {status}: {msg}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != MFS_OK:
+        raise MfsError(st, lib().mfs_last_error().decode())
+
+
+def _ptr(a: np.ndarray, typ=_dp):
+    return a.ctypes.data_as(typ)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t):
+    import torch
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.complex128, "need contiguous cuda complex128"
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ API
+
+def polar_geometry(a: float, eps: float, j: int, M: int, N: int, tau: float, colloc: str = "mid"):
+    """Host geometry of a polar body (the library's own implementation)."""
+    spec = PolarSpec(a, eps, j, 1 if colloc == "gauss" else 0, M, N, tau)
+    out = {k: np.zeros(M) for k in ("rho", "z", "nrho", "nz")}
+    out.update({k: np.zeros(N) for k in ("srho", "sz")})
+    _check(lib().mfs_polar_geometry(C.byref(spec), _ptr(out["rho"]), _ptr(out["z"]), _ptr(out["nrho"]),
+                                    _ptr(out["nz"]), _ptr(out["srho"]), _ptr(out["sz"])))
+    return out
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().mfs_create(device, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mfs_destroy(self.h)
+            self.h = None
+
+
+def create(device: int = 0) -> Context:
+    return Context(device)
+
+
+@dataclass
+class BodySpec:
+    M: int
+    N: int
+    P: int
+    q: int
+    k: float
+    geom: dict
+
+
+class Operator:
+    def __init__(self, ctx: Context, bodies: Sequence[BodySpec]):
+        import torch
+        self.ctx = ctx
+        self.bodies = list(bodies)
+        keep = []
+        arr = (Body * len(bodies))()
+        for i, b in enumerate(bodies):
+            g = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in b.geom.items()}
+            keep.append(g)
+            arr[i] = Body(b.M, b.N, b.P, b.q, b.k, _ptr(g["rho"]), _ptr(g["z"]), _ptr(g["nrho"]),
+                          _ptr(g["nz"]), _ptr(g["srho"]), _ptr(g["sz"]))
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib().mfs_build_operator(ctx.h, arr, len(bodies), _stream(), C.byref(h)))
+        self.h = h
+        self.ranks = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mfs_destroy_op(self.h)
+            self.h = None
+
+    def blocks(self, body: int = 0):
+        import torch
+        b = self.bodies[body]
+        out = torch.empty((b.P // 2 + 1, b.N, b.M), dtype=torch.complex128, device="cuda")
+        _check(lib().mfs_op_blocks(self.h, body, _dev(out), _stream()))
+        torch.cuda.synchronize()
+        return out
+
+    def factor_modes(self, rel_cutoff: float = 1e-10):
+        import torch
+        n = sum(b.P // 2 + 1 for b in self.bodies)
+        r = np.zeros(n, dtype=np.int32)
+        torch.cuda.synchronize()
+        _check(lib().mfs_factor_modes(self.h, rel_cutoff, _ptr(r, _ip)))
+        self.ranks = r
+        return r
+
+    def singular_values(self, body: int = 0) -> np.ndarray:
+        b = self.bodies[body]
+        out = np.zeros((b.P // 2 + 1, b.N))
+        _check(lib().mfs_op_singular_values(self.h, body, _ptr(out)))
+        return out
+
+
+def build_operator(ctx: Context, bodies: Sequence[BodySpec]) -> Operator:
+    return Operator(ctx, bodies)
+
+
+def factor_modes(op: Operator, rel_cutoff: float = 1e-10):
+    return op.factor_modes(rel_cutoff)
+
+
+def apply_solution_op(op: Operator, x, body: int = 0):
+    """c = A'^+ x per mode; x: cuda complex128 [nrhs][P][M] -> [nrhs][P][N]."""
+    import torch
+    b = op.bodies[body]
+    x = x.contiguous()
+    out = torch.empty((x.shape[0], b.P, b.N), dtype=torch.complex128, device=x.device)
+    _check(lib().mfs_apply_solution_op(op.h, body, x.shape[0], _dev(x), _dev(out), _stream()))
+    return out
+
+
+def rhs_modes(op: Operator, kvecs: np.ndarray, body: int = 0):
+    import torch
+    b = op.bodies[body]
+    kv = np.ascontiguousarray(np.atleast_2d(kvecs), dtype=np.float64)
+    out = torch.empty((kv.shape[0], b.P, b.M), dtype=torch.complex128, device="cuda")
+    _check(lib().mfs_rhs_modes(op.h, body, kv.shape[0], _ptr(kv), _dev(out), _stream()))
+    return out
+
+
+def point_strengths(op: Operator, c, qs: int, body: int = 0):
+    import torch
+    b = op.bodies[body]
+    c = c.contiguous()
+    out = torch.empty((c.shape[0], qs, b.N), dtype=torch.complex128, device=c.device)
+    _check(lib().mfs_point_strengths(op.h, body, c.shape[0], qs, _dev(c), _dev(out), _stream()))
+    return out
+
+
+def neighbour_sum(op: Operator, lattice: Lattice, sigma, ab: np.ndarray, target_set: int,
+                  user: Optional[np.ndarray] = None, want: int = 0, qs: Optional[int] = None,
+                  body: int = 0):
+    """Phased 3x3 near sum of point sources sigma [nrhs][qs][N]; ab [nrhs][2] complex."""
+    import torch
+    b = op.bodies[body]
+    sigma = sigma.contiguous()
+    nrhs = sigma.shape[0]
+    qs = sigma.shape[1] if qs is None else qs
+    abc = np.ascontiguousarray(ab, dtype=np.complex128).reshape(nrhs, 2)
+    ab_arr = (C128 * (2 * nrhs))(*[C128(v.real, v.imag) for v in abc.reshape(-1)])
+    if target_set == TARGETS_SURFACE:
+        nout = b.P * b.M
+    elif target_set == TARGETS_WALLS:
+        nout = 8 * lattice.M1 * lattice.M1
+    else:
+        nout = user.shape[0]
+    uptr = None
+    if user is not None:
+        user = np.ascontiguousarray(user, dtype=np.float64)
+        uptr = _ptr(user)
+    out = torch.empty((nrhs, nout), dtype=torch.complex128, device=sigma.device)
+    _check(lib().mfs_neighbour_sum(op.h, body, C.byref(lattice), nrhs, qs, _dev(sigma), ab_arr,
+                                   target_set, uptr, 0 if user is None else user.shape[0], want,
+                                   _dev(out), _stream()))
+    return out
+
+
+def field_free(op: Operator, c, qs: int, targets: np.ndarray, body: int = 0):
+    import torch
+    c = c.contiguous()
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    out = torch.empty((c.shape[0], t.shape[0]), dtype=torch.complex128, device=c.device)
+    _check(lib().mfs_field_free(op.h, body, c.shape[0], qs, _dev(c), _ptr(t), t.shape[0], _dev(out),
+                                _stream()))
+    return out
+
+
+@dataclass
+class WaveResult:
+    iters: int
+    resid: float
+    m: np.ndarray
+    n: np.ndarray
+    kz: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    field: np.ndarray
+    eps_flux: float
+    q_rank: int
+    nq_cols: int
+
+
+def solve_incident(ctx: Context, op: Operator, lattice: Lattice, waves: Sequence, tol: float = 1e-10,
+                   maxit: int = 200, rel_cutoff: float = 1e-10, targets: Optional[np.ndarray] = None,
+                   q_field: Optional[int] = None, body: int = 0, cap_orders: int = 4096,
+                   timing: bool = False, allow_notconv: bool = False):
+    """Periodic solve of up to 16 incident waves (each (theta, phi))."""
+    import torch
+    b = op.bodies[body]
+    W = len(waves)
+    wv = (Wave * W)(*[Wave(float(t), float(p)) for (t, p) in waves])
+    nt = 0 if targets is None else targets.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.float64)
+    qf = q_field if q_field is not None else 2 * b.P
+    keep = []
+    res = (Result * W)()
+    for w in range(W):
+        arrs = dict(m=np.zeros(cap_orders, np.int32), n=np.zeros(cap_orders, np.int32),
+                    kz=np.zeros(cap_orders, np.complex128), a=np.zeros(cap_orders, np.complex128),
+                    b=np.zeros(cap_orders, np.complex128), field=np.zeros(max(nt, 1), np.complex128))
+        keep.append(arrs)
+        res[w].cap_orders = cap_orders
+        res[w].m = _ptr(arrs["m"], _ip)
+        res[w].n = _ptr(arrs["n"], _ip)
+        for k in ("kz", "a", "b", "field"):
+            setattr(res[w], k, arrs[k].ctypes.data_as(_cp))
+    tm = SolveTiming()
+    torch.cuda.synchronize()
+    st = lib().mfs_solve_incident(ctx.h, op.h, body, C.byref(lattice), W, wv, tol, maxit, rel_cutoff,
+                                  None if tg is None else _ptr(tg), nt, qf, res, C.byref(tm))
+    if not (st == MFS_OK or (allow_notconv and st == MFS_ENOTCONV)):
+        _check(st)
+    out = []
+    for w in range(W):
+        r = res[w]
+        n = r.norders
+        a = keep[w]
+        out.append(WaveResult(r.iters, r.resid, a["m"][:n].copy(), a["n"][:n].copy(), a["kz"][:n].copy(),
+                              a["a"][:n].copy(), a["b"][:n].copy(), a["field"][:nt].copy(), r.eps_flux,
+                              r.q_rank, r.nq_cols))
+    if timing:
+        return out, {k: getattr(tm, k) for k, _ in SolveTiming._fields_}
+    return out
+
+
+def lattice(ex, ey, z0, p, N0, M1) -> Lattice:
+    return Lattice(ex, ey, z0, p, N0, M1)

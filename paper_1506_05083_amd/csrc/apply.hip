@@ -1,0 +1,133 @@
+// Solution-operator apply A^+ x = W (U^H x), W = V S^+ (Sec. 4.2: the
+// pseudoinverse is never formed, the two factors are applied in turn).
+//
+// Mode 0 (one-body operator): the distinct block of mode d serves bins d and
+// P-d (A'_{-n} = A'_n), so every block multiplies 2 nrhs columns at once (one
+// for d = 0 and d = P/2): a small batched GEMM whose cost is reading U and W
+// from HBM once per call.  Mode 1 (periodizing matrix Q): one matrix per
+// right-hand side.
+//
+// stage 1: Y[mat][c][i] = sum_m conj(U[m][i]) x_c[m], 64 rows of Y per
+//          workgroup, 16-row chunks of U and X staged through LDS;
+// stage 2: out_c[jj] = sum_i W[jj][i] Y[c][i], 64 output rows per workgroup,
+//          W streamed with coalesced column reads.
+#include "internal.hpp"
+
+namespace mfs {
+namespace {
+
+constexpr int MAXC = 32;  // columns per call (2 * nrhs for mode 0)
+constexpr int KC = 16;    // reduction chunk
+
+__device__ inline int ncols_of(const PinvJob &j, int mat) {
+  if (j.mode == 1) return 1;
+  const int nsign = (mat == 0 || 2 * mat == j.P) ? 1 : 2;
+  return j.nrhs * nsign;
+}
+
+__device__ inline size_t col_offset(const PinvJob &j, int mat, int c, int len, int ld) {
+  if (j.mode == 1) return (size_t)mat * ld;
+  const int nsign = (mat == 0 || 2 * mat == j.P) ? 1 : 2;
+  const int rhs = c / nsign, s = c % nsign;
+  const int bin = s ? j.P - mat : mat;
+  return ((size_t)rhs * j.P + bin) * len;
+}
+
+__global__ __launch_bounds__(256) void pinv_stage1(PinvJob j) {
+  const int mat = blockIdx.y;
+  const MatDesc d = j.descs[mat];
+  const int r = d.rank[0];
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= r) return;
+  const int nc = ncols_of(j, mat);
+  __shared__ double2 Us[KC][65];
+  __shared__ double2 Xs[KC][MAXC + 1];
+  const int tid = threadIdx.x;
+  const int ii = tid & 63, cg = tid >> 6;
+  double2 acc[MAXC / 4];
+#pragma unroll
+  for (int t = 0; t < MAXC / 4; ++t) acc[t] = cz(0.0, 0.0);
+  for (int m0 = 0; m0 < d.m; m0 += KC) {
+    for (int idx = tid; idx < KC * 64; idx += 256) {
+      const int mm = idx % KC, c = idx / KC;
+      const int m = m0 + mm, i = i0 + c;
+      Us[mm][c] = (m < d.m && i < r) ? d.u[(size_t)i * d.lda + m] : cz(0.0, 0.0);
+    }
+    for (int idx = tid; idx < KC * MAXC; idx += 256) {
+      const int mm = idx % KC, c = idx / KC;
+      const int m = m0 + mm;
+      Xs[mm][c] = (m < d.m && c < nc) ? j.x[col_offset(j, mat, c, d.m, j.ldx) + m] : cz(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int mm = 0; mm < KC; ++mm) {
+      const double2 u = Us[mm][ii];
+#pragma unroll
+      for (int t = 0; t < MAXC / 4; ++t) cfmac(acc[t], u, Xs[mm][cg + 4 * t]);
+    }
+    __syncthreads();
+  }
+  const int i = i0 + ii;
+  if (i < r) {
+    double2 *y = j.ywork + (size_t)mat * j.maxcols * j.maxr;
+#pragma unroll
+    for (int t = 0; t < MAXC / 4; ++t) {
+      const int c = cg + 4 * t;
+      if (c < nc) y[(size_t)c * j.maxr + i] = acc[t];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void pinv_stage2(PinvJob j) {
+  const int mat = blockIdx.y;
+  const MatDesc d = j.descs[mat];
+  const int r = d.rank[0];
+  const int nc = ncols_of(j, mat);
+  const int n = d.n;
+  const int jj0 = blockIdx.x * 64;
+  if (jj0 >= n) return;
+  __shared__ double2 Ys[MAXC][65];
+  const int tid = threadIdx.x;
+  const int jr = tid & 63, cg = tid >> 6;
+  const int row = jj0 + jr;
+  double2 acc[MAXC / 4];
+#pragma unroll
+  for (int t = 0; t < MAXC / 4; ++t) acc[t] = cz(0.0, 0.0);
+  const double2 *y = j.ywork + (size_t)mat * j.maxcols * j.maxr;
+  for (int i0 = 0; i0 < r; i0 += 64) {
+    for (int idx = tid; idx < MAXC * 64; idx += 256) {
+      const int ii = idx % 64, c = idx / 64;
+      const int i = i0 + ii;
+      Ys[c][ii] = (i < r && c < nc) ? y[(size_t)c * j.maxr + i] : cz(0.0, 0.0);
+    }
+    __syncthreads();
+    const int iend = min(64, r - i0);
+    if (row < n) {
+      for (int ii = 0; ii < iend; ++ii) {
+        const double2 w = d.w[(size_t)(i0 + ii) * d.ldg + row];
+#pragma unroll
+        for (int t = 0; t < MAXC / 4; ++t) cfma(acc[t], w, Ys[cg + 4 * t][ii]);
+      }
+    }
+    __syncthreads();
+  }
+  if (row < n) {
+#pragma unroll
+    for (int t = 0; t < MAXC / 4; ++t) {
+      const int c = cg + 4 * t;
+      if (c < nc) j.out[col_offset(j, mat, c, n, j.ldo) + row] = acc[t];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_pinv_apply(const PinvJob &j, hipStream_t s) {
+  MFS_REQUIRE(j.maxcols <= MAXC, "too many right-hand sides in one apply (max 16 per call)");
+  hipLaunchKernelGGL(pinv_stage1, dim3(cdiv(j.maxr, 64), j.nmat), dim3(256), 0, s, j);
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(pinv_stage2, dim3(cdiv(j.maxn, 64), j.nmat), dim3(256), 0, s, j);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace mfs

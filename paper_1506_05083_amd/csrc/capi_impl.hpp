@@ -1,0 +1,56 @@
+// Objects behind the opaque C handles, and helpers shared by capi.cpp and
+// solve.cpp.
+#pragma once
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "geometry.hpp"
+#include "internal.hpp"
+
+struct mfs_ctx {
+  int device = 0;
+};
+
+struct mfs_op {
+  mfs_ctx *ctx = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<mfs::BodyData>> bodies;
+  bool factored = false;
+  double cutoff = 1e-10;
+  mfs::DevBuf flags_ranks;
+  std::vector<mfs::MatDesc> all_descs;
+  mfs::DevBuf all_descs_dev;
+  mfs::DevBuf work;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  double ms_qr = 0.0, ms_svd = 0.0;
+  ~mfs_op() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace mfs {
+
+void upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+void source_points(const BodyData &b, int qs, DevBuf &out, hipStream_t s);
+void build_plan(NsumPlan &plan, const std::vector<NsumGroup> &groups,
+                const std::vector<std::vector<double>> &tg, hipStream_t s);
+void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s);
+void walls_plan(const mfs_lattice &lat, NsumPlan &plan, hipStream_t s);
+void user_plan(const double *user, int nuser, int want, bool nine, NsumPlan &plan, hipStream_t s);
+void walls_weights(const std::vector<std::complex<double>> &al, const std::vector<std::complex<double>> &be,
+                   const NsumPlan &plan, std::vector<double2> &w);
+void image_weights(const std::vector<std::complex<double>> &al, const std::vector<std::complex<double>> &be,
+                   const NsumPlan &plan, std::vector<double2> &w);
+BodyData &body_of(const mfs_op *op, int body);
+double2 *op_workspace(const mfs_op *op, size_t bytes);
+// c = A0^+ x for nrhs right-hand sides in mode layout (chunks of 16)
+void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double2 *x, double2 *out,
+                     hipStream_t s);
+void launch_zero(double2 *p, long n, hipStream_t s);
+void launch_scale(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd,
+                  const double *sdev, hipStream_t s);
+
+}  // namespace mfs

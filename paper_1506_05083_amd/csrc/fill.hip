@@ -1,0 +1,204 @@
+// Modal fill of the one-body blocks (eqs. (ringkernelderiv) and (ptr)) and
+// the incident-wave right-hand side (eqs. (neu), (fhatquad)).
+//
+// Fill.  For a target ring (rho, z) with normal (nrho, nz) and a source ring
+// (rho', z'), the integrand of eq. (ringkernelderiv) at angle phi is
+//   g(phi) = dG/dn_x = G (ik - 1/R) (d.n)/R,   G = e^{ikR}/(4 pi R),
+//   R^2 = rho^2 + rho'^2 - 2 rho rho' cos phi + (z - z')^2,
+//   d.n = (rho - rho' cos phi) nrho + (z - z') nz,
+// so both R^2 and d.n are affine in cos phi.  g is even in phi, so the
+// q-node trapezoid rule of eq. (ptr) for mode n folds onto l = 0..q/2:
+//   A'_n = (1/q) [g_0 + (-1)^n g_{q/2} + 2 sum_{0<l<q/2} g_l cos(2 pi n l / q)],
+// and A'_{-n} = A'_n: only n = 0..P/2 are computed.
+//
+// Layout: one workgroup per tile of 64 (m, j) pairs (m fastest, so stores
+// of A[n][j][m] are coalesced).  The q/2+1 nodes are processed in chunks of
+// 32: the 4 waves evaluate g for the tile into LDS, then each thread folds
+// the chunk into its P/2+1 (strided by 4) mode accumulators using the
+// cosine weights staged from a per-operator table.  FP64 VALU bound: one
+// rsqrt and one sincos per kernel sample.
+#include "internal.hpp"
+
+namespace mfs {
+namespace {
+
+constexpr int TP = 64;    // (m, j) pairs per workgroup
+constexpr int LC = 32;    // trapezoid nodes per LDS chunk
+constexpr int MAXS = 26;  // accumulators per thread: P/2 + 1 <= 4 * MAXS
+
+// tab[l][0..nd-1] = c_l cos(2 pi n l / q) / q with c_0 = c_{q/2} = 1, else 2;
+// tab[l][nd] = cos(2 pi l / q).  Argument reduction is exact (integer n l mod q).
+__global__ void fill_table_kernel(int q, int nd, double *tab) {
+  const int L = q / 2 + 1;
+  const int ld = nd + 1;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < L * ld;
+       idx += gridDim.x * blockDim.x) {
+    int l = idx / ld, n = idx % ld;
+    double v;
+    if (n == nd) {
+      v = cospi(2.0 * l / q);
+    } else {
+      long r = ((long)n * l) % q;
+      double cl = (l == 0 || 2 * l == q) ? 1.0 : 2.0;
+      v = cl * cospi(2.0 * (double)r / q) / q;
+    }
+    tab[idx] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(int M, int N, int q, int nd, int ldA, double k,
+                                                   const double *__restrict__ rho,
+                                                   const double *__restrict__ zc,
+                                                   const double *__restrict__ nrho,
+                                                   const double *__restrict__ nzc,
+                                                   const double *__restrict__ srho,
+                                                   const double *__restrict__ szc,
+                                                   const double *__restrict__ tab,
+                                                   double2 *__restrict__ A) {
+  __shared__ double2 gs[LC][TP];
+  __shared__ double wt[LC * 105];
+  const int tid = threadIdx.x;
+  const int pl = tid & 63;
+  const int grp = tid >> 6;   // wave index: uniform within a wave
+  const long pair = (long)blockIdx.x * TP + pl;
+  const bool valid = pair < (long)M * N;
+  const int m = valid ? (int)(pair % M) : 0;
+  const int j = valid ? (int)(pair / M) : 0;
+  const double r = rho[m], rs = srho[j];
+  const double dz = zc[m] - szc[j];
+  const double Ac = r * r + rs * rs + dz * dz;
+  const double Bc = 2.0 * r * rs;
+  const double Cc = r * nrho[m] + dz * nzc[m];
+  const double Dc = rs * nrho[m];
+  const double inv4pi = 0.25 / kPi;
+  const int L = q / 2 + 1;
+  const int ld = nd + 1;
+
+  double2 acc[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) acc[s] = cz(0.0, 0.0);
+
+  for (int l0 = 0; l0 < L; l0 += LC) {
+    const int lc = min(LC, L - l0);
+    __syncthreads();
+    for (int idx = tid; idx < lc * ld; idx += 256) wt[idx] = tab[(size_t)l0 * ld + idx];
+    __syncthreads();
+    for (int ll = grp; ll < LC; ll += 4) {
+      double2 g = cz(0.0, 0.0);
+      if (ll < lc && valid) {
+        const double c = wt[ll * ld + nd];
+        const double R2 = fma(-Bc, c, Ac);
+        const double dn = fma(-Dc, c, Cc);
+        const double invR = rsqrt(R2);
+        const double R = R2 * invR;
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+        const double t = dn * invR * invR * inv4pi;
+        // (cs + i sn) (i k - invR) t
+        g = cz(t * fma(-cs, invR, -sn * k), t * fma(cs, k, -sn * invR));
+      }
+      gs[ll][pl] = g;
+    }
+    __syncthreads();
+    for (int ll = 0; ll < lc; ++ll) {
+      const double2 g = gs[ll][pl];
+      const double *w = wt + ll * ld;
+#pragma unroll
+      for (int s = 0; s < MAXS; ++s) {
+        const int n = grp + 4 * s;
+        if (n < nd) {
+          const double c = w[n];
+          acc[s].x = fma(c, g.x, acc[s].x);
+          acc[s].y = fma(c, g.y, acc[s].y);
+        }
+      }
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    const int n = grp + 4 * s;
+    if (n < nd) A[((size_t)n * N + j) * ldA + m] = acc[s];
+  }
+}
+
+// f = -du^i/dn = -i (k.n) e^{i k.x} on the P x M surface nodes, folded into
+// f_hat_b = (1/P) sum_l f_l e^{-2 pi i b l / P}.  One workgroup per 8 rings
+// of one wave; twiddles from an exact table in LDS.
+constexpr int RM = 8;
+__global__ __launch_bounds__(256) void rhs_kernel(int M, int P, const double *__restrict__ rho,
+                                                  const double *__restrict__ zc,
+                                                  const double *__restrict__ nrho,
+                                                  const double *__restrict__ nzc,
+                                                  const double *__restrict__ kvec,
+                                                  double2 *__restrict__ out) {
+  extern __shared__ double2 sh[];
+  double2 *tw = sh;          // [P]
+  double2 *f = sh + P;       // [RM][P]
+  const int w = blockIdx.y;
+  const int m0 = blockIdx.x * RM;
+  const double kx = kvec[3 * w], ky = kvec[3 * w + 1], kzv = kvec[3 * w + 2];
+  for (int l = threadIdx.x; l < P; l += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * l / P, &s, &c);
+    tw[l] = cz(c, s);
+  }
+  for (int idx = threadIdx.x; idx < RM * P; idx += blockDim.x) {
+    const int ring = idx / P, l = idx % P;
+    const int m = m0 + ring;
+    double2 v = cz(0.0, 0.0);
+    if (m < M) {
+      double sp, cp;
+      sincospi(2.0 * l / P, &sp, &cp);
+      const double x = rho[m] * cp, y = rho[m] * sp;
+      const double kn = kx * nrho[m] * cp + ky * nrho[m] * sp + kzv * nzc[m];
+      double s, c;
+      sincos(kx * x + ky * y + kzv * zc[m], &s, &c);
+      // -i kn (c + i s) = kn s - i kn c
+      v = cz(kn * s, -kn * c);
+    }
+    f[idx] = v;
+  }
+  __syncthreads();
+  const double invP = 1.0 / P;
+  for (int idx = threadIdx.x; idx < RM * P; idx += blockDim.x) {
+    const int ring = idx % RM, b = idx / RM;
+    const int m = m0 + ring;
+    if (m >= M) continue;
+    double2 acc = cz(0.0, 0.0);
+    int ph = 0;
+    for (int l = 0; l < P; ++l) {
+      cfma(acc, f[ring * P + l], tw[ph]);
+      ph += b;
+      if (ph >= P) ph -= P;
+    }
+    out[((size_t)w * P + b) * M + m] = cscale(acc, invP);
+  }
+}
+
+}  // namespace
+
+void launch_fill(BodyData &b, hipStream_t s) {
+  MFS_REQUIRE(b.nd <= 4 * MAXS, "P/2+1 exceeds the fill kernel's mode capacity (P <= 206)");
+  const int L = b.q / 2 + 1;
+  DevBuf tab((size_t)L * (b.nd + 1) * sizeof(double));
+  hipLaunchKernelGGL(fill_table_kernel, dim3(cdiv(L * (b.nd + 1), 256)), dim3(256), 0, s, b.q,
+                     b.nd, tab.as<double>());
+  HIP_CHECK(hipGetLastError());
+  const long npair = (long)b.M * b.N;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdiv((int)npair, TP)), dim3(256), 0, s, b.M, b.N,
+                     b.q, b.nd, b.ldA, b.k, b.rho, b.z, b.nrho, b.nz, b.srho, b.sz,
+                     tab.as<double>(), b.blocks.as<double2>());
+  HIP_CHECK(hipGetLastError());
+  // the table is freed on return; make sure the kernels are done with it
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out, hipStream_t s) {
+  const size_t sh = (size_t)(b.P + RM * b.P) * sizeof(double2);
+  hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(b.M, RM), nw), dim3(256), sh, s, b.M, b.P, b.rho, b.z,
+                     b.nrho, b.nz, kvec_dev, out);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace mfs

@@ -1,0 +1,149 @@
+// Internal data structures and kernel launchers of libmfs (not part of the
+// C ABI).  All device matrices are column-major complex double (double2).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace mfs {
+
+// ------------------------------------------------------------ device buffer
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  void alloc(size_t n);
+  void release();
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ------------------------------------------------------ batched matrices
+// A matrix taking part in a batched QR / Jacobi SVD / pseudoinverse apply.
+struct MatDesc {
+  double2 *a;     // m x n, lda (QR in place: R above, Householder vectors below)
+  int m, n, lda;
+  double2 *tau;   // [n] Householder scalars
+  double2 *T;     // [npanels][nb*nb] compact-WY triangular factors
+  double2 *g;     // n x n, ldg: Jacobi work matrix (R, rotated to U S)
+  int ldg;
+  double2 *v;     // n x n, ldg: Jacobi right vectors
+  double2 *u;     // m x n, lda: left singular vectors (kept columns)
+  double2 *w;     // n x n, ldg: V S^+ (kept columns)
+  double *sv;     // [n] singular values, descending
+  int *perm;      // [n] work
+  int *rank;      // [1] kept rank
+  int *flag;      // [1] Jacobi sweep activity flag
+};
+
+constexpr int kQRNB = 32;   // Householder panel width
+
+// One body of an operator: geometry and its P/2+1 distinct mode blocks.
+struct BodyData {
+  int M, N, P, q, nd, ldA;
+  double k;
+  DevBuf geom;        // rho z nrho nz [M] each, srho sz [N] each
+  double *rho, *z, *nrho, *nz, *srho, *sz;
+  std::vector<double> h_rho, h_z, h_nrho, h_nz, h_srho, h_sz;
+  DevBuf blocks;      // [nd][N][ldA]
+  DevBuf fac;         // tau, T, g, v, u, w, sv, perm, rank, flag for all nd blocks
+  DevBuf descs;       // MatDesc[nd] on device
+  std::vector<MatDesc> h_descs;
+  std::vector<int> rank;
+  DevBuf src_P;       // point sources at q = P angles, SoA x y z [P*N] each
+};
+
+// ---------------------------------------------------------- launchers
+void launch_fill(BodyData &b, hipStream_t s);
+void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out, hipStream_t s);
+// out[r][b][x] = scale * sum_l in[r][l][x] e^{sgn 2 pi i b l / P}, r < nr, x < X
+void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, double scale,
+                hipStream_t s);
+// sigma[r][l][j] = (1/qs) sum_n c[r][bin(n)][j] e^{+i n 2 pi l / qs}
+void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, double2 *sigma,
+                            hipStream_t s);
+
+// batched QR of nmat matrices described by descs (device) / h (host copy)
+void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s);
+// Jacobi SVD of the R factors, truncation, explicit U = Q [U_R; 0] and W = V S^+
+void svd_truncate(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff,
+                  hipStream_t s, std::vector<int> &ranks);
+
+// y = A^+ x with the kept factors: job layout
+//   mode 0 (one-body blocks): mat d = distinct mode, columns = bins d and P-d
+//           of nrhs right-hand sides, x: [nrhs][P][M], out: [nrhs][P][N]
+//   mode 1 (one matrix per rhs): mat r, one column, x: [nrhs][ldx], out [nrhs][ldo]
+struct PinvJob {
+  int mode, nmat, P, nrhs, ldx, ldo, maxcols, maxr, maxm, maxn;
+  const MatDesc *descs;
+  const double2 *x;
+  double2 *out;
+  double2 *ywork;   // [nmat][maxcols][maxr]
+};
+void launch_pinv_apply(const PinvJob &j, hipStream_t s);
+
+// ------------------------------------------------------- neighbour sums
+// Targets are grouped; every group shares an image list and per-rhs weights.
+struct NsumGroup {
+  int t0, nt;         // target range [t0, t0+nt) (nt padded to 64 in the launch)
+  int deriv;          // 0: value, 1: derivative along the target direction
+  int nimg;
+  int ia[9], ib[9];   // image shifts (a, b)
+};
+struct NsumPlan {
+  int ntarget_pad;    // targets padded per group to multiples of 64
+  std::vector<NsumGroup> groups;
+  DevBuf tgt;         // SoA x y z dx dy dz [ntarget_pad] each
+  DevBuf grp;         // NsumGroup[] on device
+  DevBuf tile_group;  // int [ntarget_pad/64]
+};
+// out[r][t] = sum_img w[g][img][r] sum_s K(x_t - a ex - b ey, y_s) sigma[r][s]
+// w: device [ngroups][9][nrhs] complex; src: SoA x y z [S]; sigma [nrhs][S]
+void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
+                 const double *src, int S, const double2 *sigma, const double2 *w,
+                 double2 *out, double2 *partial, hipStream_t s);
+int nsum_splits(const NsumPlan &plan, int S);
+
+// ----------------------------------------------------------- harmonics
+// Fill rows of Q (S block and -W blocks) for one wave.
+struct QFillArgs {
+  double k, ex, ey, z0;
+  int p, M1, nrb;
+  double2 alpha, beta;
+  const double *wall;     // SoA x y z of the 6 walls: R L F B T D, each M1^2
+  const double *kx, *ky;  // [nrb]
+  const double2 *kz;      // [nrb]
+  double2 *Q;             // column-major [8 M1^2][ldq]
+  int ldq;
+};
+void launch_qfill(const QFillArgs &a, hipStream_t s);
+// Btilde: values dH_lm/dn at the surface rings (phi = 0): out [NH][M]
+void launch_bfill(int M, int p, double k, const double *rho, const double *z, const double *nrho,
+                  const double *nz, double2 *out, hipStream_t s);
+// out[r][bin][m] -= sum_{(l,mm): mm = bin mod P} B[(l,mm)][m] d[r][(l,mm)] ; d stride ldd
+void launch_bapply(int nrhs, int P, int M, int p, const double2 *B, const double2 *d, int ldd,
+                   double2 *out, hipStream_t s);
+// u[r][t] += sum_lm H_lm(x_t) d[r][lm]
+void launch_harm_field(int nrhs, int nt, const double *xyz, int p, double k, const double2 *d,
+                       int ldd, double2 *out, hipStream_t s);
+
+// ------------------------------------------------------------- GMRES
+void launch_dots(int nw, int nvec, int n, const double2 *V, size_t ldv_w, size_t ldv_i,
+                 const double2 *z, double2 *h, hipStream_t s);
+void launch_update(int nw, int nvec, int n, const double2 *V, size_t ldv_w, size_t ldv_i,
+                   double2 *z, const double2 *h, int hstride, hipStream_t s);
+void launch_axpby_op(int nw, int n, const double2 *x, const double2 *g, const double2 *bd,
+                     double2 *out, hipStream_t s);
+void launch_combine_walls(int nw, int M1sq, const double2 *in, double2 *out, hipStream_t s);
+
+}  // namespace mfs

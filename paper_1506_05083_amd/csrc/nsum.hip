@@ -1,0 +1,191 @@
+// Direct phased near-neighbour Helmholtz sums (eqs. (A) and (Phinear)): the
+// A_else action on the surface nodes, the C block on the wall nodes, and
+// field evaluation at arbitrary points.
+//
+//   out[r][t] = sum_img w[g][img][r] sum_s K(x_t - a e_x - b e_y, y_s) sigma[r][s]
+//
+// with K = G (value) or the derivative of G along the target's direction.
+// Targets are grouped (a group shares one image list, one kind and per-rhs
+// weights) and every 64-target tile belongs to one group.  A workgroup takes
+// one tile (lane = target) and one slice of the sources; its four waves
+// split the slice, staged through LDS in chunks with the strengths of all
+// right-hand sides, so the geometry part of each pair (one rsqrt, one
+// sincos) is shared by every right-hand side.  Slices are summed by a second
+// kernel.  FP64 VALU bound; the only HBM traffic is the strengths and the
+// output.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace mfs {
+namespace {
+
+constexpr int SC = 128;     // sources per LDS chunk (32 per wave)
+constexpr int MAXR = 16;    // right-hand sides per launch
+
+template <int NR>
+__global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tgt, int ntp,
+                                                   const NsumGroup *__restrict__ groups,
+                                                   const int *__restrict__ tile_group, int nrhs,
+                                                   double k, double ex, double ey,
+                                                   const double *__restrict__ src, int S,
+                                                   const double2 *__restrict__ sigma,
+                                                   const double2 *__restrict__ wts, int nsplit,
+                                                   double2 *__restrict__ out) {
+  extern __shared__ double shm[];
+  double *sx = shm, *sy = shm + SC, *szs = shm + 2 * SC;
+  double2 *ssig = reinterpret_cast<double2 *>(shm + 3 * SC);   // [NR][SC]
+  const int tile = blockIdx.x;
+  const int split = blockIdx.y;
+  const int gi = tile_group[tile];
+  const NsumGroup g = groups[gi];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = tile * 64 + lane;
+  const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
+  const double dxt = tgt[3 * ntp + t], dyt = tgt[4 * ntp + t], dzt = tgt[5 * ntp + t];
+  const int per = (S + nsplit - 1) / nsplit;
+  const int s_begin = split * per;
+  const int s_end = min(S, s_begin + per);
+  const double inv4pi = 0.25 / kPi;
+
+  double2 tot[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
+
+  for (int im = 0; im < g.nimg; ++im) {
+    const double xs = xt - g.ia[im] * ex, ys = yt - g.ib[im] * ey;
+    double2 acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
+    for (int c0 = s_begin; c0 < s_end; c0 += SC) {
+      const int nc = min(SC, s_end - c0);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < SC; idx += 256) {
+        const int s = c0 + idx;
+        const bool ok = idx < nc;
+        sx[idx] = ok ? src[s] : 0.0;
+        sy[idx] = ok ? src[S + s] : 0.0;
+        szs[idx] = ok ? src[2 * S + s] : 1e3;   // far dummy source, zero strength
+      }
+      for (int idx = threadIdx.x; idx < NR * SC; idx += 256) {
+        const int r = idx / SC, ss = idx % SC;
+        ssig[idx] = (r < nrhs && ss < nc) ? sigma[(size_t)r * S + c0 + ss] : cz(0.0, 0.0);
+      }
+      __syncthreads();
+      const int sbeg = wv * (SC / 4);
+      for (int ss = sbeg; ss < sbeg + SC / 4; ++ss) {
+        const double ddx = xs - sx[ss], ddy = ys - sy[ss], ddz = zt - szs[ss];
+        const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
+        const double invR = rsqrt(R2);
+        const double R = R2 * invR;
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+        double2 K;
+        if (g.deriv) {
+          const double dn = fma(dxt, ddx, fma(dyt, ddy, dzt * ddz));
+          const double tt = dn * invR * invR * inv4pi;
+          K = cz(tt * fma(-cs, invR, -sn * k), tt * fma(cs, k, -sn * invR));
+        } else {
+          const double tt = invR * inv4pi;
+          K = cz(cs * tt, sn * tt);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma(acc[r], K, ssig[r * SC + ss]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
+  }
+  // reduce the four waves
+  __syncthreads();
+  double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot[r];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+    const int r = idx / 64, l = idx % 64;
+    if (r >= nrhs) continue;
+    double2 v = red[(0 * NR + r) * 64 + l];
+    for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
+    out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = v;
+  }
+}
+
+__global__ void nsum_reduce(int nsplit, int nrhs, int ntp, const double2 *__restrict__ part,
+                            double2 *__restrict__ out) {
+  const long n = (long)nrhs * ntp;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double2 v = part[i];
+    for (int s = 1; s < nsplit; ++s) v = cadd(v, part[(size_t)s * n + i]);
+    out[i] = v;
+  }
+}
+
+// Wall rows of C from the 12 padded target groups (R L Rx Lx F B Fy By T Tz D Dz):
+// [R+L, Rx+Lx, F+B, Fy+By, T, Tz, D, Dz], each M1^2 rows.
+__global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict__ in,
+                                     double2 *__restrict__ out) {
+  const int pad = (M1sq + 63) / 64 * 64;
+  const int ntp = 12 * pad;
+  const long n = (long)nw * 8 * M1sq;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int w = (int)(i / (8 * M1sq));
+    const int row = (int)(i % (8 * M1sq));
+    const int blk = row / M1sq, t = row % M1sq;
+    const double2 *src = in + (size_t)w * ntp;
+    double2 v;
+    if (blk < 4) v = cadd(src[(2 * blk) * pad + t], src[(2 * blk + 1) * pad + t]);
+    else v = src[(blk + 4) * pad + t];
+    out[i] = v;
+  }
+}
+
+template <int NR>
+void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
+                   const double *src, int S, const double2 *sigma, const double2 *w,
+                   int nsplit, double2 *dst, hipStream_t s) {
+  const size_t sh = std::max((size_t)(3 * SC) * sizeof(double) + (size_t)NR * SC * sizeof(double2),
+                             (size_t)4 * NR * 64 * sizeof(double2));
+  hipLaunchKernelGGL(nsum_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                     plan.tgt.as<double>(), plan.ntarget_pad, plan.grp.as<NsumGroup>(),
+                     plan.tile_group.as<int>(), nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace
+
+int nsum_splits(const NsumPlan &plan, int S) {
+  const int tiles = plan.ntarget_pad / 64;
+  int ns = std::max(1, cdiv(2048, tiles));
+  ns = std::min(ns, std::max(1, S / 256));
+  return ns;
+}
+
+void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey, const double *src,
+                 int S, const double2 *sigma, const double2 *w, double2 *out, double2 *partial,
+                 hipStream_t s) {
+  MFS_REQUIRE(nrhs >= 1 && nrhs <= MAXR, "neighbour sum: 1 <= nrhs <= 16");
+  const int nsplit = nsum_splits(plan, S);
+  double2 *dst = (nsplit == 1) ? out : partial;
+  if (nrhs <= 1) launch_nsum_t<1>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  else if (nrhs <= 2) launch_nsum_t<2>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  else if (nrhs <= 4) launch_nsum_t<4>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  else if (nrhs <= 8) launch_nsum_t<8>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  else launch_nsum_t<16>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  if (nsplit > 1) {
+    const long n = (long)nrhs * plan.ntarget_pad;
+    hipLaunchKernelGGL(nsum_reduce, dim3((unsigned)std::min<long>(2048, (n + 255) / 256)), dim3(256),
+                       0, s, nsplit, nrhs, plan.ntarget_pad, partial, out);
+    HIP_CHECK(hipGetLastError());
+  }
+}
+
+void launch_combine_walls(int nw, int M1sq, const double2 *in, double2 *out, hipStream_t s) {
+  const long n = (long)nw * 8 * M1sq;
+  hipLaunchKernelGGL(combine_walls_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)),
+                     dim3(256), 0, s, nw, M1sq, in, out);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace mfs

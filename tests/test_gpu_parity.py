@@ -1,0 +1,223 @@
+"""GPU parity: every step of the libmfs path, called through the C ABI,
+against the CPU oracle on the same seeded inputs.
+
+Tolerances (relative to the largest entry / the norm of the reference):
+  fill, right-hand sides, point strengths, neighbour sums: 1e-12 -- these are
+  direct sums of O(q) terms in FP64, different summation order only;
+  singular values: 1e-13 * s_max absolute (backward-stable SVDs);
+  fields and Bragg amplitudes: 1e-10 (the target accuracy of the method;
+  the coefficient vectors themselves are not unique and are never compared).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry, mie, onebody, periodic
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mfs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1506_05083_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mfs):
+    return mfs.create(0)
+
+
+def make_op(mfs, ctx, body: W.Body):
+    sh = body.shape
+    g = mfs.polar_geometry(sh.a, sh.eps, sh.j, body.M, body.N, body.tau, body.colloc)
+    return mfs.build_operator(ctx, [mfs.BodySpec(body.M, body.N, body.P, body.q, body.k, g)])
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+CASES = {"tiny": W.tiny_free_space, "sphere": W.sphere_free_space, "small_periodic": W.small_periodic}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fill_parity(mfs, ctx, name):
+    pr = CASES[name]()
+    b = pr.body
+    log(f"[fill] {name} M={b.M} N={b.N} P={b.P} q={b.q}")
+    op = make_op(mfs, ctx, b)
+    Ag = op.blocks().cpu().numpy().transpose(0, 2, 1)        # [nd][M][N]
+    g = geometry.build_geometry(b)
+    Ao = onebody.modal_blocks(b, g)[: b.P // 2 + 1]
+    err = rel(Ag, Ao)
+    log(f"[fill] {name} max rel err {err:.2e}")
+    assert err < 1e-12
+
+
+def test_fill_parity_periodic_k10_sampled(mfs, ctx):
+    """Full size of the k = 10 periodic body (240 x 200, 33 blocks, q = 400),
+    sampled rows against the oracle's per-row fill."""
+    b = W.periodic_k10(1).body
+    log("[fill] periodic_k10")
+    op = make_op(mfs, ctx, b)
+    Ag = op.blocks().cpu().numpy().transpose(0, 2, 1)
+    g = geometry.build_geometry(b)
+    rows = np.array([0, 1, 57, 119, 120, 201, 238, 239])
+    s = onebody.ring_samples_dGdn(b, g, b.q, rows)
+    Ao = (np.fft.fft(s, axis=2) / b.q)[:, :, : b.P // 2 + 1]      # [rows][N][nd]
+    err = rel(Ag[:, rows, :], np.transpose(Ao, (2, 0, 1)))
+    log(f"[fill] periodic_k10 sampled max rel err {err:.2e}")
+    assert err < 1e-12
+
+
+def test_rhs_and_strengths_parity(mfs, ctx):
+    import torch
+    pr = W.small_periodic()
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    g = geometry.build_geometry(b)
+    kv = np.stack([W.wave_vector(b.k, w) for w in pr.waves])
+    fg = mfs.rhs_modes(op, kv).cpu().numpy()
+    fo = np.stack([onebody.rhs_modes(b, g, w) for w in pr.waves])
+    log(f"[rhs] max rel err {rel(fg, fo):.2e}")
+    assert rel(fg, fo) < 1e-12
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal((2, b.P, b.N)) + 1j * rng.standard_normal((2, b.P, b.N))
+    for qs in (b.P, 3 * b.P):
+        sg = mfs.point_strengths(op, torch.from_numpy(c).cuda(), qs).cpu().numpy()
+        so = np.stack([onebody.point_strengths(c[i], qs) for i in range(2)])
+        log(f"[strengths] qs={qs} max rel err {rel(sg, so):.2e}")
+        assert rel(sg, so) < 1e-12
+
+
+def test_factor_singular_values_and_ranks(mfs, ctx):
+    pr = W.small_periodic()
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    ranks = op.factor_modes(1e-10)
+    sv = op.singular_values()
+    g = geometry.build_geometry(b)
+    A = onebody.modal_blocks(b, g)
+    for n in range(b.P // 2 + 1):
+        s = np.linalg.svd(A[n], compute_uv=False)
+        err = np.max(np.abs(sv[n] - s)) / s[0]
+        assert err < 1e-13, (n, err)
+        assert abs(int(ranks[n]) - int(np.sum(s > 1e-10 * s[0]))) <= 1, n
+    log(f"[factor] ranks {list(ranks)}")
+
+
+@pytest.mark.parametrize("name", ["tiny", "sphere"])
+def test_free_space_fields(mfs, ctx, name):
+    """Whole one-body path on the GPU (fill, QR + Jacobi truncation, RHS,
+    apply, point-source field) against the oracle's field; the sphere also
+    against the Mie series."""
+    pr = CASES[name]()
+    b = pr.body
+    log(f"[free] {name}")
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    kv = np.stack([W.wave_vector(b.k, w) for w in pr.waves])
+    fh = mfs.rhs_modes(op, kv)
+    c = mfs.apply_solution_op(op, fh)
+    u = mfs.field_free(op, c, pr.q_field, pr.targets).cpu().numpy()[0]
+    g = geometry.build_geometry(b)
+    A = onebody.modal_blocks(b, g)
+    co = onebody.solve_modes(A, onebody.rhs_modes(b, g, pr.waves[0]))
+    uo = onebody.field(b, g, co, pr.targets, pr.q_field)
+    err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    log(f"[free] {name} field rel err vs oracle {err:.2e}")
+    assert err < 1e-10
+    if name == "sphere":
+        um = mie.sound_hard_sphere(b.k, b.shape.a, kv[0], pr.targets)
+        em = np.linalg.norm(u - um) / np.linalg.norm(um)
+        log(f"[free] sphere rel err vs Mie {em:.2e}")
+        assert em < 1e-9
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    pr = W.small_periodic(nwaves=2)
+    b, lat = pr.body, pr.lattice
+    g = geometry.build_geometry(b)
+    A = onebody.modal_blocks(b, g)
+    ps = periodic.PeriodicSolver(b, lat, g, A)
+    out = []
+    for w in pr.waves:
+        ps.set_wave(w)
+        fh = onebody.rhs_modes(b, g, w)
+        r = ps.solve(fh, tol=1e-12)
+        u, _ = ps.field_and_grad(r["c"], r["d"], pr.targets, pr.q_field, want_grad=False)
+        out.append(dict(alpha=ps.alpha, beta=ps.beta, Kelse=ps.Kelse.copy(), Cpt=ps.Cpt.copy(),
+                        res=r, u=u, m=ps.orders.m.copy(), n=ps.orders.n.copy(),
+                        flux=ps.eps_flux(r["a"], r["b"])))
+    return pr, g, out
+
+
+def _lat(mfs, lat):
+    return mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+
+
+def test_neighbour_sum_parity(mfs, ctx, small_oracle):
+    import torch
+    pr, g, out = small_oracle
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    rng = np.random.default_rng(4)
+    sig = rng.standard_normal((2, b.P, b.N)) + 1j * rng.standard_normal((2, b.P, b.N))
+    ab = np.array([[o["alpha"], o["beta"]] for o in out])
+    L = _lat(mfs, pr.lattice)
+    st = torch.from_numpy(sig).cuda()
+    gs = mfs.neighbour_sum(op, L, st, ab, mfs.TARGETS_SURFACE).cpu().numpy()
+    gw = mfs.neighbour_sum(op, L, st, ab, mfs.TARGETS_WALLS).cpu().numpy()
+    for i in range(2):
+        es = rel(gs[i], out[i]["Kelse"] @ sig[i].reshape(-1))
+        ew = rel(gw[i], out[i]["Cpt"] @ sig[i].reshape(-1))
+        log(f"[nsum] wave {i} surface {es:.2e} walls {ew:.2e}")
+        assert es < 1e-12 and ew < 1e-12
+    # user targets, value and derivative, all 9 copies
+    X = pr.targets[:10]
+    d = rng.standard_normal((10, 3))
+    user = np.concatenate([X, d], axis=1)
+    Y = geometry.source_ring_points(g, b.P).reshape(-1, 3)
+    for want in (0, 1):
+        gu = mfs.neighbour_sum(op, L, st, ab, mfs.TARGETS_USER, user=user, want=want).cpu().numpy()
+        imgs = periodic.image_list(pr.lattice, out[0]["alpha"], out[0]["beta"], periodic.NEAR9)
+        Vm, Gm = periodic.near_matrices(b.k, Y, X, imgs)
+        ref = (Vm @ sig[0].reshape(-1)) if want == 0 else np.einsum("tsc,tc,s->t", Gm, d, sig[0].reshape(-1))
+        log(f"[nsum] user want={want} {rel(gu[0], ref):.2e}")
+        assert rel(gu[0], ref) < 1e-12
+
+
+def test_periodic_solve_parity_small(mfs, ctx, small_oracle):
+    """Whole periodic path on the GPU (Q fill and factorisation, batched
+    GMRES with the neighbour sums, recovery) for two incidences against the
+    oracle: Bragg amplitudes and cell fields to 1e-10."""
+    pr, g, out = small_oracle
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    L = _lat(mfs, pr.lattice)
+    res = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=1e-12, maxit=100,
+                             targets=pr.targets, q_field=pr.q_field)
+    for i, r in enumerate(res):
+        o = out[i]
+        assert np.array_equal(r.m, o["m"]) and np.array_equal(r.n, o["n"])
+        ea = np.max(np.abs(r.a - o["res"]["a"])) / np.max(np.abs(o["res"]["a"]))
+        eb = np.max(np.abs(r.b - o["res"]["b"])) / np.max(np.abs(o["res"]["b"]))
+        eu = np.linalg.norm(r.field - o["u"]) / np.linalg.norm(o["u"])
+        log(f"[periodic] wave {i} iters gpu {r.iters} oracle {o['res']['iters']} a {ea:.2e} b {eb:.2e} "
+            f"u {eu:.2e} flux gpu {r.eps_flux:.2e} oracle {o['flux']:.2e}")
+        assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+        assert r.eps_flux < 1e-6
