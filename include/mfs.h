@@ -146,6 +146,11 @@ mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *st
  * the kept rank of each distinct block, [sum over bodies of P/2+1]. */
 mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks);
 
+/* Stage times of the operator, milliseconds, measured with HIP events on the
+ * operator's stream: ms[0] fill (mfs_build_operator), ms[1] QR and ms[2]
+ * Jacobi truncation + explicit U (mfs_factor_modes; zero before it runs). */
+mfs_status mfs_op_timing(const mfs_op *op, double *ms);
+
 /* Singular values (descending) of the distinct blocks of one body, host
  * out [P/2+1][N].  ESTATE before mfs_factor_modes. */
 mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out);

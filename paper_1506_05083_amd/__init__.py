@@ -78,6 +78,7 @@ _SIGS = {
     "mfs_op_blocks": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mfs_factor_modes": (C.c_int, [C.c_void_p, C.c_double, _ip]),
     "mfs_op_singular_values": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "mfs_op_timing": (C.c_int, [C.c_void_p, _dp]),
     "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "mfs_rhs_modes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_void_p, C.c_void_p]),
@@ -213,6 +214,12 @@ class Operator:
         _check(lib().mfs_factor_modes(self.h, rel_cutoff, _ptr(r, _ip)))
         self.ranks = r
         return r
+
+    def timing(self) -> dict:
+        """Fill, QR and truncation stage times (ms, HIP events)."""
+        ms = np.zeros(3)
+        _check(lib().mfs_op_timing(self.h, _ptr(ms)))
+        return dict(fill=ms[0], qr=ms[1], svd=ms[2])
 
     def singular_values(self, body: int = 0) -> np.ndarray:
         b = self.bodies[body]

@@ -364,7 +364,18 @@ mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbod
     upload(b->srho, src.srho, src.N * sizeof(double), op->stream);
     upload(b->sz, src.sz, src.N * sizeof(double), op->stream);
     b->blocks.alloc((size_t)b->nd * src.N * b->ldA * sizeof(double2));
+    hipEvent_t f0, f1;
+    HIP_CHECK(hipEventCreate(&f0));
+    HIP_CHECK(hipEventCreate(&f1));
+    HIP_CHECK(hipEventRecord(f0, op->stream));
     launch_fill(*b, op->stream);
+    HIP_CHECK(hipEventRecord(f1, op->stream));
+    HIP_CHECK(hipEventSynchronize(f1));
+    float fms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&fms, f0, f1));
+    op->ms_fill += fms;
+    (void)hipEventDestroy(f0);
+    (void)hipEventDestroy(f1);
     source_points(*b, b->P, b->src_P, op->stream);
     op->bodies.push_back(std::move(b));
   }
@@ -417,6 +428,15 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   if (ranks) std::copy(rk.begin(), rk.end(), ranks);
   op->factored = true;
   op->cutoff = rel_cutoff;
+  MFS_API_END
+}
+
+mfs_status mfs_op_timing(const mfs_op *op, double *ms) {
+  MFS_API_BEGIN
+  MFS_REQUIRE(op != nullptr && ms != nullptr, "null pointer");
+  ms[0] = op->ms_fill;
+  ms[1] = op->ms_qr;
+  ms[2] = op->ms_svd;
   MFS_API_END
 }
 

@@ -24,7 +24,7 @@ struct mfs_op {
   mfs::DevBuf all_descs_dev;
   mfs::DevBuf work;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  double ms_qr = 0.0, ms_svd = 0.0;
+  double ms_fill = 0.0, ms_qr = 0.0, ms_svd = 0.0;
   ~mfs_op() {
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);

@@ -29,62 +29,102 @@ __device__ inline double2 vload(const double2 *a, int lda, int k0, int i, int r)
   return a[(size_t)c * lda + r];
 }
 
-__global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc *__restrict__ descs, int k0) {
+constexpr int PT = 512;    // panel kernel threads (8 waves)
+
+// Block-wide sum of a complex value over PT threads (red: 16 slots).
+__device__ inline double2 block_sum(double2 v, double2 *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double2 t = cz(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < PT / 64; ++i) t = cadd(t, red[i]);
+  return t;
+}
+
+__global__ __launch_bounds__(PT) void qr_panel_kernel(const MatDesc *__restrict__ descs, int k0) {
   const MatDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
   const int m = d.m, lda = d.lda;
   double2 *a = d.a;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   __shared__ double2 s_tau[NB];
   __shared__ double2 gram[NB][NB + 1];
   __shared__ double2 tmp[NB];
+  __shared__ double2 red[PT / 64];
+  __shared__ double2 wred[PT / 64][NB];
 
   for (int jj = 0; jj < nbp; ++jj) {
     const int j = k0 + jj;
     double2 *col = a + (size_t)j * lda;
-    if (wv == 0) {
-      double s = 0.0;
-      for (int r = j + 1 + lane; r < m; r += 64) s += cabs2(col[r]);
-      s = wave_sum(s);
-      const double2 alpha = col[j];
-      double2 tau = cz(0.0, 0.0);
-      if (!(s == 0.0 && alpha.y == 0.0)) {
-        const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s), alpha.x);
-        tau = cz((beta - alpha.x) / beta, -alpha.y / beta);
-        const double2 den = cz(alpha.x - beta, alpha.y);
-        const double dd = cabs2(den);
-        const double2 scal = cz(den.x / dd, -den.y / dd);
-        for (int r = j + 1 + lane; r < m; r += 64) col[r] = cmul(col[r], scal);
-        if (lane == 0) col[j] = cz(beta, 0.0);
-      }
-      if (lane == 0) {
-        s_tau[jj] = tau;
-        d.tau[j] = tau;
-      }
+    // Householder vector of column j (rows j..m-1), all threads
+    double s = 0.0;
+    for (int r = j + 1 + tid; r < m; r += PT) s += cabs2(col[r]);
+    const double ssum = block_sum(cz(s, 0.0), red).x;
+    const double2 alpha = col[j];
+    double2 tau = cz(0.0, 0.0);
+    if (!(ssum == 0.0 && alpha.y == 0.0)) {
+      const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + ssum), alpha.x);
+      tau = cz((beta - alpha.x) / beta, -alpha.y / beta);
+      const double2 den = cz(alpha.x - beta, alpha.y);
+      const double dd = cabs2(den);
+      const double2 scal = cz(den.x / dd, -den.y / dd);
+      for (int r = j + 1 + tid; r < m; r += PT) col[r] = cmul(col[r], scal);
+      __syncthreads();   // alpha read by every thread before it is overwritten
+      if (tid == 0) col[j] = cz(beta, 0.0);
+    }
+    if (tid == 0) {
+      s_tau[jj] = tau;
+      d.tau[j] = tau;
     }
     __syncthreads();
-    const double2 ctau = cconj(s_tau[jj]);
-    for (int c = j + 1 + wv; c < k0 + nbp; c += 4) {
-      double2 *cc = a + (size_t)c * lda;
-      double2 acc = cz(0.0, 0.0);
-      for (int r = j + lane; r < m; r += 64) {
+    // w_c = v^H A[:, c] for the remaining panel columns, one pass over the rows
+    const int nc = k0 + nbp - (j + 1);
+    if (nc > 0) {
+      double2 w[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) w[c] = cz(0.0, 0.0);
+      for (int r = j + tid; r < m; r += PT) {
         const double2 vr = (r == j) ? cz(1.0, 0.0) : col[r];
-        cfmac(acc, vr, cc[r]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < nc) cfmac(w[c], vr, a[(size_t)(j + 1 + c) * lda + r]);
       }
-      acc = wave_sum(acc);
-      const double2 f = cmul(ctau, acc);
-      for (int r = j + lane; r < m; r += 64) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c < nc) {
+          const double2 t = wave_sum(w[c]);
+          if (lane == 0) wred[wv][c] = t;
+        }
+      }
+      __syncthreads();
+      if (tid < nc) {
+        double2 t = cz(0.0, 0.0);
+        for (int i = 0; i < PT / 64; ++i) t = cadd(t, wred[i][tid]);
+        tmp[tid] = cmul(cconj(s_tau[jj]), t);
+      }
+      __syncthreads();
+      for (int r = j + tid; r < m; r += PT) {
         const double2 vr = (r == j) ? cz(1.0, 0.0) : col[r];
-        cc[r] = csub(cc[r], cmul(vr, f));
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c < nc) {
+            double2 *p = a + (size_t)(j + 1 + c) * lda + r;
+            *p = csub(*p, cmul(vr, tmp[c]));
+          }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // Gram matrix of the panel's Householder vectors, G[g][i] = v_g^H v_i, g < i
   const int npairs = nbp * (nbp - 1) / 2;
-  for (int pidx = wv; pidx < npairs; pidx += 4) {
+  for (int pidx = wv; pidx < npairs; pidx += PT / 64) {
     // unrank pidx -> (g, i) with g < i
     int i = 1, base = 0;
     while (base + i <= pidx) { base += i; ++i; }
@@ -99,7 +139,6 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc *__restrict
   // T (forward, columnwise): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i,0:i] G[0:i, i].
   // Row h of T is only ever written by thread h, so only tmp needs barriers.
   __shared__ double2 Tsh[NB][NB + 1];
-  const int tid = threadIdx.x;
   for (int i = 0; i < nbp; ++i) {
     const double2 ti = s_tau[i];
     if (tid < i) tmp[tid] = cmul(cz(-ti.x, -ti.y), gram[tid][i]);
@@ -113,7 +152,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc *__restrict
     __syncthreads();
   }
   double2 *T = d.T + (size_t)(k0 / NB) * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
+  for (int idx = tid; idx < NB * NB; idx += PT) {
     const int r = idx % NB, c = idx / NB;
     T[idx] = (r <= c && c < nbp) ? Tsh[r][c] : cz(0.0, 0.0);
   }
@@ -222,7 +261,7 @@ void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t 
   for (const auto &d : h) nmax = std::max(nmax, d.n);
   const int nmat = (int)h.size();
   for (int k0 = 0; k0 < nmax; k0 += NB) {
-    hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(256), 0, s, descs, k0);
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(PT), 0, s, descs, k0);
     HIP_CHECK(hipGetLastError());
     const int trail = nmax - k0 - NB;
     if (trail > 0) {

@@ -35,13 +35,44 @@ __global__ void jac_init_kernel(const MatDesc *__restrict__ descs) {
   }
 }
 
+// Squared column norms of R into d.sv (kept up to date by the rotations) and
+// the deflation threshold of each matrix: rel * max column norm, squared.
+// The largest column norm bounds s_max from below, so pairs of columns whose
+// norms are both below rel * s_max_estimate are certainly below the
+// truncation cutoff and stay so: a rotation only moves norm between its two
+// columns (|g_p|^2 + |g_q|^2 is invariant), and a rotation of a tiny column
+// against a large one shrinks the tiny one.  Such pairs are skipped.
+__global__ __launch_bounds__(256) void jac_norms_kernel(const MatDesc *__restrict__ descs,
+                                                        double rel, double *__restrict__ thr) {
+  const MatDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double wmax[4];
+  double mx = 0.0;
+  for (int c = wv; c < n; c += 4) {
+    const double2 *a = d.a + (size_t)c * d.lda;
+    double s = 0.0;
+    for (int r = lane; r <= c; r += 64) s += cabs2(a[r]);
+    s = wave_sum(s);
+    if (lane == 0) d.sv[c] = s;
+    mx = fmax(mx, s);
+  }
+  if (lane == 0) wmax[wv] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    thr[blockIdx.x] = rel * rel * m;
+  }
+}
+
 __global__ void jac_clear_flags(const MatDesc *__restrict__ descs, int nmat) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nmat) descs[i].flag[0] = 0;
 }
 
 __global__ __launch_bounds__(256) void jac_round_kernel(const MatDesc *__restrict__ descs,
-                                                        int round, double tol) {
+                                                        int round, double tol,
+                                                        const double *__restrict__ thr) {
   const MatDesc d = descs[blockIdx.y];
   const int n = d.n;
   const int np = n + (n & 1);
@@ -59,6 +90,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(const MatDesc *__restric
     q = (rr - pair + mod) % mod;
   }
   if (p >= n || q >= n) return;
+  if (fmax(d.sv[p], d.sv[q]) < thr[blockIdx.y]) return;   // both negligible: skip
   double2 *gp = d.g + (size_t)p * d.ldg;
   double2 *gq = d.g + (size_t)q * d.ldg;
   double a = 0.0, b = 0.0;
@@ -82,6 +114,10 @@ __global__ __launch_bounds__(256) void jac_round_kernel(const MatDesc *__restric
   const double2 e = cz(c.x / ac, c.y / ac);           // e^{i th}
   const double2 se = cz(sn * e.x, sn * e.y);            // s e^{i th}
   const double2 sec = cz(sn * e.x, -sn * e.y);          // s e^{-i th}
+  if (lane == 0) {
+    d.sv[p] = fmax(a - t * ac, 0.0);
+    d.sv[q] = b + t * ac;
+  }
   for (int r = lane; r < n; r += 64) {
     const double2 x = gp[r], y = gq[r];
     gp[r] = csub(cscale(x, cs), cmul(sec, y));
@@ -173,6 +209,11 @@ void svd_truncate(const MatDesc *descs, const std::vector<MatDesc> &h, double re
                 "svd_truncate: flags and ranks must be contiguous");
   }
   std::vector<int> flags(nmat);
+  DevBuf thr((size_t)nmat * sizeof(double));
+  // pairs of columns below 1e-3 of the cutoff are skipped (see jac_norms_kernel)
+  hipLaunchKernelGGL(jac_norms_kernel, dim3(nmat), dim3(256), 0, s, descs, 1e-3 * rel_cutoff,
+                     thr.as<double>());
+  HIP_CHECK(hipGetLastError());
   // relative orthogonality reachable in floating point is ~ sqrt(n) eps (the
   // stopping rule of LAPACK's one-sided Jacobi)
   const double tol = 4.0 * sqrt((double)nmax) * 2.220446049250313e-16;
@@ -181,7 +222,7 @@ void svd_truncate(const MatDesc *descs, const std::vector<MatDesc> &h, double re
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
     for (int rnd = 0; rnd < npmax - 1; ++rnd) {
       hipLaunchKernelGGL(jac_round_kernel, dim3(cdiv(npmax / 2, 4), nmat), dim3(256), 0, s, descs,
-                         rnd, tol);
+                         rnd, tol, thr.as<double>());
     }
     HIP_CHECK(hipGetLastError());
     bool any = false;
