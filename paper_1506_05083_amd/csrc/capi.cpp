@@ -223,56 +223,6 @@ static void validate_body(const mfs_body &b) {
   for (int m = 0; m < b.M; ++m) MFS_REQUIRE(b.rho[m] > 0.0, "collocation rho must be > 0");
 }
 
-static void factor_storage(mfs_op *op) {
-  // all distinct blocks of all bodies share one QR + Jacobi batch
-  size_t nblk = 0;
-  for (auto &bp : op->bodies) nblk += bp->nd;
-  op->flags_ranks.alloc(2 * nblk * sizeof(int));
-  int *flags = op->flags_ranks.as<int>();
-  int *ranks = flags + nblk;
-  size_t bi = 0;
-  op->all_descs.clear();
-  for (auto &bp : op->bodies) {
-    BodyData &b = *bp;
-    const int N = b.N, ldA = b.ldA, ldg = round_up(N, 16);
-    const int npan = cdiv(N, kQRNB);
-    const size_t per_c = (size_t)N + (size_t)npan * kQRNB * kQRNB + 3 * (size_t)N * ldg + (size_t)N * ldA;
-    const size_t per_r = (size_t)N + (size_t)N / 2 + 1;   // sv doubles + perm ints (as doubles)
-    b.fac.alloc((per_c * sizeof(double2) + per_r * sizeof(double)) * b.nd);
-    double2 *base = b.fac.as<double2>();
-    double *rbase = reinterpret_cast<double *>(base + per_c * b.nd);
-    b.h_descs.resize(b.nd);
-    for (int d = 0; d < b.nd; ++d) {
-      MatDesc m{};
-      double2 *p = base + per_c * d;
-      m.a = b.blocks.as<double2>() + (size_t)d * N * ldA;
-      m.m = b.M;
-      m.n = N;
-      m.lda = ldA;
-      m.tau = p; p += N;
-      m.T = p; p += (size_t)npan * kQRNB * kQRNB;
-      m.g = p; p += (size_t)N * ldg;
-      m.v = p; p += (size_t)N * ldg;
-      m.w = p; p += (size_t)N * ldg;
-      m.u = p; p += (size_t)N * ldA;
-      m.ldg = ldg;
-      double *rp = rbase + per_r * d;
-      m.sv = rp;
-      m.perm = reinterpret_cast<int *>(rp + N);
-      m.flag = flags + bi;
-      m.rank = ranks + bi;
-      ++bi;
-      b.h_descs[d] = m;
-      op->all_descs.push_back(m);
-    }
-    b.descs.alloc(b.nd * sizeof(MatDesc));
-    upload(b.descs.p, b.h_descs.data(), b.nd * sizeof(MatDesc), op->stream);
-  }
-  op->all_descs_dev.alloc(op->all_descs.size() * sizeof(MatDesc));
-  upload(op->all_descs_dev.p, op->all_descs.data(), op->all_descs.size() * sizeof(MatDesc), op->stream);
-  HIP_CHECK(hipStreamSynchronize(op->stream));
-}
-
 BodyData &body_of(const mfs_op *op, int body) {
   MFS_REQUIRE(op != nullptr, "null operator");
   MFS_REQUIRE(body >= 0 && body < (int)op->bodies.size(), "body index out of range");
@@ -403,16 +353,25 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   MFS_REQUIRE(rel_cutoff >= 0.0 && rel_cutoff < 1.0, "rel_cutoff must be in [0, 1)");
   if (op->factored) MFS_THROW(MFS_ESTATE, "operator already factored");
   HIP_CHECK(hipSetDevice(op->ctx->device));
-  factor_storage(op);
-  const MatDesc *descs = op->all_descs_dev.as<MatDesc>();
-  HIP_CHECK(hipEventCreate(&op->ev[0]));
-  HIP_CHECK(hipEventCreate(&op->ev[1]));
-  HIP_CHECK(hipEventCreate(&op->ev[2]));
+  // every distinct block of every body in one batched pseudoinverse
+  std::vector<MatDesc> in;
+  for (auto &bp : op->bodies) {
+    BodyData &b = *bp;
+    for (int d = 0; d < b.nd; ++d) {
+      MatDesc m{};
+      m.a = b.blocks.as<double2>() + (size_t)d * b.N * b.ldA;
+      m.m = b.M;
+      m.n = b.N;
+      m.lda = b.ldA;
+      in.push_back(m);
+    }
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!op->ev[i]) HIP_CHECK(hipEventCreate(&op->ev[i]));
+  op->gp = std::make_unique<GradedPinv>();
+  op->gp->ev_qr_done = op->ev[1];
   HIP_CHECK(hipEventRecord(op->ev[0], op->stream));
-  qr_factor(descs, op->all_descs, op->stream);
-  HIP_CHECK(hipEventRecord(op->ev[1], op->stream));
-  std::vector<int> rk;
-  svd_truncate(descs, op->all_descs, rel_cutoff, op->stream, rk);
+  graded_pinv(*op->gp, in, rel_cutoff, op->stream);
   HIP_CHECK(hipEventRecord(op->ev[2], op->stream));
   HIP_CHECK(hipStreamSynchronize(op->stream));
   float ms_qr = 0, ms_svd = 0;
@@ -422,10 +381,15 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   op->ms_svd = ms_svd;
   size_t bi = 0;
   for (auto &bp : op->bodies) {
-    bp->rank.assign(rk.begin() + bi, rk.begin() + bi + bp->nd);
-    bi += bp->nd;
+    BodyData &b = *bp;
+    b.h_descs.assign(op->gp->h_fin.begin() + bi, op->gp->h_fin.begin() + bi + b.nd);
+    b.rank.assign(op->gp->kept.begin() + bi, op->gp->kept.begin() + bi + b.nd);
+    b.descs.alloc(b.nd * sizeof(MatDesc));
+    upload(b.descs.p, b.h_descs.data(), b.nd * sizeof(MatDesc), op->stream);
+    bi += b.nd;
   }
-  if (ranks) std::copy(rk.begin(), rk.end(), ranks);
+  HIP_CHECK(hipStreamSynchronize(op->stream));
+  if (ranks) std::copy(op->gp->kept.begin(), op->gp->kept.end(), ranks);
   op->factored = true;
   op->cutoff = rel_cutoff;
   MFS_API_END
@@ -445,8 +409,15 @@ mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out) {
   BodyData &b = body_of(op, body);
   if (!op->factored) MFS_THROW(MFS_ESTATE, "operator not factored");
   MFS_REQUIRE(out != nullptr, "null output");
-  for (int d = 0; d < b.nd; ++d)
-    HIP_CHECK(hipMemcpy(out + (size_t)d * b.N, b.h_descs[d].sv, b.N * sizeof(double), hipMemcpyDeviceToHost));
+  size_t bi = 0;
+  for (int i = 0; i < body; ++i) bi += op->bodies[i]->nd;
+  for (int d = 0; d < b.nd; ++d) {
+    const MatDesc &l = op->gp->h_lq[bi + d];
+    std::fill(out + (size_t)d * b.N, out + (size_t)(d + 1) * b.N, 0.0);
+    // the Jacobi factor holds the r leading singular values; the rest are
+    // below 1e-15 of the largest and reported as zero
+    HIP_CHECK(hipMemcpy(out + (size_t)d * b.N, l.sv, std::min(l.n, b.N) * sizeof(double), hipMemcpyDeviceToHost));
+  }
   MFS_API_END
 }
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "geometry.hpp"
+#include "gpinv.hpp"
 #include "internal.hpp"
 
 struct mfs_ctx {
@@ -19,9 +20,7 @@ struct mfs_op {
   std::vector<std::unique_ptr<mfs::BodyData>> bodies;
   bool factored = false;
   double cutoff = 1e-10;
-  mfs::DevBuf flags_ranks;
-  std::vector<mfs::MatDesc> all_descs;
-  mfs::DevBuf all_descs_dev;
+  std::unique_ptr<mfs::GradedPinv> gp;   // factors of all distinct blocks
   mfs::DevBuf work;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double ms_fill = 0.0, ms_qr = 0.0, ms_svd = 0.0;

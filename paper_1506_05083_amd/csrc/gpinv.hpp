@@ -1,0 +1,28 @@
+// Truncated pseudoinverse of graded matrices (see gpinv.hip).
+#pragma once
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mfs {
+
+struct GradedPinv {
+  struct Store {
+    DevBuf a, fac;
+  };
+  DevBuf d_in, d_qc, d_lq, d_fin, perm, piv, small;
+  std::vector<Store> qc, lq;
+  std::vector<DevBuf> fin;
+  std::vector<MatDesc> h_qc, h_lq, h_fin;
+  std::vector<double> maxcol;
+  std::vector<int> cols, rows, kept;
+  hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the pivoted QR
+  // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
+  const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
+};
+
+// in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.
+void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, hipStream_t s);
+
+}  // namespace mfs

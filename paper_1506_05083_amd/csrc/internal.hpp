@@ -75,9 +75,6 @@ void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, doub
 
 // batched QR of nmat matrices described by descs (device) / h (host copy)
 void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s);
-// Jacobi SVD of the R factors, truncation, explicit U = Q [U_R; 0] and W = V S^+
-void svd_truncate(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff,
-                  hipStream_t s, std::vector<int> &ranks);
 
 // y = A^+ x with the kept factors: job layout
 //   mode 0 (one-body blocks): mat d = distinct mode, columns = bins d and P-d

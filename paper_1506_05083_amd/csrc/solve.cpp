@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "capi_impl.hpp"
+#include "gpinv.hpp"
 
 namespace mfs {
 
@@ -70,6 +71,7 @@ struct Solver {
   DevBuf qflags, qdescs, Bvals, walls_soa;
   std::vector<MatDesc> h_qdescs;
   std::vector<int> qrank;
+  GradedPinv gp;
   // plans
   NsumPlan psurf, pwalls;
   DevBuf wsurf, wwalls;
@@ -110,23 +112,9 @@ struct Solver {
       MFS_REQUIRE(NQ <= rows, "periodizer: Q has more columns than rows (raise M1)");
       QStore &q = Q[w];
       q.a.alloc((size_t)ldq * NQ * sizeof(double2));
-      const int ldg = round_up(NQ, 16);
-      const int npan = cdiv(NQ, kQRNB);
-      const size_t nc = (size_t)NQ + (size_t)npan * kQRNB * kQRNB + 3 * (size_t)NQ * ldg + (size_t)NQ * ldq;
-      q.fac.alloc(nc * sizeof(double2) + (size_t)2 * NQ * sizeof(double));
-      double2 *p = q.fac.as<double2>();
       MatDesc &d = q.d;
+      d = MatDesc{};
       d.a = q.a.as<double2>(); d.m = rows; d.n = NQ; d.lda = ldq;
-      d.tau = p; p += NQ;
-      d.T = p; p += (size_t)npan * kQRNB * kQRNB;
-      d.g = p; p += (size_t)NQ * ldg;
-      d.v = p; p += (size_t)NQ * ldg;
-      d.w = p; p += (size_t)NQ * ldg;
-      d.u = p; p += (size_t)NQ * ldq;
-      d.ldg = ldg;
-      double *rp = reinterpret_cast<double *>(p);
-      d.sv = rp;
-      d.perm = reinterpret_cast<int *>(rp + NQ);
       d.flag = flags + w;
       d.rank = flags + W + w;
       h_qdescs[w] = d;
@@ -160,8 +148,8 @@ struct Solver {
     qdescs.alloc(W * sizeof(MatDesc));
     upload(qdescs.p, h_qdescs.data(), W * sizeof(MatDesc), s);
     HIP_CHECK(hipStreamSynchronize(s));   // ordbufs are released on return
-    qr_factor(qdescs.as<MatDesc>(), h_qdescs, s);
-    svd_truncate(qdescs.as<MatDesc>(), h_qdescs, rel_cutoff, s, qrank);
+    graded_pinv(gp, h_qdescs, rel_cutoff, s);
+    qrank = gp.kept;
     // harmonics' Neumann data on the surface rings
     Bvals.alloc((size_t)NH * M * sizeof(double2));
     launch_bfill(M, lat.p, b.k, b.rho, b.z, b.nrho, b.nz, Bvals.as<double2>(), s);
@@ -214,7 +202,7 @@ struct Solver {
     PinvJob j{};
     j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
     j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
-    j.descs = qdescs.as<MatDesc>(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
+    j.descs = gp.apply_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
     launch_pinv_apply(j, s);
   }
 
@@ -244,7 +232,7 @@ struct Solver {
     PinvJob j{};
     j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
     j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
-    j.descs = qdescs.as<MatDesc>(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
+    j.descs = gp.apply_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
     launch_pinv_apply(j, s);
     launch_bapply(W, P, M, lat.p, Bvals.as<double2>(), XI.as<double2>(), NQmax, out, s);
   }
