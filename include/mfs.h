@@ -104,11 +104,16 @@ typedef struct {
   int32_t nq_cols;        /* columns of Q                                     */
 } mfs_result;
 
-/* Timing of the last mfs_solve_incident stages, milliseconds (HIP events). */
+/* Timing of the last mfs_solve_incident stages, milliseconds (HIP events on
+ * the operator's stream). */
 typedef struct {
   double rhs, periodizer, gmres, recover, total;
-  double nsum_avg;        /* mean duration of one neighbour-sum launch       */
+  double nsum_avg;        /* mean duration of one surface neighbour-sum launch */
   int32_t nsum_launches;
+  double jacobi_ms;       /* Jacobi sweeps of the periodizer's pseudoinverse   */
+  int32_t jacobi_launches;
+  double jacobi_bytes;    /* algorithmic bytes of those launches: every pair
+                             rotation reads and writes 4 columns of length n  */
 } mfs_solve_timing;
 
 const char *mfs_last_error(void);

@@ -30,8 +30,6 @@
 namespace mfs {
 
 void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s);
-void jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
-             hipStream_t s);
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,
               std::vector<int> &ranks);
 
@@ -416,7 +414,10 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
                      g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_lq.as<MatDesc>(), g.h_lq, s);
-  jac_run(g.d_lq.as<MatDesc>(), g.h_lq, 1, rel_cutoff, s);
+  const JacStats js = jac_run(g.d_lq.as<MatDesc>(), g.h_lq, 1, rel_cutoff, s);
+  g.jacobi_ms = js.ms;
+  g.jacobi_launches = js.launches;
+  g.jacobi_bytes = js.bytes;
   jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
   // 6. explicit factors
   const int rmax = *std::max_element(rr.begin(), rr.end());

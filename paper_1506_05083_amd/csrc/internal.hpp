@@ -73,6 +73,14 @@ void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, 
 void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, double2 *sigma,
                             hipStream_t s);
 
+struct JacStats {
+  double ms = 0.0;       // time of the rotation launches (HIP events)
+  int launches = 0;
+  double bytes = 0.0;    // algorithmic bytes: 4 columns read + 4 written per pair
+};
+JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
+                 hipStream_t s);
+
 // batched QR of nmat matrices described by descs (device) / h (host copy)
 void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s);
 

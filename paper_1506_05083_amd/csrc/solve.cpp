@@ -520,6 +520,9 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       timing->total = t04;
       timing->nsum_avg = S.nsum_avg_ms();
       timing->nsum_launches = (int)(S.nsum_ev.size() / 2);
+      timing->jacobi_ms = S.gp.jacobi_ms;
+      timing->jacobi_launches = S.gp.jacobi_launches;
+      timing->jacobi_bytes = S.gp.jacobi_bytes;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (notconv) {

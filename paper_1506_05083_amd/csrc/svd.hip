@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(const MatDesc *__restric
   c = wave_sum(c);
   const double ac = sqrt(cabs2(c));
   if (!(ac > tol * sqrt(a) * sqrt(b))) return;
-  if (lane == 0) d.flag[0] = 1;
+  if (lane == 0) atomicAdd(d.flag, 1);   // rotations this sweep
   const double zeta = (b - a) / (2.0 * ac);
   const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + t * t);
@@ -143,13 +143,17 @@ __global__ __launch_bounds__(256) void jac_sort_kernel(const MatDesc *__restrict
 
 }  // namespace
 
-void jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
-             hipStream_t s) {
+JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
+                 hipStream_t s) {
+  JacStats st;
   const int nmat = (int)h.size();
   int nmax = 0;
   for (const auto &d : h) nmax = std::max(nmax, d.n);
-  if (nmax == 0) return;
+  if (nmax == 0) return st;
   const int npmax = nmax + (nmax & 1);
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
   hipLaunchKernelGGL(jac_init_kernel, dim3(std::min(1024, cdiv(nmax * nmax, 256)), nmat), dim3(256),
                      0, s, descs, init_mode);
   HIP_CHECK(hipGetLastError());
@@ -166,22 +170,39 @@ void jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode,
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
+    HIP_CHECK(hipEventRecord(e0, s));
     for (int rnd = 0; rnd < npmax - 1; ++rnd) {
       hipLaunchKernelGGL(jac_round_kernel, dim3(cdiv(npmax / 2, 4), nmat), dim3(256), 0, s, descs,
                          rnd, tol);
     }
     HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipEventRecord(e1, s));
     bool any = false;
     HIP_CHECK(hipMemcpyAsync(flags.data(), h[0].flag, nmat * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    st.ms += ms;
+    st.launches += npmax - 1;
+    // algorithmic bytes: every pair reads its two columns of G; a pair that
+    // rotates also writes them and reads and writes its two columns of V
+    for (int i = 0; i < nmat; ++i) {
+      const double col = (double)h[i].n * sizeof(double2);
+      st.bytes += 0.5 * h[i].n * (h[i].n - 1) * 2.0 * col + (double)flags[i] * 6.0 * col;
+    }
     for (int f : flags) any |= (f != 0);
     if (dbg) {
       int nact = 0;
-      for (int f : flags) nact += (f != 0);
-      fprintf(stderr, "[jacobi] nmat %d n %d sweep %d active %d\n", nmat, nmax, sweep, nact);
+      long nrot = 0;
+      for (int f : flags) { nact += (f != 0); nrot += f; }
+      fprintf(stderr, "[jacobi] nmat %d n %d sweep %d active %d rotations %ld\n", nmat, nmax, sweep, nact,
+              nrot);
     }
     if (!any) break;
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,

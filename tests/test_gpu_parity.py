@@ -221,3 +221,33 @@ def test_periodic_solve_parity_small(mfs, ctx, small_oracle):
             f"u {eu:.2e} flux gpu {r.eps_flux:.2e} oracle {o['flux']:.2e}")
         assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
         assert r.eps_flux < 1e-6
+
+
+def test_periodic_k10_full_size_vs_golden(mfs, ctx):
+    """Full size of the benchmark workload, in the benchmark's launch
+    configuration (all 8 incidences in one batched solve), against the
+    oracle's stored solution of incidence 0 (tests/golden/make_golden.py):
+    Bragg amplitudes and cell fields to 1e-10."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "periodic_k10_wave0.json")))
+    pr = W.periodic_k10(8)
+    b, lat = pr.body, pr.lattice
+    assert abs(pr.waves[0].theta - gold["theta"]) < 1e-15 and abs(pr.waves[0].phi - gold["phi"]) < 1e-15
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    tg = np.array(gold["targets"])
+    res = mfs.solve_incident(ctx, op, _lat(mfs, lat), [(w.theta, w.phi) for w in pr.waves], tol=1e-12,
+                             maxit=100, targets=tg, q_field=gold["q_field"])
+    r = res[0]
+    assert r.m.tolist() == gold["m"] and r.n.tolist() == gold["n"]
+    ga = np.array(gold["a_re"]) + 1j * np.array(gold["a_im"])
+    gb = np.array(gold["b_re"]) + 1j * np.array(gold["b_im"])
+    gu = np.array(gold["u_re"]) + 1j * np.array(gold["u_im"])
+    ea = np.max(np.abs(r.a - ga)) / np.max(np.abs(ga))
+    eb = np.max(np.abs(r.b - gb)) / np.max(np.abs(gb))
+    eu = np.linalg.norm(r.field - gu) / np.linalg.norm(gu)
+    log(f"[k10] iters gpu {r.iters} oracle {gold['iters']} a {ea:.2e} b {eb:.2e} u {eu:.2e} "
+        f"flux {r.eps_flux:.2e} (oracle {gold['eps_flux']:.2e})")
+    assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+    assert all(x.eps_flux < 1e-7 for x in res)
