@@ -196,11 +196,21 @@ def main():
     jac_ms = float(np.median([t["jacobi_ms"] for t in tms]))
     jac_launch_ms = jac_ms / max(1, int(np.median([t["jacobi_launches"] for t in tms])))
     jac_bytes = float(np.median([t["jacobi_bytes"] / max(1, t["jacobi_launches"]) for t in tms]))
+    jac_flops = float(np.median([t["jacobi_flops"] / max(1, t["jacobi_launches"]) for t in tms]))
     jac_gbs = jac_bytes / (jac_launch_ms * 1e-3) / 1e9
-    roof_jac = {"bound": "hbm", "kernel": "jac_round_kernel (periodizer pseudoinverse, 8 waves)",
-                "achieved": jac_gbs, "peak": PEAK_HBM, "unit": "GB/s", "frac": jac_gbs / PEAK_HBM,
-                "traffic": None, "launch_ms": jac_launch_ms, "bytes_per_launch": jac_bytes,
-                "share_of_step": jac_ms / ms_step}
+    jac_tflops = jac_flops / (jac_launch_ms * 1e-3) / 1e12
+    jac_common = {"kernel": "jac_block_kernel (periodizer pseudoinverse, 8 waves)",
+                  "traffic": None, "launch_ms": jac_launch_ms, "bytes_per_launch": jac_bytes,
+                  "flops_per_launch": jac_flops, "flops_per_byte": jac_flops / max(jac_bytes, 1.0),
+                  "share_of_step": jac_ms / ms_step}
+    # the bound is the one the kernel's arithmetic intensity selects against
+    # the FP64 / HBM balance of the chip
+    if jac_flops / max(jac_bytes, 1.0) >= PEAK_FP64 * 1e12 / (PEAK_HBM * 1e9):
+        roof_jac = {"bound": "alu", "achieved": jac_tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                    "frac": jac_tflops / PEAK_FP64, **jac_common}
+    else:
+        roof_jac = {"bound": "hbm", "achieved": jac_gbs, "peak": PEAK_HBM, "unit": "GB/s",
+                    "frac": jac_gbs / PEAK_HBM, **jac_common}
     roofline, other = (roof_jac, roof_nsum) if roof_jac["share_of_step"] >= roof_nsum["share_of_step"] \
         else (roof_nsum, roof_jac)
     line = {

@@ -112,8 +112,13 @@ typedef struct {
   int32_t nsum_launches;
   double jacobi_ms;       /* Jacobi sweeps of the periodizer's pseudoinverse   */
   int32_t jacobi_launches;
-  double jacobi_bytes;    /* algorithmic bytes of those launches: every pair
-                             rotation reads and writes 4 columns of length n  */
+  double jacobi_bytes;    /* algorithmic HBM bytes of those launches: every
+                             block-pair task reads its columns of G, a task
+                             that rotated also writes them and reads and
+                             writes its columns of V                          */
+  double jacobi_flops;    /* algorithmic FP64 flops: the Hermitian Gram matrix
+                             of every task, and the rotation product applied
+                             to G and V by the tasks that rotated             */
 } mfs_solve_timing;
 
 const char *mfs_last_error(void);

@@ -64,7 +64,8 @@ class SolveTiming(C.Structure):
     _fields_ = [("rhs", C.c_double), ("periodizer", C.c_double), ("gmres", C.c_double),
                 ("recover", C.c_double), ("total", C.c_double), ("nsum_avg", C.c_double),
                 ("nsum_launches", C.c_int32), ("jacobi_ms", C.c_double),
-                ("jacobi_launches", C.c_int32), ("jacobi_bytes", C.c_double)]
+                ("jacobi_launches", C.c_int32), ("jacobi_bytes", C.c_double),
+                ("jacobi_flops", C.c_double)]
 
 
 _SIGS = {

@@ -11,6 +11,10 @@
 //          workgroup, 16-row chunks of U and X staged through LDS;
 // stage 2: out_c[jj] = sum_i W[jj][i] Y[c][i], 64 output rows per workgroup,
 //          W streamed with coalesced column reads.
+// Mode 1 has a single right-hand side per matrix, so both stages are
+// matrix-vector products bound by streaming U and W from HBM: stage 1 gives
+// every column of U its own wave (a dot product with x), stage 2 gives every
+// 64 output rows eight waves that split the sum over i and meet in LDS.
 #include "internal.hpp"
 
 namespace mfs {
@@ -120,10 +124,73 @@ __global__ __launch_bounds__(256) void pinv_stage2(PinvJob j) {
   }
 }
 
+constexpr int S2W = 8;   // waves per workgroup in the mode-1 stage 2
+
+// mode 1, stage 1: y[mat][i] = sum_m conj(U[m][i]) x[mat][m], one wave per column i
+__global__ __launch_bounds__(256) void pinv_gemvh_kernel(PinvJob j) {
+  const int mat = blockIdx.y;
+  const MatDesc d = j.descs[mat];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= d.rank[0]) return;
+  const int lane = threadIdx.x & 63;
+  const double2 *u = d.u + (size_t)i * d.lda;
+  const double2 *x = j.x + (size_t)mat * j.ldx;
+  double2 a0 = cz(0.0, 0.0), a1 = cz(0.0, 0.0), a2 = cz(0.0, 0.0), a3 = cz(0.0, 0.0);
+  int m = lane;
+  for (; m + 192 < d.m; m += 256) {
+    const double2 u0 = u[m], u1 = u[m + 64], u2 = u[m + 128], u3 = u[m + 192];
+    const double2 x0 = x[m], x1 = x[m + 64], x2 = x[m + 128], x3 = x[m + 192];
+    cfmac(a0, u0, x0);
+    cfmac(a1, u1, x1);
+    cfmac(a2, u2, x2);
+    cfmac(a3, u3, x3);
+  }
+  for (; m < d.m; m += 64) cfmac(a0, u[m], x[m]);
+  double2 acc = cadd(cadd(a0, a1), cadd(a2, a3));
+  acc = wave_sum(acc);
+  if (lane == 0) j.ywork[(size_t)mat * j.maxcols * j.maxr + i] = acc;
+}
+
+// mode 1, stage 2: out[mat][row] = sum_{i < rank} W[row][i] y[i]
+__global__ __launch_bounds__(64 * S2W) void pinv_gemv_kernel(PinvJob j) {
+  const int mat = blockIdx.y;
+  const MatDesc d = j.descs[mat];
+  const int r = d.rank[0];
+  const int row = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int wv = threadIdx.x >> 6;
+  __shared__ double2 part[S2W][64];
+  const double2 *y = j.ywork + (size_t)mat * j.maxcols * j.maxr;
+  double2 a0 = cz(0.0, 0.0), a1 = cz(0.0, 0.0);
+  if (row < d.n) {
+    const double2 *w = d.w + row;
+    int i = wv;
+    for (; i + S2W < r; i += 2 * S2W) {
+      cfma(a0, w[(size_t)i * d.ldg], y[i]);
+      cfma(a1, w[(size_t)(i + S2W) * d.ldg], y[i + S2W]);
+    }
+    for (; i < r; i += S2W) cfma(a0, w[(size_t)i * d.ldg], y[i]);
+  }
+  part[wv][threadIdx.x & 63] = cadd(a0, a1);
+  __syncthreads();
+  if (wv == 0 && row < d.n) {
+    double2 t = part[0][threadIdx.x];
+#pragma unroll
+    for (int g = 1; g < S2W; ++g) t = cadd(t, part[g][threadIdx.x]);
+    j.out[(size_t)mat * j.ldo + row] = t;
+  }
+}
+
 }  // namespace
 
 void launch_pinv_apply(const PinvJob &j, hipStream_t s) {
   MFS_REQUIRE(j.maxcols <= MAXC, "too many right-hand sides in one apply (max 16 per call)");
+  if (j.mode == 1) {
+    hipLaunchKernelGGL(pinv_gemvh_kernel, dim3(cdiv(j.maxr, 4), j.nmat), dim3(256), 0, s, j);
+    HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(pinv_gemv_kernel, dim3(cdiv(j.maxn, 64), j.nmat), dim3(64 * S2W), 0, s, j);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(pinv_stage1, dim3(cdiv(j.maxr, 64), j.nmat), dim3(256), 0, s, j);
   HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(pinv_stage2, dim3(cdiv(j.maxn, 64), j.nmat), dim3(256), 0, s, j);

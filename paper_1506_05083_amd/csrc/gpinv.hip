@@ -418,6 +418,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.jacobi_ms = js.ms;
   g.jacobi_launches = js.launches;
   g.jacobi_bytes = js.bytes;
+  g.jacobi_flops = js.flops;
   jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
   // 6. explicit factors
   const int rmax = *std::max_element(rr.begin(), rr.end());

@@ -18,9 +18,10 @@ struct GradedPinv {
   std::vector<double> maxcol;
   std::vector<int> cols, rows, kept;
   hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the pivoted QR
-  double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes
+  double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;
   double jacobi_bytes = 0.0;
+  double jacobi_flops = 0.0;
   // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
   const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
 };

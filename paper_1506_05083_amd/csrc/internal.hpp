@@ -74,9 +74,10 @@ void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, doub
                             hipStream_t s);
 
 struct JacStats {
-  double ms = 0.0;       // time of the rotation launches (HIP events)
+  double ms = 0.0;       // time of the sweep launches (HIP events)
   int launches = 0;
-  double bytes = 0.0;    // algorithmic bytes: 4 columns read + 4 written per pair
+  double bytes = 0.0;    // algorithmic HBM bytes of the sweeps
+  double flops = 0.0;    // algorithmic FP64 flops of the sweeps
 };
 JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
                  hipStream_t s);

@@ -523,6 +523,7 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       timing->jacobi_ms = S.gp.jacobi_ms;
       timing->jacobi_launches = S.gp.jacobi_launches;
       timing->jacobi_bytes = S.gp.jacobi_bytes;
+      timing->jacobi_flops = S.gp.jacobi_flops;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (notconv) {
