@@ -69,11 +69,53 @@ __host__ __device__ inline void cfmac(double2 &acc, double2 a, double2 b) {
   acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
 }
 
+// cond ? a : b component by component (a select of the whole struct can be
+// lowered through private memory)
+__host__ __device__ inline double2 csel(bool cond, double2 a, double2 b) {
+  return cz(cond ? a.x : b.x, cond ? a.y : b.y);
+}
+
+// p[i] if ok, else 0.  The load itself is unconditional (index 0 when !ok,
+// so p must point at valid memory) and its bits are masked, not selected, so
+// that the compiler cannot move it under a branch: a run of these is issued
+// back to back instead of one branch and one wait per element.
+__device__ inline double2 ld_or0(const double2 *p, size_t i, bool ok) {
+  const double2 v = p[ok ? i : 0];
+  const long long m = ok ? -1LL : 0LL;
+  return cz(__longlong_as_double(__double_as_longlong(v.x) & m),
+            __longlong_as_double(__double_as_longlong(v.y) & m));
+}
+
 // ----------------------------------------------------- reductions
+// DPP lane move of a double (both 32-bit halves with the same pattern);
+// lanes whose source is outside the pattern, or whose row is masked off,
+// receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ inline double lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// Sum over the 64 lanes of a wave, returned to every lane.  An inclusive
+// scan inside each row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast 15
+// (rows 1 and 3 add the last lane of the row before) and row_bcast 31 (rows
+// 2 and 3 add lane 31) leave the total in lane 63.  All 64 lanes must be
+// active.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0x111, 0xf>(v);
+  v += dpp_move<0x112, 0xf>(v);
+  v += dpp_move<0x114, 0xf>(v);
+  v += dpp_move<0x118, 0xf>(v);
+  v += dpp_move<0x142, 0xa>(v);
+  v += dpp_move<0x143, 0xc>(v);
+  return lane63(v);
 }
 __device__ inline double2 wave_sum(double2 v) {
   v.x = wave_sum(v.x);

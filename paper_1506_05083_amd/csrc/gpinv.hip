@@ -6,17 +6,21 @@
 //  1. columns with norm below 1e-15 of the largest are set aside (their
 //     coefficients are zero; the perturbation is below the SVD's own
 //     rounding level eps*sqrt(n)*s_max);
-//  2. Householder QR with column pivoting  Q P = Q_h R (the largest remaining
-//     column moves to the front at every step; unblocked, one pivot/reflector
-//     launch and one trailing-update launch per column, the partial column
-//     norms recomputed exactly by the update), then compact-WY T factors per
-//     32-column panel for the later applications of Q_h;
-//  3. trailing rows of R whose joint Frobenius norm is below 1e-15 of the
+//  2. blocked Householder QR without pivoting, Q = Q_1 R_1, which takes the
+//     tall matrix (7200 rows for the k = 10 periodizer) down to its n2 x n2
+//     triangle with matrix-product work;
+//  3. Householder QR with column pivoting of the triangle, R_1 P = Q_2 R (the
+//     largest remaining column moves to the front at every step; unblocked,
+//     one pivot/reflector launch and one trailing-update launch per column,
+//     the partial column norms recomputed exactly by the update; the pivots
+//     are those of pivoted QR of Q itself, since R_1 and Q have the same
+//     column inner products), compact-WY T factors per 32-column panel;
+//     trailing rows of R whose joint Frobenius norm is below 1e-15 of the
 //     largest column norm are dropped: R ~ R_top (r x n2);
 //  4. LQ of R_top via QR of R_top^H = Z L^H;
 //  5. one-sided Jacobi SVD of the r x r factor L = U_L S V_L^H, truncated at
 //     rel_cutoff * s_max as in the paper;
-//  6. Q^+ = P (Z V_L S^{-1}) (Q_h [U_L; 0])^H: U = Q_h [U_L; 0] and
+//  6. Q^+ = P (Z V_L S^{-1}) (Q_1 [Q_2 [U_L; 0]; 0])^H: U and
 //     W = P Z V_L S^{-1} are formed explicitly for the two-stage apply.
 // Column-pivoted QR followed by LQ is the standard preconditioning that makes
 // one-sided Jacobi converge in a handful of sweeps (7 instead of ~30 on the
@@ -75,6 +79,17 @@ __global__ void transpose_top_kernel(const MatDesc *__restrict__ src, const MatD
        idx += (long)gridDim.x * blockDim.x) {
     const int j = (int)(idx % d.m), i = (int)(idx / d.m);   // dst row j (R column), dst column i (R row)
     d.a[(size_t)i * d.lda + j] = (j >= i) ? cconj(s.a[(size_t)j * s.lda + i]) : cz(0.0, 0.0);
+  }
+}
+
+// dst (n2 x n2) = triu(src.a[0:n2, 0:n2])
+__global__ void copy_r_kernel(const MatDesc *__restrict__ src, const MatDesc *__restrict__ dst) {
+  const MatDesc s = src[blockIdx.y], d = dst[blockIdx.y];
+  const long total = (long)d.n * d.n;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % d.n), c = (int)(idx / d.n);
+    d.a[(size_t)c * d.lda + r] = (r <= c) ? s.a[(size_t)c * s.lda + r] : cz(0.0, 0.0);
   }
 }
 
@@ -308,12 +323,13 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
       if (hn[(size_t)w * nmax + c] >= 1e-15 * mx && mx > 0.0) idx.push_back(c);
     n2[w] = (int)idx.size();
     MFS_REQUIRE(n2[w] >= 1, "graded pseudoinverse: matrix is zero");
+    MFS_REQUIRE(n2[w] <= in[w].m, "graded pseudoinverse: more independent columns than rows");
     std::copy(idx.begin(), idx.end(), perm.begin() + (size_t)w * nmax);
   }
   g.perm.alloc(perm.size() * sizeof(int));
   HIP_CHECK(hipMemcpyAsync(g.perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, s));
   int n2max = *std::max_element(n2.begin(), n2.end());
-  // 2. QR of the selected, ordered columns
+  // 2. QR without pivoting of the selected, ordered columns
   g.qc.resize(W);
   g.h_qc.resize(W);
   g.small.alloc((size_t)4 * W * sizeof(int));
@@ -338,10 +354,31 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   hipLaunchKernelGGL(gather_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_in.as<MatDesc>(), g.d_qc.as<MatDesc>(),
                      g.perm.as<int>(), nmax);
   HIP_CHECK(hipGetLastError());
-  // column-pivoted QR: norms of the gathered columns, identity pivots
+  qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
+  // 3. column-pivoted QR of the n2 x n2 triangle
+  g.rq.resize(W);
+  g.h_rq.resize(W);
+  for (int w = 0; w < W; ++w) {
+    const int n = n2[w], ldr = round_up(n, 16);
+    const int npan = cdiv(n, kQRNB);
+    auto &st = g.rq[w];
+    st.a.alloc((size_t)ldr * n * sizeof(double2));
+    st.fac.alloc(((size_t)n + (size_t)npan * kQRNB * kQRNB) * sizeof(double2));
+    MatDesc d{};
+    double2 *p = st.fac.as<double2>();
+    d.a = st.a.as<double2>(); d.m = n; d.n = n; d.lda = ldr;
+    d.tau = p; p += n;
+    d.T = p;
+    d.flag = flags + 3 * W + w;
+    d.rank = flags + W + w;
+    g.h_rq[w] = d;
+  }
+  upload_descs(g.d_rq, g.h_rq, s);
+  hipLaunchKernelGGL(copy_r_kernel, dim3(1024, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_rq.as<MatDesc>());
+  HIP_CHECK(hipGetLastError());
   {
     DevBuf qn((size_t)W * nmax * sizeof(double));
-    hipLaunchKernelGGL(colnorm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+    hipLaunchKernelGGL(colnorm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
                        qn.as<double>(), nmax);
     std::vector<int> ident((size_t)W * nmax);
     for (int w = 0; w < W; ++w)
@@ -349,21 +386,21 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     g.piv.alloc(ident.size() * sizeof(int));
     HIP_CHECK(hipMemcpyAsync(g.piv.p, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice, s));
     for (int k = 0; k < n2max; ++k) {
-      hipLaunchKernelGGL(qrcp_pivot_kernel, dim3(W), dim3(PK), 0, s, g.d_qc.as<MatDesc>(), k, qn.as<double>(),
+      hipLaunchKernelGGL(qrcp_pivot_kernel, dim3(W), dim3(PK), 0, s, g.d_rq.as<MatDesc>(), k, qn.as<double>(),
                          g.piv.as<int>(), nmax);
       if (k + 1 < n2max)
         hipLaunchKernelGGL(qrcp_update_kernel, dim3(cdiv(n2max - k - 1, 4), W), dim3(256), 0, s,
-                           g.d_qc.as<MatDesc>(), k, qn.as<double>(), nmax);
+                           g.d_rq.as<MatDesc>(), k, qn.as<double>(), nmax);
     }
     HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(build_t_kernel, dim3(W, cdiv(n2max, kQRNB)), dim3(256), 0, s, g.d_qc.as<MatDesc>());
+    hipLaunchKernelGGL(build_t_kernel, dim3(W, cdiv(n2max, kQRNB)), dim3(256), 0, s, g.d_rq.as<MatDesc>());
     HIP_CHECK(hipGetLastError());
     if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
     HIP_CHECK(hipStreamSynchronize(s));   // qn is released here
   }
   // 3. rows of R to keep
   DevBuf rn((size_t)W * n2max * sizeof(double));
-  hipLaunchKernelGGL(rownorm_kernel, dim3(cdiv(n2max, 256), W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+  hipLaunchKernelGGL(rownorm_kernel, dim3(cdiv(n2max, 256), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
                      rn.as<double>(), n2max);
   HIP_CHECK(hipGetLastError());
   std::vector<double> hr((size_t)W * n2max);
@@ -410,7 +447,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     g.h_lq[w] = d;
   }
   upload_descs(g.d_lq, g.h_lq, s);
-  hipLaunchKernelGGL(transpose_top_kernel, dim3(1024, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+  hipLaunchKernelGGL(transpose_top_kernel, dim3(1024, W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
                      g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_lq.as<MatDesc>(), g.h_lq, s);
@@ -426,6 +463,15 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   for (int k : g.kept) kmax = std::max(kmax, k);
   hipLaunchKernelGGL(prep_uv_kernel, dim3(rmax, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
+  // U = Q_1 [Q_2 [U_L; 0]; 0]: the reflectors of the pivoted triangle act on
+  // the first n2 rows of the left factor, then those of the tall QR
+  g.h_rqu = g.h_rq;
+  for (int w = 0; w < W; ++w) {
+    g.h_rqu[w].u = g.h_qc[w].u;
+    g.h_rqu[w].ldu = g.h_qc[w].lda;
+  }
+  upload_descs(g.d_rqu, g.h_rqu, s);
+  qr_form_u(g.d_rqu.as<MatDesc>(), g.h_rqu, kmax, s);
   qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, kmax, s);
   qr_form_u(g.d_lq.as<MatDesc>(), g.h_lq, kmax, s);
   g.fin.resize(W);

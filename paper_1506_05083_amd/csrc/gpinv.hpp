@@ -11,13 +11,13 @@ struct GradedPinv {
   struct Store {
     DevBuf a, fac;
   };
-  DevBuf d_in, d_qc, d_lq, d_fin, perm, piv, small;
-  std::vector<Store> qc, lq;
+  DevBuf d_in, d_qc, d_rq, d_rqu, d_lq, d_fin, perm, piv, small;
+  std::vector<Store> qc, rq, lq;
   std::vector<DevBuf> fin;
-  std::vector<MatDesc> h_qc, h_lq, h_fin;
+  std::vector<MatDesc> h_qc, h_rq, h_rqu, h_lq, h_fin;
   std::vector<double> maxcol;
   std::vector<int> cols, rows, kept;
-  hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the pivoted QR
+  hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the two QR stages
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;
   double jacobi_bytes = 0.0;

@@ -44,6 +44,7 @@ struct MatDesc {
   int *perm;      // [n] work
   int *rank;      // [1] kept rank
   int *flag;      // [1] Jacobi sweep activity flag
+  int ldu;        // leading dimension of u (0: lda)
 };
 
 constexpr int kQRNB = 32;   // Householder panel width

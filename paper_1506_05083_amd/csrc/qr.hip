@@ -1,146 +1,319 @@
-// Batched blocked Householder QR of complex M x N blocks (the dense
-// per-mode least-squares factorisation of Sec. 3, eq. (linsys), and of the
-// periodizing matrix Q of Sec. 4.2).
+// Batched blocked Householder QR of tall complex matrices (the dense
+// least-squares factorisations of Sec. 3, eq. (linsys), and of the
+// periodizing matrix Q of Sec. 4.2), LAPACK's zlarfg convention:
+// H = I - tau v v^H, v(1) = 1, H^H x = beta e_1 with beta real.
 //
-// For each panel of NB = 32 columns:
-//  * qr_panel_kernel (one workgroup per matrix): unblocked Householder QR of
-//    the panel in place (LAPACK's zlarfg convention: H = I - tau v v^H,
-//    v(1) = 1, H^H x = beta e_1 with beta real), then the compact-WY factor T
-//    with H_1 ... H_nb = I - V T V^H from the Gram matrix V^H V;
-//  * qr_block_apply_kernel (many workgroups per matrix, 16 columns each):
-//    B <- (I - V T V^H)^H B = B - V T^H (V^H B) on the trailing columns, two
-//    passes over 64-row chunks staged in LDS.
-// The same block-apply kernel with T in place of T^H, run over the panels in
-// reverse, forms U = Q [U_R; 0] for the explicit left singular vectors.
+// Panels of NB = 32 columns.  The panel is factorised column by column with
+// one launch per column that spans all rows of all matrices (CH-row chunks,
+// one row per thread, the row's panel entries in registers):
+//   * launch s finishes reflector s from the chunk partial sums written by
+//     launch s-1: |x(2:)|^2 and x^H a_c for the panel columns c > s (so the
+//     reflector and every w_c = v^H a_c follow from one pass over the rows),
+//     with row j of the panel read from a side buffer that no workgroup of
+//     launch s writes;
+//   * it then applies H_s^H to its rows of the columns c > s and writes the
+//     partial sums of step s + 1.
+// The trailing matrix is updated with the compact-WY form
+// C <- (I - V T V^H)^H C = C - V T^H (V^H C):
+//   bqr_vhy_kernel   P = V^H [V | C], split over 256-row slices (partials);
+//   bqr_t_kernel     T from the V^H V part (forward, columnwise);
+//   bqr_w2_kernel    W2 = op(T) (V^H C), the slices summed;
+//   bqr_update       C -= V W2, 64 x 64 tiles, 4 x 4 outputs per thread.
+// The same three apply kernels with T in place of T^H, run over the panels
+// in reverse, form U = Q [U_R; 0] for the explicit left singular vectors.
 #include "internal.hpp"
 
 namespace mfs {
 namespace {
 
-constexpr int NB = kQRNB;
-constexpr int TC = 16;   // target columns per workgroup
-constexpr int RC = 64;   // rows per LDS chunk
+constexpr int NB = kQRNB;   // panel width
+constexpr int CH = 256;     // rows per workgroup in the panel column step
+constexpr int KR = 256;     // rows per workgroup of V^H Y (split-K slice)
+constexpr int KS = 16;      // rows per LDS stage in V^H Y
+constexpr int YT = 128;     // columns of Y per workgroup in V^H Y
+constexpr int WT = 64;      // columns per workgroup in W2 and in the update
+constexpr int UR = 64;      // rows per workgroup in the update
+constexpr int NPART = NB + 1;
 
-__device__ inline double2 vload(const double2 *a, int lda, int k0, int i, int r) {
-  // element r of Householder vector i of the panel starting at column k0
+// element r of Householder vector i of the panel starting at column k0
+__device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
   const int c = k0 + i;
-  if (r < c) return cz(0.0, 0.0);
-  if (r == c) return cz(1.0, 0.0);
-  return a[(size_t)c * lda + r];
+  const double2 x = ld_or0(d.a, (size_t)c * d.lda + r, c < d.n && r > c && r < d.m);
+  return csel(c < d.n && r == c, cz(1.0, 0.0), x);
 }
 
-constexpr int PT = 512;    // panel kernel threads (8 waves)
+__device__ inline int ldu_of(const MatDesc &d) { return d.ldu ? d.ldu : d.lda; }
 
-// Block-wide sum of a complex value over PT threads (red: 16 slots).
-__device__ inline double2 block_sum(double2 v, double2 *red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wv] = v;
-  __syncthreads();
-  double2 t = cz(0.0, 0.0);
-#pragma unroll
-  for (int i = 0; i < PT / 64; ++i) t = cadd(t, red[i]);
-  return t;
-}
-
-__global__ __launch_bounds__(PT) void qr_panel_kernel(const MatDesc *__restrict__ descs, int k0) {
-  const MatDesc d = descs[blockIdx.x];
+// Panel column step s (s = -1: partial sums of step 0 only).
+// part: [mat][2][nchmax][NPART] (slot [0].x: |x(2:)|^2, slot 1 + c: x^H a_c)
+// side: [mat][2][NB] row j of the panel columns
+__global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__ descs, int k0, int s,
+                                                     double2 *__restrict__ part, double2 *__restrict__ side,
+                                                     int nchmax) {
+  const MatDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
-  const int m = d.m, lda = d.lda;
-  double2 *a = d.a;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  __shared__ double2 s_tau[NB];
-  __shared__ double2 gram[NB][NB + 1];
-  __shared__ double2 tmp[NB];
-  __shared__ double2 red[PT / 64];
-  __shared__ double2 wred[PT / 64][NB];
+  if (s >= nbp) return;
+  const int mrows = d.m - k0;
+  if ((int)blockIdx.x * CH >= mrows) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = k0 + blockIdx.x * CH + tid;
+  const bool live = r < d.m;
+  double2 *pb = part + (size_t)blockIdx.y * 2 * nchmax * NPART;
+  double2 *sb = side + (size_t)blockIdx.y * 2 * NB;
+  __shared__ double2 fin[NPART];
+  __shared__ double2 fsum[NPART][7];
+  __shared__ double2 sf[NB];
+  __shared__ double2 red[CH / 64][NPART];
+  __shared__ double2 s_scale, s_tau, s_alpha;
+  __shared__ double s_beta;
+  __shared__ int s_refl;
 
-  for (int jj = 0; jj < nbp; ++jj) {
-    const int j = k0 + jj;
-    double2 *col = a + (size_t)j * lda;
-    // Householder vector of column j (rows j..m-1), all threads
-    double s = 0.0;
-    for (int r = j + 1 + tid; r < m; r += PT) s += cabs2(col[r]);
-    const double ssum = block_sum(cz(s, 0.0), red).x;
-    const double2 alpha = col[j];
-    double2 tau = cz(0.0, 0.0);
-    if (!(ssum == 0.0 && alpha.y == 0.0)) {
-      const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + ssum), alpha.x);
-      tau = cz((beta - alpha.x) / beta, -alpha.y / beta);
-      const double2 den = cz(alpha.x - beta, alpha.y);
-      const double dd = cabs2(den);
-      const double2 scal = cz(den.x / dd, -den.y / dd);
-      for (int r = j + 1 + tid; r < m; r += PT) col[r] = cmul(col[r], scal);
-      __syncthreads();   // alpha read by every thread before it is overwritten
-      if (tid == 0) col[j] = cz(beta, 0.0);
-    }
-    if (tid == 0) {
-      s_tau[jj] = tau;
-      d.tau[j] = tau;
+  double2 vals[NB];
+  const int cfirst = s < 0 ? 0 : s;
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    vals[c] = ld_or0(d.a, (size_t)(k0 + c) * d.lda + r, live && c >= cfirst && c < nbp);
+
+  if (s >= 0) {
+    const int j = k0 + s;
+    const double2 *pin = pb + (size_t)(s & 1) * nchmax * NPART;
+    const double2 *srow = sb + (s & 1) * NB;
+    const int nch = (mrows + CH - 1) / CH;
+    // chunk partials summed by 7 threads per slot, then across them
+    if (tid < NPART * 7) {
+      const int slot = tid / 7, sub = tid % 7;
+      double2 t = cz(0.0, 0.0);
+      for (int ch = sub; ch < nch; ch += 7) t = cadd(t, pin[(size_t)ch * NPART + slot]);
+      fsum[slot][sub] = t;
     }
     __syncthreads();
-    // w_c = v^H A[:, c] for the remaining panel columns, one pass over the rows
-    const int nc = k0 + nbp - (j + 1);
-    if (nc > 0) {
-      double2 w[NB];
+    if (tid < NPART) {
+      double2 t = fsum[tid][0];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) w[c] = cz(0.0, 0.0);
-      for (int r = j + tid; r < m; r += PT) {
-        const double2 vr = (r == j) ? cz(1.0, 0.0) : col[r];
+      for (int u = 1; u < 7; ++u) t = cadd(t, fsum[tid][u]);
+      fin[tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double ssum = fin[0].x;
+      const double2 alpha = srow[s];
+      s_alpha = alpha;
+      if (ssum == 0.0 && alpha.y == 0.0) {
+        s_refl = 0;
+        s_tau = cz(0.0, 0.0);
+        s_beta = alpha.x;
+        s_scale = cz(0.0, 0.0);
+      } else {
+        const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + ssum), alpha.x);
+        const double2 den = cz(alpha.x - beta, alpha.y);
+        const double dd = cabs2(den);
+        s_refl = 1;
+        s_tau = cz((beta - alpha.x) / beta, -alpha.y / beta);
+        s_beta = beta;
+        s_scale = cz(den.x / dd, -den.y / dd);
+      }
+      if (blockIdx.x == 0) d.tau[j] = s_tau;
+    }
+    __syncthreads();
+    const double2 scale = s_scale, tau = s_tau, alpha = s_alpha;
+    const int refl = s_refl;
+    if (tid > s && tid < nbp) {
+      // w_c = v^H a_c = a_c(j) + conj(scale) (x^H a_c - conj(alpha) a_c(j))
+      const double2 acj = srow[tid];
+      double2 w = fin[1 + tid];
+      w = csub(w, cmul(cconj(alpha), acj));
+      w = cadd(acj, cmul(cconj(scale), w));
+      sf[tid] = refl ? cmul(cconj(tau), w) : cz(0.0, 0.0);
+    }
+    __syncthreads();
+    double2 xs = cz(0.0, 0.0);   // vals[s] without a run-time index into the array
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < nc) cfmac(w[c], vr, a[(size_t)(j + 1 + c) * lda + r]);
+    for (int c = 0; c < NB; ++c)
+      if (c == s) xs = vals[c];
+    if (live && r >= j) {
+      double2 v;
+      if (r == j) {
+        v = cz(1.0, 0.0);
+        d.a[(size_t)j * d.lda + j] = refl ? cz(s_beta, 0.0) : alpha;
+      } else {
+        v = refl ? cmul(xs, scale) : xs;
+        d.a[(size_t)j * d.lda + r] = v;
       }
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        if (c < nc) {
-          const double2 t = wave_sum(w[c]);
-          if (lane == 0) wred[wv][c] = t;
+        if (c > s && c < nbp) {
+          vals[c] = csub(vals[c], cmul(v, sf[c]));
+          d.a[(size_t)(k0 + c) * d.lda + r] = vals[c];
         }
       }
-      __syncthreads();
-      if (tid < nc) {
-        double2 t = cz(0.0, 0.0);
-        for (int i = 0; i < PT / 64; ++i) t = cadd(t, wred[i][tid]);
-        tmp[tid] = cmul(cconj(s_tau[jj]), t);
-      }
-      __syncthreads();
-      for (int r = j + tid; r < m; r += PT) {
-        const double2 vr = (r == j) ? cz(1.0, 0.0) : col[r];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          if (c < nc) {
-            double2 *p = a + (size_t)(j + 1 + c) * lda + r;
-            *p = csub(*p, cmul(vr, tmp[c]));
-          }
-        }
-      }
-      __syncthreads();
     }
   }
 
-  // Gram matrix of the panel's Householder vectors, G[g][i] = v_g^H v_i, g < i
-  const int npairs = nbp * (nbp - 1) / 2;
-  for (int pidx = wv; pidx < npairs; pidx += PT / 64) {
-    // unrank pidx -> (g, i) with g < i
-    int i = 1, base = 0;
-    while (base + i <= pidx) { base += i; ++i; }
-    const int g = pidx - base;
-    double2 acc = cz(0.0, 0.0);
-    for (int r = k0 + i + lane; r < m; r += 64)
-      cfmac(acc, vload(a, lda, k0, g, r), vload(a, lda, k0, i, r));
-    acc = wave_sum(acc);
-    if (lane == 0) gram[g][i] = acc;
+  // partial sums of step s + 1
+  const int s1 = s + 1;
+  if (s1 >= nbp) return;
+  const int j1 = k0 + s1;
+  double2 x = cz(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (c == s1) x = vals[c];
+  if (!(live && r >= j1)) x = cz(0.0, 0.0);
+  if (live && r == j1) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c >= s1 && c < nbp) sb[(s1 & 1) * NB + c] = vals[c];
+  }
+  double2 *pout = pb + (size_t)(s1 & 1) * nchmax * NPART + (size_t)blockIdx.x * NPART;
+  {
+    double q = (live && r > j1) ? cabs2(x) : 0.0;
+    q = wave_sum(q);
+    if (lane == 0) red[wv][0] = cz(q, 0.0);
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c > s1 && c < nbp) {
+      double2 p = cz(0.0, 0.0);
+      cfmac(p, x, vals[c]);
+      p = wave_sum(p);
+      if (lane == 0) red[wv][1 + c] = p;
+    }
   }
   __syncthreads();
-  // T (forward, columnwise): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i,0:i] G[0:i, i].
-  // Row h of T is only ever written by thread h, so only tmp needs barriers.
+  if (tid < NPART && (tid == 0 || (tid - 1 > s1 && tid - 1 < nbp))) {
+    double2 t = red[0][tid];
+#pragma unroll
+    for (int w = 1; w < CH / 64; ++w) t = cadd(t, red[w][tid]);
+    pout[tid] = t;
+  }
+}
+
+// Y columns: which = 0 -> trailing columns of the matrix after the panel,
+// which = 1 -> columns [0, rank) of d.u.
+__device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, double2 *&B, int &ldb,
+                                int &nb_cols) {
+  if (which == 0) {
+    B = d.a + (size_t)(k0 + nbp) * d.lda;
+    ldb = d.lda;
+    nb_cols = d.n - k0 - nbp;
+  } else {
+    B = d.u;
+    ldb = ldu_of(d);
+    nb_cols = d.rank[0];
+  }
+}
+
+// P[mat][kc][i][c] = sum over rows of slice kc of conj(V[r][i]) Y[r][c],
+// Y = [V | B] (withV) or B.  Thread -> V columns vi + 8k, Y columns yj + 32k2.
+__global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0, int which,
+                                                      int withV, double2 *__restrict__ P, int ldp, int nkcmax) {
+  const MatDesc d = descs[blockIdx.z];
+  if (k0 >= d.n) return;
+  const int nbp = min(NB, d.n - k0);
+  double2 *B;
+  int ldb, nb_cols;
+  y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  const int nv = withV ? NB : 0;
+  const int ny = nv + max(nb_cols, 0);
+  const int c0 = blockIdx.x * YT;
+  if (c0 >= ny) return;
+  const int rbeg = k0 + blockIdx.y * KR;
+  if (rbeg >= d.m) return;
+  const int rend = min(d.m, rbeg + KR);
+  __shared__ double2 Vs[KS][NB + 1];
+  __shared__ double2 Ys[KS][YT + 1];
+  const int tid = threadIdx.x;
+  const int vi = tid & 7, yj = tid >> 3;
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
+  for (int r0 = rbeg; r0 < rend; r0 += KS) {
+    double2 vv[KS * NB / 256], yy[KS * YT / 256];
+#pragma unroll
+    for (int u = 0; u < KS * NB / 256; ++u) {
+      const int idx = tid + 256 * u, rr = idx % KS, i = idx / KS;
+      const int r = r0 + rr;
+      vv[u] = csel(r < rend, vel(d, k0, i, r), cz(0.0, 0.0));
+    }
+#pragma unroll
+    for (int u = 0; u < KS * YT / 256; ++u) {
+      const int idx = tid + 256 * u, rr = idx % KS, cc = idx / KS;
+      const int r = r0 + rr, c = c0 + cc;
+      const double2 yv = vel(d, k0, c < nv ? c : 0, r);
+      const double2 yb = ld_or0(B, (size_t)(c - nv) * ldb + r, r < rend && c >= nv && c < ny);
+      yy[u] = csel(r < rend && c < nv, yv, yb);
+    }
+#pragma unroll
+    for (int u = 0; u < KS * NB / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Vs[idx % KS][idx / KS] = vv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < KS * YT / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Ys[idx % KS][idx / KS] = yy[u];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < KS; ++rr) {
+      double2 v[4], y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[k] = Vs[rr][vi + 8 * k];
+        y[k] = Ys[rr][yj + 32 * k];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cfmac(acc[a][b], v[a], y[b]);
+    }
+    __syncthreads();
+  }
+  double2 *out = P + ((size_t)blockIdx.z * nkcmax + blockIdx.y) * NB * ldp;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = c0 + yj + 32 * b;
+      if (c < ny) out[(size_t)(vi + 8 * a) * ldp + c] = acc[a][b];
+    }
+}
+
+// T of the panel (forward, columnwise): T[i][i] = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] (V^H V)[0:i, i]; V^H V from the slices of P.
+__global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ descs, int k0,
+                                                    const double2 *__restrict__ P, int ldp, int nkcmax) {
+  const MatDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  const int nbp = min(NB, d.n - k0);
+  const int nkc = (d.m - k0 + KR - 1) / KR;
+  const int tid = threadIdx.x;
+  __shared__ double2 gram[NB][NB + 1];
   __shared__ double2 Tsh[NB][NB + 1];
+  __shared__ double2 tmp[NB];
+  const double2 *base = P + (size_t)blockIdx.x * nkcmax * NB * ldp;
+  {
+    double2 t[NB * NB / 256];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) t[u] = cz(0.0, 0.0);
+    for (int kc = 0; kc < nkc; ++kc) {
+#pragma unroll
+      for (int u = 0; u < NB * NB / 256; ++u) {
+        const int idx = tid + 256 * u, g = idx % NB, i = idx / NB;
+        t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + g) * ldp + i, g < i && i < nbp));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int idx = tid + 256 * u;
+      gram[idx % NB][idx / NB] = t[u];
+    }
+  }
+  __syncthreads();
   for (int i = 0; i < nbp; ++i) {
-    const double2 ti = s_tau[i];
+    const double2 ti = d.tau[k0 + i];
     if (tid < i) tmp[tid] = cmul(cz(-ti.x, -ti.y), gram[tid][i]);
     __syncthreads();
     if (tid < i) {
@@ -152,137 +325,222 @@ __global__ __launch_bounds__(PT) void qr_panel_kernel(const MatDesc *__restrict_
     __syncthreads();
   }
   double2 *T = d.T + (size_t)(k0 / NB) * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += PT) {
+  for (int idx = tid; idx < NB * NB; idx += 256) {
     const int r = idx % NB, c = idx / NB;
     T[idx] = (r <= c && c < nbp) ? Tsh[r][c] : cz(0.0, 0.0);
   }
 }
 
-// which = 0: B = the matrix itself, columns [k0 + nbp, n), trans = 1 (QR);
-// which = 1: B = d.u, columns [0, rank), trans = 0 (form Q [U_R; 0]).
-__global__ __launch_bounds__(256) void qr_block_apply_kernel(const MatDesc *__restrict__ descs,
-                                                             int k0, int trans, int which) {
-  const MatDesc d = descs[blockIdx.x];
+// W2[mat][i][c] = sum_h op(T)[i][h] W[h][c], W = V^H B summed over the slices;
+// op(T) = T^H (trans, QR) or T.
+__global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__ descs, int k0, int which,
+                                                     int withV, int trans, const double2 *__restrict__ P,
+                                                     int ldp, int nkcmax, double2 *__restrict__ W2,
+                                                     int ldw) {
+  const MatDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
-  const int m = d.m;
   double2 *B;
-  int ldb, cbeg, cend;
-  if (which == 0) {
-    B = d.a; ldb = d.lda; cbeg = k0 + nbp; cend = d.n;
-  } else {
-    B = d.u; ldb = d.lda; cbeg = 0; cend = d.rank[0];
-  }
-  const int c0 = cbeg + blockIdx.y * TC;
-  if (c0 >= cend) return;
-  const int ncol = min(TC, cend - c0);
-
-  __shared__ double2 Vs[RC][NB + 1];
-  __shared__ double2 Bs[RC][TC + 1];
-  __shared__ double2 Ws[NB][TC + 1];
+  int ldb, nb_cols;
+  y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  const int c0 = blockIdx.x * WT;
+  if (c0 >= nb_cols) return;
+  const int nv = withV ? NB : 0;
+  const int nkc = (d.m - k0 + KR - 1) / KR;
   __shared__ double2 Ts[NB][NB + 1];
+  __shared__ double2 Ws[NB][WT + 1];
   const int tid = threadIdx.x;
-  const double2 *a = d.a;
-  const int lda = d.lda;
-
-  // pass 1: Ws = V^H B
-  const int pi = tid >> 3, pc = tid & 7;
-  double2 acc0 = cz(0.0, 0.0), acc1 = cz(0.0, 0.0);
-  for (int r0 = k0; r0 < m; r0 += RC) {
-    for (int idx = tid; idx < RC * NB; idx += 256) {
-      const int rr = idx % RC, i = idx / RC;
-      const int r = r0 + rr;
-      Vs[rr][i] = (r < m && i < nbp) ? vload(a, lda, k0, i, r) : cz(0.0, 0.0);
-    }
-    for (int idx = tid; idx < RC * TC; idx += 256) {
-      const int rr = idx % RC, c = idx / RC;
-      const int r = r0 + rr;
-      Bs[rr][c] = (r < m && c < ncol) ? B[(size_t)(c0 + c) * ldb + r] : cz(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < RC; ++rr) {
-      const double2 v = Vs[rr][pi];
-      cfmac(acc0, v, Bs[rr][pc]);
-      cfmac(acc1, v, Bs[rr][pc + 8]);
-    }
-    __syncthreads();
-  }
-  Ws[pi][pc] = acc0;
-  Ws[pi][pc + 8] = acc1;
   const double2 *T = d.T + (size_t)(k0 / NB) * NB * NB;
   for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = T[idx];
-  __syncthreads();
-  // W2 = op(T) Ws, op(T) = T^H (trans) or T; T upper triangular
-  double2 w0 = cz(0.0, 0.0), w1 = cz(0.0, 0.0);
-  if (trans) {
-    for (int h = 0; h <= pi; ++h) {
-      cfmac(w0, Ts[h][pi], Ws[h][pc]);
-      cfmac(w1, Ts[h][pi], Ws[h][pc + 8]);
-    }
-  } else {
-    for (int h = pi; h < NB; ++h) {
-      cfma(w0, Ts[pi][h], Ws[h][pc]);
-      cfma(w1, Ts[pi][h], Ws[h][pc + 8]);
-    }
-  }
-  __syncthreads();
-  Ws[pi][pc] = w0;
-  Ws[pi][pc + 8] = w1;
-  __syncthreads();
-
-  // pass 2: B -= V W2
-  const int ur = tid & 63, ucg = tid >> 6;
-  for (int r0 = k0; r0 < m; r0 += RC) {
-    for (int idx = tid; idx < RC * NB; idx += 256) {
-      const int rr = idx % RC, i = idx / RC;
-      const int r = r0 + rr;
-      Vs[rr][i] = (r < m && i < nbp) ? vload(a, lda, k0, i, r) : cz(0.0, 0.0);
-    }
-    __syncthreads();
-    const int r = r0 + ur;
-    if (r < m) {
-      for (int c = ucg; c < ncol; c += 4) {
-        double2 acc = cz(0.0, 0.0);
-#pragma unroll 8
-        for (int i = 0; i < NB; ++i) cfma(acc, Vs[ur][i], Ws[i][c]);
-        double2 *p = B + (size_t)(c0 + c) * ldb + r;
-        *p = csub(*p, acc);
+  const double2 *base = P + (size_t)blockIdx.y * nkcmax * NB * ldp;
+  {
+    double2 t[NB * WT / 256];
+#pragma unroll
+    for (int u = 0; u < NB * WT / 256; ++u) t[u] = cz(0.0, 0.0);
+    for (int kc = 0; kc < nkc; ++kc) {
+#pragma unroll
+      for (int u = 0; u < NB * WT / 256; ++u) {
+        const int idx = tid + 256 * u, cc = idx % WT, i = idx / WT;
+        t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + i) * ldp + nv + c0 + cc, c0 + cc < nb_cols));
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB * WT / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Ws[idx / WT][idx % WT] = t[u];
+    }
   }
+  __syncthreads();
+  double2 *out = W2 + (size_t)blockIdx.y * NB * ldw;
+  for (int idx = tid; idx < NB * WT; idx += 256) {
+    const int cc = idx % WT, i = idx / WT;
+    const int c = c0 + cc;
+    if (c >= nb_cols) continue;
+    double2 acc = cz(0.0, 0.0);
+    if (trans) {
+      for (int h = 0; h <= i; ++h) cfmac(acc, Ts[h][i], Ws[h][cc]);
+    } else {
+      for (int h = i; h < NB; ++h) cfma(acc, Ts[i][h], Ws[h][cc]);
+    }
+    out[(size_t)i * ldw + c] = acc;
+  }
+}
+
+// B[r][c] -= sum_i V[r][i] W2[i][c], rows r >= k0; thread -> rows tx + 16a,
+// columns ty + 16b of a 64 x 64 tile.
+__global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restrict__ descs, int k0, int which,
+                                                         const double2 *__restrict__ W2, int ldw) {
+  const MatDesc d = descs[blockIdx.z];
+  if (k0 >= d.n) return;
+  const int nbp = min(NB, d.n - k0);
+  double2 *B;
+  int ldb, nb_cols;
+  y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  const int c0 = blockIdx.y * WT;
+  if (c0 >= nb_cols) return;
+  const int r0 = k0 + blockIdx.x * UR;
+  if (r0 >= d.m) return;
+  __shared__ double2 Vs[UR][NB + 1];
+  __shared__ double2 Ws[NB][WT + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  // the tile of B is fetched first, its latency hidden behind the product
+  double2 cv[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int c = c0 + ty + 16 * b, r = r0 + tx + 16 * a;
+      cv[a][b] = ld_or0(B, (size_t)c * ldb + r, c < nb_cols && r < d.m);
+    }
+  {
+    double2 vv[UR * NB / 256], ww[NB * WT / 256];
+    const double2 *w = W2 + (size_t)blockIdx.z * NB * ldw;
+#pragma unroll
+    for (int u = 0; u < UR * NB / 256; ++u) {
+      const int idx = tid + 256 * u, rr = idx % UR, i = idx / UR;
+      vv[u] = vel(d, k0, i, r0 + rr);   // zero for rows >= m
+    }
+#pragma unroll
+    for (int u = 0; u < NB * WT / 256; ++u) {
+      const int idx = tid + 256 * u, cc = idx % WT, i = idx / WT;
+      ww[u] = ld_or0(w, (size_t)i * ldw + c0 + cc, c0 + cc < nb_cols);
+    }
+#pragma unroll
+    for (int u = 0; u < UR * NB / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Vs[idx % UR][idx / UR] = vv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB * WT / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Ws[idx / WT][idx % WT] = ww[u];
+    }
+  }
+  __syncthreads();
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
+#pragma unroll 4
+  for (int i = 0; i < NB; ++i) {
+    double2 v[4], x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = Vs[tx + 16 * k][i];
+      x[k] = Ws[i][ty + 16 * k];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cfma(acc[a][b], v[a], x[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = c0 + ty + 16 * b;
+    if (c >= nb_cols) continue;
+    double2 *col = B + (size_t)c * ldb;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = r0 + tx + 16 * a;
+      if (r < d.m) col[r] = csub(cv[a][b], acc[a][b]);
+    }
+  }
+}
+
+struct ApplyWork {
+  DevBuf P, W2;
+  int ldp = 0, ldw = 0, nkcmax = 0;
+  void size(int nmat, int mmax, int ncols) {
+    ldp = NB + ncols;
+    ldw = std::max(ncols, 1);
+    nkcmax = cdiv(std::max(mmax, 1), KR);
+    P.alloc((size_t)nmat * nkcmax * NB * ldp * sizeof(double2));
+    W2.alloc((size_t)nmat * NB * ldw * sizeof(double2));
+  }
+};
+
+// C <- (I - V T V^H)^{op} C for the panel at k0 (which/withV/trans as above)
+void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0, int which, int withV,
+                 int trans, ApplyWork &w, bool build_t, hipStream_t s) {
+  const int ny = (withV ? NB : 0) + ncols_max;
+  const int nkc = cdiv(std::max(mmax - k0, 1), KR);
+  if (ny > 0)
+    hipLaunchKernelGGL(bqr_vhy_kernel, dim3(cdiv(ny, YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
+                       w.P.as<double2>(), w.ldp, w.nkcmax);
+  if (build_t)
+    hipLaunchKernelGGL(bqr_t_kernel, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
+                       w.nkcmax);
+  if (ncols_max > 0) {
+    hipLaunchKernelGGL(bqr_w2_kernel, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
+                       withV, trans, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw);
+    hipLaunchKernelGGL(bqr_update_kernel, dim3(cdiv(std::max(mmax - k0, 1), UR), cdiv(ncols_max, WT), nmat),
+                       dim3(256), 0, s, descs, k0, which, w.W2.as<double2>(), w.ldw);
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace
 
 void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
-  int nmax = 0;
-  for (const auto &d : h) nmax = std::max(nmax, d.n);
+  int nmax = 0, mmax = 0;
+  for (const auto &d : h) {
+    nmax = std::max(nmax, d.n);
+    mmax = std::max(mmax, d.m);
+  }
   const int nmat = (int)h.size();
+  if (nmax == 0 || nmat == 0) return;
+  const int nchmax = cdiv(mmax, CH);
+  DevBuf part((size_t)nmat * 2 * nchmax * NPART * sizeof(double2));
+  DevBuf side((size_t)nmat * 2 * NB * sizeof(double2));
+  ApplyWork w;
+  w.size(nmat, mmax, nmax);
   for (int k0 = 0; k0 < nmax; k0 += NB) {
-    hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(PT), 0, s, descs, k0);
+    const int nch = cdiv(std::max(mmax - k0, 1), CH);
+    const int nbp = std::min(NB, nmax - k0);
+    for (int st = -1; st < nbp; ++st)
+      hipLaunchKernelGGL(bqr_col_kernel, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st, part.as<double2>(),
+                         side.as<double2>(), nchmax);
     HIP_CHECK(hipGetLastError());
-    const int trail = nmax - k0 - NB;
-    if (trail > 0) {
-      hipLaunchKernelGGL(qr_block_apply_kernel, dim3(nmat, cdiv(trail, TC)), dim3(256), 0, s,
-                         descs, k0, 1, 0);
-      HIP_CHECK(hipGetLastError());
-    }
+    apply_panel(descs, nmat, mmax, std::max(0, nmax - k0 - NB), k0, 0, 1, 1, w, true, s);
   }
 }
 
-// Form U = Q [U_R; 0] in place in d.u (rows >= n of d.u must be zero).
+// Form U = Q [U_R; 0] in place in d.u (leading dimension d.ldu, or d.lda if
+// zero); rows >= n of d.u must be zero.  T of every panel must be present.
 void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s) {
-  int nmax = 0;
-  for (const auto &d : h) nmax = std::max(nmax, d.n);
-  const int nmat = (int)h.size();
-  if (maxrank <= 0) return;
-  for (int k0 = ((nmax - 1) / NB) * NB; k0 >= 0; k0 -= NB) {
-    hipLaunchKernelGGL(qr_block_apply_kernel, dim3(nmat, cdiv(maxrank, TC)), dim3(256), 0, s,
-                       descs, k0, 0, 1);
-    HIP_CHECK(hipGetLastError());
+  int nmax = 0, mmax = 0;
+  for (const auto &d : h) {
+    nmax = std::max(nmax, d.n);
+    mmax = std::max(mmax, d.m);
   }
+  const int nmat = (int)h.size();
+  if (maxrank <= 0 || nmax == 0) return;
+  ApplyWork w;
+  w.size(nmat, mmax, maxrank);
+  for (int k0 = ((nmax - 1) / NB) * NB; k0 >= 0; k0 -= NB)
+    apply_panel(descs, nmat, mmax, maxrank, k0, 1, 0, 0, w, false, s);
 }
 
 }  // namespace mfs
