@@ -12,14 +12,19 @@
 //
 // Blocked form for the GPU: the columns are cut into blocks of 16 and the
 // round-robin (circle) schedule pairs the blocks, n_b - 1 rounds per sweep.
-// One workgroup per block pair (32 columns):
-//   1. H = G_IJ^H G_IJ (32 x 32), every entry a dot product of two columns
-//      accumulated from 64-row chunks staged in LDS;
-//   2. one Jacobi sweep over the 32 columns carried out on H in LDS (the
+// A task is a block pair (32 columns); a round is three launches over all
+// tasks of all matrices:
+//   1. jac_gram_kernel: partial H = G_IJ^H G_IJ (32 x 32) over 128-row
+//      tiles, every entry a dot product of two columns, staged through LDS;
+//   2. jac_inner_kernel (one workgroup per task): H summed over the tiles,
+//      one Jacobi sweep over the 32 columns carried out on H in LDS (the
 //      two-sided update H <- R^H H R of each rotation R, with the exact
 //      diagonal formulas above and the annihilated entry set to zero), the
 //      product J of the rotations accumulated alongside;
-//   3. if any pair rotated, G_IJ <- G_IJ J and V_IJ <- V_IJ J.
+//   3. jac_apply_kernel: if any pair of the task rotated, G_IJ <- G_IJ J and
+//      V_IJ <- V_IJ J over 64-row tiles.
+// The row tiles spread every round over the whole chip whatever the number
+// of tasks, and the apply streams G and V once per round.
 // Every pair of columns meets in some workgroup every sweep, pairs inside a
 // block in every task of that block; sweeps repeat until no pair of a matrix
 // needed a rotation (|gamma| <= tol sqrt(a b)), a matrix that converged
@@ -73,66 +78,64 @@ __device__ inline void circle_pair(int np, int round, int pair, int &p, int &q) 
   }
 }
 
-// One round of the blocked sweep: blockIdx.x = block pair, blockIdx.y = matrix.
-// flag[mat] counts the tasks that rotated; act[mat] == 0 skips the matrix.
-__global__ __launch_bounds__(256) void jac_block_kernel(const MatDesc *__restrict__ descs,
-                                                        const int *__restrict__ act, int round,
-                                                        double tol) {
-  const int mat = blockIdx.y;
+constexpr int GT = 128;   // rows per workgroup of the partial Gram matrices
+constexpr int AT = 64;    // rows per workgroup of the rotation apply
+
+// Blocks (bi, bj) of block pair `pair` of matrix d in this round; false if
+// the pair is out of range or both blocks are padding.
+__device__ inline bool task_blocks(const MatDesc &d, int round, int pair, int &bi, int &bj, int &nb) {
+  nb = (d.n + JB - 1) / JB;
+  const int nbp = nb + (nb & 1);
+  if (pair >= nbp / 2) return false;
+  circle_pair(nbp, round, pair, bi, bj);
+  return bi < nb || bj < nb;
+}
+// column of local index a of the task (-1: past n or in the padding block)
+__device__ inline int task_col(int a, int bi, int bj, int nb, int n) {
+  const int blk = a < JB ? bi : bj;
+  const int c = blk * JB + (a & (JB - 1));
+  return (blk < nb && c < n) ? c : -1;
+}
+
+// 1. partial Gram matrices: hpart[mat][pair][tile] = G_IJ(rows of tile)^H G_IJ(rows of tile)
+//    lane (ti, tj) -> entries H[ti + 8k][tj + 8k2]; wave -> rows wv, wv + 4, ... of a 64-row chunk
+__global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict__ descs,
+                                                       const int *__restrict__ act, int round,
+                                                       double2 *__restrict__ hpart, int npair_max,
+                                                       int ntile_max) {
+  const int mat = blockIdx.z;
   if (!act[mat]) return;
   const MatDesc d = descs[mat];
   const int n = d.n;
-  const int nb = (n + JB - 1) / JB;
-  const int nbp = nb + (nb & 1);
-  if ((int)blockIdx.x >= nbp / 2) return;
-  int bi, bj;
-  circle_pair(nbp, round, blockIdx.x, bi, bj);
-  if (bi >= nb && bj >= nb) return;
-
-  __shared__ double2 Gs[JR][JC + 1];   // chunk, row-major: lanes on rows or on columns read conflict-free
-  __shared__ double2 Hs[JC][JC + 1];
-  __shared__ double2 Js[JC][JC + 1];
+  const int rbeg = blockIdx.x * GT;
+  if (rbeg >= n) return;
   __shared__ int colx[JC];
-  __shared__ double r_c[JB], r_tg[JB], r_a[JB], r_b[JB];
-  __shared__ double2 r_se[JB];
-  __shared__ int r_act[JB];
-  __shared__ int s_nrot;
+  __shared__ double2 Gs[JR][JC + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < JC) {
-    const int blk = tid < JB ? bi : bj;
-    const int c = blk * JB + (tid & (JB - 1));
-    colx[tid] = (blk < nb && c < n) ? c : -1;
+  {
+    int bi, bj, nb;
+    if (!task_blocks(d, round, blockIdx.y, bi, bj, nb)) return;
+    if (tid < JC) colx[tid] = task_col(tid, bi, bj, nb, n);
   }
-  if (tid == 0) s_nrot = 0;
   __syncthreads();
-
-  // 1. Gram matrix: lane (ti, tj) -> entries H[ti + 8k][tj + 8k2], k, k2 < 4; wave -> rows wv, wv+4, ...
   const int ti = lane >> 3, tj = lane & 7;
   double2 acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = cz(0.0, 0.0);
-  // chunk loads go through registers one chunk ahead of the LDS copy in use
-  constexpr int PER = JC * JR / 256;   // elements per thread and chunk
-  double2 pre[PER];
-  auto fetch = [&](const double2 *M, int r0) {
+  const int rend = min(n, rbeg + GT);
+  for (int r0 = rbeg; r0 < rend; r0 += JR) {
+    double2 pre[JC * JR / 256];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < JC * JR / 256; ++i) {
       const int a = wv + 4 * i, r = r0 + lane;
       const int c = colx[a];
-      pre[i] = (c >= 0 && r < n) ? M[(size_t)c * d.ldg + r] : cz(0.0, 0.0);
+      pre[i] = ld_or0(d.g, (size_t)(c < 0 ? 0 : c) * d.ldg + r, c >= 0 && r < rend);
     }
-  };
-  auto stash = [&]() {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) Gs[lane][wv + 4 * i] = pre[i];
-  };
-  fetch(d.g, 0);
-  for (int r0 = 0; r0 < n; r0 += JR) {
-    stash();
+    for (int i = 0; i < JC * JR / 256; ++i) Gs[lane][wv + 4 * i] = pre[i];
     __syncthreads();
-    if (r0 + JR < n) fetch(d.g, r0 + JR);
     for (int rr = wv; rr < JR; rr += 4) {
       double2 x[4], y[4];
 #pragma unroll
@@ -147,41 +150,86 @@ __global__ __launch_bounds__(256) void jac_block_kernel(const MatDesc *__restric
     }
     __syncthreads();
   }
+  // sum the four waves in LDS (Gs reused as a 32 x 33 array)
   for (int w = 0; w < 4; ++w) {
     if (wv == w) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2) {
-          double2 &h = Hs[ti + 8 * k][tj + 8 * k2];
+          double2 &h = Gs[ti + 8 * k][tj + 8 * k2];
           h = (w == 0) ? acc[k][k2] : cadd(h, acc[k][k2]);
         }
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < JC * JC; idx += 256) {
-    const int r = idx % JC, c = idx / JC;
-    Js[r][c] = cz(r == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
+  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
+  for (int idx = tid; idx < JC * JC; idx += 256) out[idx] = Gs[idx / JC][idx % JC];
+}
 
-  // 2. one sweep over the 32 columns on H
+// 2. one workgroup per task: H = sum of the partials, one Jacobi sweep over
+//    its 32 columns on H, J = product of the rotations -> jbuf, rot = any rotation
+__global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restrict__ descs,
+                                                        const int *__restrict__ act, int round, double tol,
+                                                        const double2 *__restrict__ hpart,
+                                                        double2 *__restrict__ jbuf, int *__restrict__ rot,
+                                                        int npair_max, int ntile_max) {
+  const int mat = blockIdx.y;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int pair = blockIdx.x;
+  {
+    int bi, bj, nb;
+    if (!task_blocks(d, round, pair, bi, bj, nb)) return;
+  }
+  __shared__ double2 Hs[JC][JC + 1];
+  __shared__ double2 Js[JC][JC + 1];
+  __shared__ double r_c[JB], r_tg[JB], r_a[JB], r_b[JB];
+  __shared__ double2 r_se[JB];
+  __shared__ int r_act[JB];
+  __shared__ int s_nrot;
+  const int tid = threadIdx.x;
+  const int ntile = (d.n + GT - 1) / GT;
+  const double2 *hp = hpart + ((size_t)mat * npair_max + pair) * ntile_max * JC * JC;
+  {
+    double2 h[JC * JC / 256];
+#pragma unroll
+    for (int u = 0; u < JC * JC / 256; ++u) h[u] = cz(0.0, 0.0);
+    for (int t = 0; t < ntile; ++t) {
+#pragma unroll
+      for (int u = 0; u < JC * JC / 256; ++u) h[u] = cadd(h[u], hp[(size_t)t * JC * JC + tid + 256 * u]);
+    }
+#pragma unroll
+    for (int u = 0; u < JC * JC / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Hs[idx / JC][idx % JC] = h[u];
+      Js[idx / JC][idx % JC] = cz(idx / JC == idx % JC ? 1.0 : 0.0, 0.0);
+    }
+  }
+  if (tid == 0) s_nrot = 0;
+  __syncthreads();
+  // one sweep over the 32 columns on H.  Rotation of pair (p, q) from
+  // a = H_pp, b = H_qq, gamma = H_pq, d = b - a:
+  //   q' = 2 sign(d) / (|d| + sqrt(d^2 + 4 |gamma|^2)),  t = q' |gamma|,
+  //   c = 1 / sqrt(1 + t^2),  s e^{i th} = c q' gamma,  t |gamma| = q' |gamma|^2
+  // (the formulas of the header with zeta = d / (2 |gamma|), |gamma| never formed).
+  // H <- R^H H R acts on every 2 x 2 block (rows of pair i, columns of pair j)
+  // on its own: one thread per block, J <- J R alongside.
   for (int rnd = 0; rnd < JC - 1; ++rnd) {
     if (tid < JB) {
       int p, q;
       circle_pair(JC, rnd, tid, p, q);
       const double a = Hs[p][p].x, b = Hs[q][q].x;
       const double2 gam = Hs[p][q];
-      const double ag = sqrt(cabs2(gam));
-      int on = ag > tol * sqrt(a) * sqrt(b);
+      const double g2 = cabs2(gam);
+      const int on = g2 > tol * tol * a * b;
       if (on) {
-        const double zeta = (b - a) / (2.0 * ag);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
+        const double dd = b - a;
+        const double qq = copysign(2.0, dd) / (fabs(dd) + sqrt(fma(dd, dd, 4.0 * g2)));
+        const double cs = rsqrt(fma(qq * qq, g2, 1.0));
         r_c[tid] = cs;
-        r_se[tid] = cz(sn * gam.x / ag, sn * gam.y / ag);
-        r_tg[tid] = t * ag;
+        r_se[tid] = cz(cs * qq * gam.x, cs * qq * gam.y);
+        r_tg[tid] = qq * g2;
         r_a[tid] = a;
         r_b[tid] = b;
       }
@@ -197,77 +245,143 @@ __global__ __launch_bounds__(256) void jac_block_kernel(const MatDesc *__restric
         for (int i = 0; i < JB; ++i) cnt += r_act[i];
         s_nrot += cnt;
       }
-      // columns p, q of H and J: X <- X R
-      for (int item = tid; item < 2 * JB * JC; item += 256) {
-        const int which = item / (JB * JC), rem = item % (JB * JC);
-        const int pr = rem / JC, k = rem % JC;
-        if (!r_act[pr]) continue;
-        int p, q;
-        circle_pair(JC, rnd, pr, p, q);
-        double2(*M)[JC + 1] = which ? Js : Hs;
-        const double2 x = M[k][p], y = M[k][q];
-        const double cs = r_c[pr];
-        const double2 se = r_se[pr], sec = cconj(r_se[pr]);
-        M[k][p] = csub(cscale(x, cs), cmul(sec, y));
-        M[k][q] = cadd(cmul(se, x), cscale(y, cs));
-      }
-      __syncthreads();
-      // rows p, q of H: H <- R^H H; the 2x2 pivot block takes its exact values
-      for (int item = tid; item < JB * JC; item += 256) {
-        const int pr = item / JC, k = item % JC;
-        if (!r_act[pr]) continue;
-        int p, q;
-        circle_pair(JC, rnd, pr, p, q);
-        if (k == p) {
-          Hs[p][p] = cz(r_a[pr] - r_tg[pr], 0.0);
-          Hs[q][p] = cz(0.0, 0.0);
-        } else if (k == q) {
-          Hs[p][q] = cz(0.0, 0.0);
-          Hs[q][q] = cz(r_b[pr] + r_tg[pr], 0.0);
-        } else {
-          const double2 x = Hs[p][k], y = Hs[q][k];
-          const double cs = r_c[pr];
-          const double2 se = r_se[pr], sec = cconj(r_se[pr]);
-          Hs[p][k] = csub(cscale(x, cs), cmul(se, y));
-          Hs[q][k] = cadd(cmul(sec, x), cscale(y, cs));
+      {
+        // H block (pair i rows, pair j columns)
+        const int bi = tid >> 4, bj = tid & 15;
+        int p, q, u, v;
+        circle_pair(JC, rnd, bi, p, q);
+        circle_pair(JC, rnd, bj, u, v);
+        const int ai = r_act[bi], aj = r_act[bj];
+        if (ai || aj) {
+          double2 h_pu = Hs[p][u], h_pv = Hs[p][v], h_qu = Hs[q][u], h_qv = Hs[q][v];
+          if (bi == bj) {
+            // pivot block: exact values
+            h_pu = cz(r_a[bi] - r_tg[bi], 0.0);
+            h_qv = cz(r_b[bi] + r_tg[bi], 0.0);
+            h_pv = cz(0.0, 0.0);
+            h_qu = cz(0.0, 0.0);
+          } else {
+            if (aj) {   // columns: [x_u, x_v] <- [c x_u - conj(se) x_v, se x_u + c x_v]
+              const double cs = r_c[bj];
+              const double2 se = r_se[bj], sec = cconj(r_se[bj]);
+              const double2 pu = csub(cscale(h_pu, cs), cmul(sec, h_pv));
+              const double2 pv = cadd(cmul(se, h_pu), cscale(h_pv, cs));
+              const double2 qu = csub(cscale(h_qu, cs), cmul(sec, h_qv));
+              const double2 qv = cadd(cmul(se, h_qu), cscale(h_qv, cs));
+              h_pu = pu; h_pv = pv; h_qu = qu; h_qv = qv;
+            }
+            if (ai) {   // rows: [y_p; y_q] <- [c y_p - se y_q; conj(se) y_p + c y_q]
+              const double cs = r_c[bi];
+              const double2 se = r_se[bi], sec = cconj(r_se[bi]);
+              const double2 pu = csub(cscale(h_pu, cs), cmul(se, h_qu));
+              const double2 qu = cadd(cmul(sec, h_pu), cscale(h_qu, cs));
+              const double2 pv = csub(cscale(h_pv, cs), cmul(se, h_qv));
+              const double2 qv = cadd(cmul(sec, h_pv), cscale(h_qv, cs));
+              h_pu = pu; h_pv = pv; h_qu = qu; h_qv = qv;
+            }
+          }
+          Hs[p][u] = h_pu; Hs[p][v] = h_pv; Hs[q][u] = h_qu; Hs[q][v] = h_qv;
+        }
+        // J columns of pair bj, rows 2 (tid >> 4) and 2 (tid >> 4) + 1
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int k = 2 * bi + e;
+          if (aj) {
+            const double cs = r_c[bj];
+            const double2 se = r_se[bj], sec = cconj(r_se[bj]);
+            const double2 x = Js[k][u], y = Js[k][v];
+            Js[k][u] = csub(cscale(x, cs), cmul(sec, y));
+            Js[k][v] = cadd(cmul(se, x), cscale(y, cs));
+          }
         }
       }
     }
-    __syncthreads();   // flags of this round are read by all before the next round writes them
+    __syncthreads();   // H, J and the flags of this round settled before the next
   }
-  if (s_nrot == 0) return;
-  if (tid == 0) atomicAdd(d.flag, 1);
+  double2 *jo = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
+  for (int idx = tid; idx < JC * JC; idx += 256) jo[idx] = Js[idx / JC][idx % JC];
+  if (tid == 0) {
+    rot[(size_t)mat * npair_max + pair] = s_nrot > 0;
+    if (s_nrot > 0) atomicAdd(d.flag, 1);
+  }
+}
 
-  // 3. G_IJ <- G_IJ J and V_IJ <- V_IJ J; thread -> rows (rp, rp + 32), columns 4 cq .. 4 cq + 3
-  const int rp = tid & 31, cq = tid >> 5;
-  const int nch = (n + JR - 1) / JR;
-  fetch(d.g, 0);
-  for (int v = 0; v < 2 * nch; ++v) {
-    double2 *M = v < nch ? d.g : d.v;
-    const int r0 = (v % nch) * JR;
-    __syncthreads();   // the previous chunk's readers are done with Gs
-    stash();
-    __syncthreads();
-    if (v + 1 < 2 * nch) fetch(v + 1 < nch ? d.g : d.v, ((v + 1) % nch) * JR);
-    double2 o0[4], o1[4];
+// 3. G_IJ <- G_IJ J and V_IJ <- V_IJ J on 64-row tiles (tiles [0, nt) of G,
+//    [nt, 2 nt) of V); thread -> rows tx + 16a, columns 4 cq + b
+__global__ __launch_bounds__(128) void jac_apply_kernel(const MatDesc *__restrict__ descs,
+                                                        const int *__restrict__ act, int round,
+                                                        const double2 *__restrict__ jbuf,
+                                                        const int *__restrict__ rot, int npair_max) {
+  const int mat = blockIdx.z;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int n = d.n;
+  const int pair = blockIdx.y;
+  const int nt = (n + AT - 1) / AT;
+  if ((int)blockIdx.x >= 2 * nt) return;
+  __shared__ int colx[JC];
+  __shared__ double2 Gs[AT][JC + 1];
+  __shared__ double2 Js[JC][JC + 1];
+  const int tid = threadIdx.x;
+  {
+    int bi, bj, nb;
+    if (!task_blocks(d, round, pair, bi, bj, nb)) return;
+    if (!rot[(size_t)mat * npair_max + pair]) return;
+    if (tid < JC) colx[tid] = task_col(tid, bi, bj, nb, n);
+  }
+  double2 *M = (int)blockIdx.x < nt ? d.g : d.v;
+  const int r0 = ((int)blockIdx.x % nt) * AT;
+  const double2 *ji = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
+  __syncthreads();
+  {
+    double2 pre[AT * JC / 128], jj[JC * JC / 128];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) { o0[j] = cz(0.0, 0.0); o1[j] = cz(0.0, 0.0); }
-#pragma unroll 4
-    for (int a = 0; a < JC; ++a) {
-      const double2 x0 = Gs[rp][a], x1 = Gs[rp + 32][a];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double2 jj = Js[a][4 * cq + j];
-        cfma(o0[j], x0, jj);
-        cfma(o1[j], x1, jj);
-      }
+    for (int u = 0; u < AT * JC / 128; ++u) {
+      const int idx = tid + 128 * u, a = idx / AT, rr = idx % AT;
+      const int c = colx[a], r = r0 + rr;
+      pre[u] = ld_or0(M, (size_t)(c < 0 ? 0 : c) * d.ldg + r, c >= 0 && r < n);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = colx[4 * cq + j];
-      if (c < 0) continue;
-      if (r0 + rp < n) M[(size_t)c * d.ldg + r0 + rp] = o0[j];
-      if (r0 + rp + 32 < n) M[(size_t)c * d.ldg + r0 + rp + 32] = o1[j];
+    for (int u = 0; u < JC * JC / 128; ++u) jj[u] = ji[tid + 128 * u];
+#pragma unroll
+    for (int u = 0; u < AT * JC / 128; ++u) {
+      const int idx = tid + 128 * u;
+      Gs[idx % AT][idx / AT] = pre[u];
+    }
+#pragma unroll
+    for (int u = 0; u < JC * JC / 128; ++u) {
+      const int idx = tid + 128 * u;
+      Js[idx / JC][idx % JC] = jj[u];
+    }
+  }
+  __syncthreads();
+  const int tx = tid & 15, cq = tid >> 4;
+  double2 o[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) o[x][y] = cz(0.0, 0.0);
+#pragma unroll 4
+  for (int a = 0; a < JC; ++a) {
+    double2 x[4], jv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = Gs[tx + 16 * k][a];
+      jv[k] = Js[a][4 * cq + k];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cfma(o[i][k], x[i], jv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = colx[4 * cq + k];
+    if (c < 0) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + tx + 16 * i;
+      if (r < n) M[(size_t)c * d.ldg + r] = o[i][k];
     }
   }
 }
@@ -354,6 +468,11 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
   }
   std::vector<int> flags(nmat), active(nmat, 1);
   DevBuf act((size_t)nmat * sizeof(int));
+  const int npair_max = std::max(1, nbpmax / 2);
+  const int ntile_max = cdiv(nmax, GT), atile_max = cdiv(nmax, AT);
+  DevBuf hpart((size_t)nmat * npair_max * ntile_max * JC * JC * sizeof(double2));
+  DevBuf jbuf((size_t)nmat * npair_max * JC * JC * sizeof(double2));
+  DevBuf rotf((size_t)nmat * npair_max * sizeof(int));
   // relative orthogonality reachable in floating point is ~ sqrt(n) eps (the
   // stopping rule of LAPACK's one-sided Jacobi)
   const double tol = 4.0 * sqrt((double)nmax) * 2.220446049250313e-16;
@@ -365,8 +484,12 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
     HIP_CHECK(hipEventRecord(e0, s));
     for (int rnd = 0; rnd < rounds; ++rnd) {
-      hipLaunchKernelGGL(jac_block_kernel, dim3(std::max(1, nbpmax / 2), nmat), dim3(256), 0, s, descs,
-                         act.as<int>(), rnd, tol);
+      hipLaunchKernelGGL(jac_gram_kernel, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
+                         act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
+      hipLaunchKernelGGL(jac_inner_kernel, dim3(npair_max, nmat), dim3(256), 0, s, descs, act.as<int>(), rnd,
+                         tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max);
+      hipLaunchKernelGGL(jac_apply_kernel, dim3(2 * atile_max, npair_max, nmat), dim3(128), 0, s, descs,
+                         act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
     }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipEventRecord(e1, s));
@@ -375,7 +498,7 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
     st.ms += ms;
-    st.launches += rounds;
+    st.launches += 3 * rounds;
     // algorithmic work: every task reads its columns of G and forms the
     // Hermitian Gram matrix; a task that rotated writes them back and reads
     // and writes its columns of V, applying the c x c rotation product to both
