@@ -41,6 +41,26 @@ def nsum_pairs(pr: W.Problem) -> float:
     return 8.0 * (b.P * b.M) * (b.P * b.N)
 
 
+def measured_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
+    (rocprofv3 --pmc, scaled by the same counters of a 2 GiB copy), or None
+    if the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_1506_05083_amd", "csrc", kernel_source)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != digest:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run_gpu(pr: W.Problem, steps: int, warmup: int):
     import torch
     import paper_1506_05083_amd as mfs
@@ -160,10 +180,22 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 2 GiB device to device (the reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = 1 << 28                        # 2 GiB of float64 read, 2 GiB written
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}))
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-GPU work "
-              "shards by incident wave with no communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the work shards by "
+              "incident wave, each GPU solving its own batch with no communication", file=sys.stderr)
         sys.exit(2)
 
     pr = W.periodic_k10(8)
@@ -183,23 +215,38 @@ def main():
     nsum_avg = float(np.mean([t["nsum_avg"] for t in tms]))
     pairs = nsum_pairs(pr)                # one batched launch serves all waves
     pairs_per_s = pairs / (nsum_avg * 1e-3)
-    # algorithmic FP64 work of one (target, source, image) pair: distance and
-    # R^2 (8), 1/R and R (2), kR (1), sincos (2), kernel assembly (10), and one
-    # complex multiply-accumulate (8) per incident wave of the batch
-    flops_pair = 8 + 2 + 1 + 2 + 10 + 8 * nw
-    nsum_tflops = pairs_per_s * flops_pair / 1e12
-    roof_nsum = {"bound": "alu", "kernel": "nsum_kernel<8> (A_else surface sum, all waves)",
-                 "achieved": nsum_tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                 "frac": nsum_tflops / PEAK_FP64, "traffic": None,
-                 "launch_ms": nsum_avg, "pairs_per_launch": pairs, "flops_per_pair": flops_pair,
-                 "share_of_step": float(np.median([t["nsum_avg"] * t["nsum_launches"] for t in tms])) / ms_step}
+    near_bytes = float(np.median([t["near_bytes"] for t in tms]))
+    nsum_share = float(np.median([t["nsum_avg"] * t["nsum_launches"] for t in tms])) / ms_step
+    if near_bytes > 0:
+        # stored near field: every launch streams the kernel values once
+        # (plus the strengths and outputs, under 0.1% of them)
+        gbs = near_bytes / (nsum_avg * 1e-3) / 1e9
+        traffic = measured_traffic("nsum.hip", "nsum_dense_periodic_k10_traffic.txt")
+        roof_nsum = {"bound": "hbm", "kernel": "nsum_dense_kernel<8> (A_else surface and C wall sums from the "
+                                               "stored near field, all waves, mean over launches)",
+                     "achieved": gbs, "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs / PEAK_HBM,
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "launch_ms": nsum_avg, "bytes_per_launch": near_bytes,
+                     "fill_ms": float(np.median([t["near_fill_ms"] for t in tms])), "share_of_step": nsum_share}
+    else:
+        # algorithmic FP64 work of one (target, source, image) pair: distance and
+        # R^2 (8), 1/R and R (2), kR (1), sincos (2), kernel assembly (10), and one
+        # complex multiply-accumulate (8) per incident wave of the batch
+        flops_pair = 8 + 2 + 1 + 2 + 10 + 8 * nw
+        nsum_tflops = pairs_per_s * flops_pair / 1e12
+        roof_nsum = {"bound": "alu", "kernel": "nsum_kernel<8> (A_else surface sum, all waves)",
+                     "achieved": nsum_tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": nsum_tflops / PEAK_FP64, "traffic": None,
+                     "launch_ms": nsum_avg, "pairs_per_launch": pairs, "flops_per_pair": flops_pair,
+                     "share_of_step": nsum_share}
     jac_ms = float(np.median([t["jacobi_ms"] for t in tms]))
     jac_launch_ms = jac_ms / max(1, int(np.median([t["jacobi_launches"] for t in tms])))
     jac_bytes = float(np.median([t["jacobi_bytes"] / max(1, t["jacobi_launches"]) for t in tms]))
     jac_flops = float(np.median([t["jacobi_flops"] / max(1, t["jacobi_launches"]) for t in tms]))
     jac_gbs = jac_bytes / (jac_launch_ms * 1e-3) / 1e9
     jac_tflops = jac_flops / (jac_launch_ms * 1e-3) / 1e12
-    jac_common = {"kernel": "jac_block_kernel (periodizer pseudoinverse, 8 waves)",
+    jac_common = {"kernel": "jac_gram_kernel + jac_inner_kernel + jac_apply_kernel (periodizer "
+                            "pseudoinverse, 8 waves; per launch, three launches a round)",
                   "traffic": None, "launch_ms": jac_launch_ms, "bytes_per_launch": jac_bytes,
                   "flops_per_launch": jac_flops, "flops_per_byte": jac_flops / max(jac_bytes, 1.0),
                   "share_of_step": jac_ms / ms_step}
@@ -211,8 +258,12 @@ def main():
     else:
         roof_jac = {"bound": "hbm", "achieved": jac_gbs, "peak": PEAK_HBM, "unit": "GB/s",
                     "frac": jac_gbs / PEAK_HBM, **jac_common}
-    roofline, other = (roof_jac, roof_nsum) if roof_jac["share_of_step"] >= roof_nsum["share_of_step"] \
-        else (roof_nsum, roof_jac)
+    # the dominant single kernel: the stored-near-field sum when it is used
+    # (the Jacobi share is split over its three kernels), else the larger share
+    if near_bytes > 0 or roof_nsum["share_of_step"] >= roof_jac["share_of_step"]:
+        roofline, other = roof_nsum, roof_jac
+    else:
+        roofline, other = roof_jac, roof_nsum
     line = {
         "metric": "FP64 modal fill+QR TFLOP/s; incident-wave solves/s, p50/p99 @1e-10 rel err",
         "value": nw * K / t_total,

@@ -108,7 +108,8 @@ typedef struct {
  * the operator's stream). */
 typedef struct {
   double rhs, periodizer, gmres, recover, total;
-  double nsum_avg;        /* mean duration of one surface neighbour-sum launch */
+  double nsum_avg;        /* mean duration of one neighbour-sum launch (the
+                             surface sums of A_else and the wall sums of C)   */
   int32_t nsum_launches;
   double jacobi_ms;       /* Jacobi sweeps of the periodizer's pseudoinverse   */
   int32_t jacobi_launches;
@@ -119,6 +120,9 @@ typedef struct {
   double jacobi_flops;    /* algorithmic FP64 flops: the Hermitian Gram matrix
                              of every task, and the rotation product applied
                              to G and V by the tasks that rotated             */
+  double near_fill_ms;    /* filling the dense near field (0 if on the fly)  */
+  double near_bytes;      /* mean dense near-field bytes streamed by one of
+                             those launches (0 if evaluated on the fly)       */
 } mfs_solve_timing;
 
 const char *mfs_last_error(void);
@@ -212,6 +216,17 @@ mfs_status mfs_neighbour_sum(const mfs_op *op, int32_t body, const mfs_lattice *
 mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
                           const mfs_c128 *c, const double *targets, int32_t ntargets,
                           mfs_c128 *out, void *stream);
+
+/* Near-field policy of later mfs_solve_incident calls on op.  The kernel
+ * values of the neighbour sums (the 8 images of A_else on the surface nodes
+ * and the images of the wall rows of C) depend on the body, the lattice and
+ * k only, so a solve may fill them once in device memory and stream them in
+ * every GMRES iteration instead of evaluating them (the paper keeps B and C
+ * dense in RAM and applies A_else by the FMM; on one GPU all three fit).
+ * max_bytes bounds that storage: 0 evaluates the sums on the fly every
+ * iteration; the default (UINT64_MAX) stores them whenever they fit with
+ * 2 GiB of device memory to spare.  Results agree to rounding either way. */
+mfs_status mfs_set_near_field_budget(mfs_op *op, uint64_t max_bytes);
 
 /* (c) Periodic solve for nwaves incident waves (Sec. 4.2): per wave, fill and
  * factor Q = [S, -W] (SVD truncated at rel_cutoff relative), then GMRES on

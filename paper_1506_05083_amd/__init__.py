@@ -65,7 +65,8 @@ class SolveTiming(C.Structure):
                 ("recover", C.c_double), ("total", C.c_double), ("nsum_avg", C.c_double),
                 ("nsum_launches", C.c_int32), ("jacobi_ms", C.c_double),
                 ("jacobi_launches", C.c_int32), ("jacobi_bytes", C.c_double),
-                ("jacobi_flops", C.c_double)]
+                ("jacobi_flops", C.c_double), ("near_fill_ms", C.c_double),
+                ("near_bytes", C.c_double)]
 
 
 _SIGS = {
@@ -81,6 +82,7 @@ _SIGS = {
     "mfs_factor_modes": (C.c_int, [C.c_void_p, C.c_double, _ip]),
     "mfs_op_singular_values": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "mfs_op_timing": (C.c_int, [C.c_void_p, _dp]),
+    "mfs_set_near_field_budget": (C.c_int, [C.c_void_p, C.c_uint64]),
     "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "mfs_rhs_modes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_void_p, C.c_void_p]),
@@ -216,6 +218,10 @@ class Operator:
         _check(lib().mfs_factor_modes(self.h, rel_cutoff, _ptr(r, _ip)))
         self.ranks = r
         return r
+
+    def set_near_field_budget(self, max_bytes: int):
+        """Device-memory bound of the dense near field of later solves (0: on the fly)."""
+        _check(lib().mfs_set_near_field_budget(self.h, int(max_bytes)))
 
     def timing(self) -> dict:
         """Fill, QR and truncation stage times (ms, HIP events)."""

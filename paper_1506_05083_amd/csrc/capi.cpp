@@ -395,6 +395,13 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   MFS_API_END
 }
 
+mfs_status mfs_set_near_field_budget(mfs_op *op, uint64_t max_bytes) {
+  MFS_API_BEGIN
+  MFS_REQUIRE(op != nullptr, "null pointer");
+  op->near_budget = max_bytes;
+  MFS_API_END
+}
+
 mfs_status mfs_op_timing(const mfs_op *op, double *ms) {
   MFS_API_BEGIN
   MFS_REQUIRE(op != nullptr && ms != nullptr, "null pointer");

@@ -24,6 +24,7 @@ struct mfs_op {
   mfs::DevBuf work;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double ms_fill = 0.0, ms_qr = 0.0, ms_svd = 0.0;
+  uint64_t near_budget = UINT64_MAX;   // dense near-field storage limit (bytes)
   ~mfs_op() {
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);

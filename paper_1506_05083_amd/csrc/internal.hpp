@@ -113,6 +113,13 @@ struct NsumPlan {
   DevBuf tgt;         // SoA x y z dx dy dz [ntarget_pad] each
   DevBuf grp;         // NsumGroup[] on device
   DevBuf tile_group;  // int [ntarget_pad/64]
+  // optional dense near field (nsum_build_dense): kernel values of every
+  // group, image, source and target, for the sources `dense_src` (S of them)
+  DevBuf dense, koff;
+  const double *dense_src = nullptr;
+  int dense_S = 0;
+  double dense_k = 0.0;
+  size_t dense_bytes = 0;
 };
 // out[r][t] = sum_img w[g][img][r] sum_s K(x_t - a ex - b ey, y_s) sigma[r][s]
 // w: device [ngroups][9][nrhs] complex; src: SoA x y z [S]; sigma [nrhs][S]
@@ -120,6 +127,10 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                  const double *src, int S, const double2 *sigma, const double2 *w,
                  double2 *out, double2 *partial, hipStream_t s);
 int nsum_splits(const NsumPlan &plan, int S);
+// Fill plan.dense for the sources src (S of them); false (and nothing
+// allocated) if it would take more than max_bytes or leave under 2 GiB free.
+bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,
+                      size_t max_bytes, hipStream_t s);
 
 // ----------------------------------------------------------- harmonics
 // Fill rows of Q (S block and -W blocks) for one wave.

@@ -23,6 +23,25 @@ namespace {
 constexpr int SC = 128;     // sources per LDS chunk (32 per wave)
 constexpr int MAXR = 16;    // right-hand sides per launch
 
+// G(x - y) = e^{ikR} / (4 pi R) for (dx, dy, dz) = x - y, or its derivative
+// along the target direction (tx, ty, tz) when deriv is set
+__device__ inline double2 near_kernel(double ddx, double ddy, double ddz, double tx, double ty, double tz,
+                                      double k, int deriv) {
+  const double inv4pi = 0.25 / kPi;
+  const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
+  const double invR = rsqrt(R2);
+  const double R = R2 * invR;
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  if (deriv) {
+    const double dn = fma(tx, ddx, fma(ty, ddy, tz * ddz));
+    const double tt = dn * invR * invR * inv4pi;
+    return cz(tt * fma(-cs, invR, -sn * k), tt * fma(cs, k, -sn * invR));
+  }
+  const double tt = invR * inv4pi;
+  return cz(cs * tt, sn * tt);
+}
+
 template <int NR>
 __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tgt, int ntp,
                                                    const NsumGroup *__restrict__ groups,
@@ -46,14 +65,13 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per;
   const int s_end = min(S, s_begin + per);
-  const double inv4pi = 0.25 / kPi;
 
   double2 tot[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
 
   for (int im = 0; im < g.nimg; ++im) {
-    const double xs = xt - g.ia[im] * ex, ys = yt - g.ib[im] * ey;
+    const double xs = xt - groups[gi].ia[im] * ex, ys = yt - groups[gi].ib[im] * ey;
     double2 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
@@ -74,21 +92,7 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
       __syncthreads();
       const int sbeg = wv * (SC / 4);
       for (int ss = sbeg; ss < sbeg + SC / 4; ++ss) {
-        const double ddx = xs - sx[ss], ddy = ys - sy[ss], ddz = zt - szs[ss];
-        const double R2 = fma(ddx, ddx, fma(ddy, ddy, ddz * ddz));
-        const double invR = rsqrt(R2);
-        const double R = R2 * invR;
-        double sn, cs;
-        sincos(k * R, &sn, &cs);
-        double2 K;
-        if (g.deriv) {
-          const double dn = fma(dxt, ddx, fma(dyt, ddy, dzt * ddz));
-          const double tt = dn * invR * invR * inv4pi;
-          K = cz(tt * fma(-cs, invR, -sn * k), tt * fma(cs, k, -sn * invR));
-        } else {
-          const double tt = invR * inv4pi;
-          K = cz(cs * tt, sn * tt);
-        }
+        const double2 K = near_kernel(xs - sx[ss], ys - sy[ss], zt - szs[ss], dxt, dyt, dzt, k, g.deriv);
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], K, ssig[r * SC + ss]);
       }
@@ -98,6 +102,126 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
       if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
   }
   // reduce the four waves
+  __syncthreads();
+  double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot[r];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+    const int r = idx / 64, l = idx % 64;
+    if (r >= nrhs) continue;
+    double2 v = red[(0 * NR + r) * 64 + l];
+    for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
+    out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = v;
+  }
+}
+
+// Dense near field: the values K(x_t - a e_x - b e_y, y_s) of every group,
+// image and source are written once, per 64-target tile, image-major then
+// source-major with the tile's targets contiguous:
+//   dense[koff[g] + ((tile_g * nimg_g + img) * S + s) * 64 + lane],
+// so that every wave of the sum streams one contiguous range.
+// The sums then stream them instead of evaluating them (they depend on the
+// geometry, the lattice and k only, not on the incident wave or the iterate).
+__global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict__ tgt, int ntp,
+                                                        const NsumGroup *__restrict__ groups,
+                                                        const int *__restrict__ tile_group,
+                                                        const size_t *__restrict__ koff, double k, double ex,
+                                                        double ey, const double *__restrict__ src, int S,
+                                                        int nsplit, double2 *__restrict__ dense) {
+  __shared__ double sx[SC], sy[SC], szs[SC];
+  const int tile = blockIdx.x, split = blockIdx.y;
+  const int gi = tile_group[tile];
+  const NsumGroup &g = groups[gi];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = tile * 64 + lane;
+  const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
+  const double dxt = tgt[3 * ntp + t], dyt = tgt[4 * ntp + t], dzt = tgt[5 * ntp + t];
+  const int per = (S + nsplit - 1) / nsplit;
+  const int s_begin = split * per, s_end = min(S, s_begin + per);
+  const int nimg = g.nimg, deriv = g.deriv;
+  double2 *base = dense + koff[gi] + (size_t)((t - g.t0) >> 6) * nimg * S * 64 + lane;
+  for (int c0 = s_begin; c0 < s_end; c0 += SC) {
+    const int nc = min(SC, s_end - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < SC; idx += 256) {
+      const int sidx = c0 + idx;
+      const bool ok = idx < nc;
+      sx[idx] = ok ? src[sidx] : 0.0;
+      sy[idx] = ok ? src[S + sidx] : 0.0;
+      szs[idx] = ok ? src[2 * S + sidx] : 0.0;
+    }
+    __syncthreads();
+    for (int im = 0; im < nimg; ++im) {
+      const double xs = xt - groups[gi].ia[im] * ex, ys = yt - groups[gi].ib[im] * ey;
+      for (int ss = wv; ss < nc; ss += 4) {
+        const double2 K = near_kernel(xs - sx[ss], ys - sy[ss], zt - szs[ss], dxt, dyt, dzt, k, deriv);
+        base[((size_t)im * S + c0 + ss) * 64] = K;
+      }
+    }
+  }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGroup *__restrict__ groups,
+                                                         const int *__restrict__ tile_group,
+                                                         const size_t *__restrict__ koff,
+                                                         const double2 *__restrict__ dense, int nrhs, int S,
+                                                         const double2 *__restrict__ sigma,
+                                                         const double2 *__restrict__ wts, int nsplit,
+                                                         double2 *__restrict__ out) {
+  extern __shared__ double shm[];
+  double2 *ssig = reinterpret_cast<double2 *>(shm);   // [NR][SC]
+  const int tile = blockIdx.x, split = blockIdx.y;
+  const int gi = tile_group[tile];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = tile * 64 + lane;
+  const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
+  const int per = (S + nsplit - 1) / nsplit;
+  const int s_begin = split * per, s_end = min(S, s_begin + per);
+  const double2 *base = dense + koff[gi] + (size_t)((t - t0) >> 6) * nimg * S * 64 + lane;
+  double2 tot[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
+  for (int im = 0; im < nimg; ++im) {
+    double2 acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
+    const double2 *kim = base + (size_t)im * S * 64;
+    for (int c0 = s_begin; c0 < s_end; c0 += SC) {
+      const int nc = min(SC, s_end - c0);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < NR * SC; idx += 256) {
+        const int r = idx / SC, ss = idx % SC;
+        ssig[idx] = (r < nrhs && ss < nc) ? sigma[(size_t)r * S + c0 + ss] : cz(0.0, 0.0);
+      }
+      __syncthreads();
+      // this wave's quarter of the chunk, eight values in flight
+      const int sb = wv * (SC / 4);
+      for (int u = 0; u < SC / 4; u += 8) {
+        double2 kv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          // streamed once per launch: non-temporal loads keep them out of the caches
+          const bool ok = sb + u + e < nc;
+          const double2 *pk = kim + (ok ? (size_t)(c0 + sb + u + e) * 64 : 0);
+          double2 v;
+          v.x = __builtin_nontemporal_load(&pk->x);
+          v.y = __builtin_nontemporal_load(&pk->y);
+          const long long m = ok ? -1LL : 0LL;
+          kv[e] = cz(__longlong_as_double(__double_as_longlong(v.x) & m),
+                     __longlong_as_double(__double_as_longlong(v.y) & m));
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[r], kv[e], ssig[r * SC + sb + u + e]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
+  }
   __syncthreads();
   double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
 #pragma unroll
@@ -142,6 +266,16 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
 }
 
 template <int NR>
+void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *sigma, const double2 *w,
+                         int nsplit, double2 *dst, hipStream_t s) {
+  const size_t sh = std::max((size_t)NR * SC * sizeof(double2), (size_t)4 * NR * 64 * sizeof(double2));
+  hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                     plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
+                     plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigma, w, nsplit, dst);
+  HIP_CHECK(hipGetLastError());
+}
+
+template <int NR>
 void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                    const double *src, int S, const double2 *sigma, const double2 *w,
                    int nsplit, double2 *dst, hipStream_t s) {
@@ -168,7 +302,13 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
   MFS_REQUIRE(nrhs >= 1 && nrhs <= MAXR, "neighbour sum: 1 <= nrhs <= 16");
   const int nsplit = nsum_splits(plan, S);
   double2 *dst = (nsplit == 1) ? out : partial;
-  if (nrhs <= 1) launch_nsum_t<1>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
+  if (plan.dense.p && plan.dense_src == src && plan.dense_S == S && plan.dense_k == k) {
+    if (nrhs <= 1) launch_nsum_dense_t<1>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    else if (nrhs <= 2) launch_nsum_dense_t<2>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    else if (nrhs <= 4) launch_nsum_dense_t<4>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    else if (nrhs <= 8) launch_nsum_dense_t<8>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    else launch_nsum_dense_t<16>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+  } else if (nrhs <= 1) launch_nsum_t<1>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
   else if (nrhs <= 2) launch_nsum_t<2>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
   else if (nrhs <= 4) launch_nsum_t<4>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
   else if (nrhs <= 8) launch_nsum_t<8>(plan, nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst, s);
@@ -179,6 +319,35 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                        0, s, nsplit, nrhs, plan.ntarget_pad, partial, out);
     HIP_CHECK(hipGetLastError());
   }
+}
+
+bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,
+                      size_t max_bytes, hipStream_t s) {
+  size_t off = 0;
+  std::vector<size_t> koff(plan.groups.size());
+  for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
+    const NsumGroup &g = plan.groups[gi];
+    koff[gi] = off;
+    off += (size_t)g.nimg * S * round_up(std::max(g.nt, 1), 64);
+  }
+  const size_t bytes = off * sizeof(double2);
+  if (bytes > max_bytes) return false;
+  size_t fr = 0, tot = 0;
+  HIP_CHECK(hipMemGetInfo(&fr, &tot));
+  if (bytes + ((size_t)2 << 30) > fr) return false;   // keep 2 GiB of headroom
+  plan.dense.alloc(bytes);
+  plan.koff.alloc(koff.size() * sizeof(size_t));
+  HIP_CHECK(hipMemcpyAsync(plan.koff.p, koff.data(), koff.size() * sizeof(size_t), hipMemcpyHostToDevice, s));
+  const int nsplit = nsum_splits(plan, S);
+  hipLaunchKernelGGL(nsum_fill_kernel, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), 0, s, plan.tgt.as<double>(),
+                     plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
+                     k, ex, ey, src, S, nsplit, plan.dense.as<double2>());
+  HIP_CHECK(hipGetLastError());
+  plan.dense_src = src;
+  plan.dense_S = S;
+  plan.dense_k = k;
+  plan.dense_bytes = bytes;
+  return true;
 }
 
 void launch_combine_walls(int nw, int M1sq, const double2 *in, double2 *out, hipStream_t s) {

@@ -78,9 +78,11 @@ struct Solver {
   // work
   DevBuf V, Z, XIN, C, SIG, GS, GH, WR, CY, XI, PART, YW, H1, SC;
   int nsplit_s = 1, nsplit_w = 1;
-  // timing
+  // timing: events around every neighbour-sum launch, the dense bytes each streamed
   std::vector<hipEvent_t> nsum_ev;
+  std::vector<double> nsum_bytes;
   bool time_nsum = true;
+  double near_fill_ms = 0.0;
 
   Solver(const mfs_op *o, BodyData &body, const mfs_lattice &l, int nw, int mi, hipStream_t st)
       : op(o), b(body), lat(l), W(nw), maxit(mi), s(st) {
@@ -168,6 +170,23 @@ struct Solver {
     const int S = P * N;
     nsplit_s = nsum_splits(psurf, S);
     nsplit_w = nsum_splits(pwalls, S);
+    // dense near field, surface first (the larger share of the iteration)
+    if (op->near_budget > 0) {
+      hipEvent_t f0, f1;
+      HIP_CHECK(hipEventCreate(&f0));
+      HIP_CHECK(hipEventCreate(&f1));
+      HIP_CHECK(hipEventRecord(f0, s));
+      const size_t budget = (size_t)std::min<uint64_t>(op->near_budget, (uint64_t)SIZE_MAX);
+      if (nsum_build_dense(psurf, b.k, lat.ex, lat.ey, b.src_P.as<double>(), S, budget, s))
+        nsum_build_dense(pwalls, b.k, lat.ex, lat.ey, b.src_P.as<double>(), S, budget - psurf.dense_bytes, s);
+      HIP_CHECK(hipEventRecord(f1, s));
+      HIP_CHECK(hipEventSynchronize(f1));
+      float ms = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&ms, f0, f1));
+      near_fill_ms = (psurf.dense.p || pwalls.dense.p) ? ms : 0.0;
+      (void)hipEventDestroy(f0);
+      (void)hipEventDestroy(f1);
+    }
     // work buffers
     V.alloc((size_t)W * (maxit + 1) * MP * sizeof(double2));
     Z.alloc((size_t)W * MP * sizeof(double2));
@@ -193,11 +212,28 @@ struct Solver {
     launch_pinv_apply(j, s);
   }
 
+  // neighbour sum of the point strengths in SIG over plan (weights w) into out
+  void nsum(const NsumPlan &plan, const DevBuf &w, double2 *out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_nsum) {
+      HIP_CHECK(hipEventCreate(&e0));
+      HIP_CHECK(hipEventCreate(&e1));
+      HIP_CHECK(hipEventRecord(e0, s));
+    }
+    launch_nsum(plan, W, b.k, lat.ex, lat.ey, b.src_P.as<double>(), P * N, SIG.as<double2>(), w.as<double2>(), out,
+                PART.as<double2>(), s);
+    if (time_nsum) {
+      HIP_CHECK(hipEventRecord(e1, s));
+      nsum_ev.push_back(e0);
+      nsum_ev.push_back(e1);
+      nsum_bytes.push_back((double)plan.dense_bytes);
+    }
+  }
+
   // XI = Q^+ (C c) for mode coefficients in C
   void c_then_qpinv(const double2 *cmodes) {
     launch_point_strengths(W, P, P, N, cmodes, SIG.as<double2>(), s);
-    launch_nsum(pwalls, W, b.k, lat.ex, lat.ey, b.src_P.as<double>(), P * N, SIG.as<double2>(),
-                wwalls.as<double2>(), WR.as<double2>(), PART.as<double2>(), s);
+    nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
     PinvJob j{};
     j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
@@ -210,24 +246,11 @@ struct Solver {
   void apply_op(const double2 *x, double2 *out) {
     pinv_A0(x, C.as<double2>());
     launch_point_strengths(W, P, P, N, C.as<double2>(), SIG.as<double2>(), s);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (time_nsum) {
-      HIP_CHECK(hipEventCreate(&e0));
-      HIP_CHECK(hipEventCreate(&e1));
-      HIP_CHECK(hipEventRecord(e0, s));
-    }
-    launch_nsum(psurf, W, b.k, lat.ex, lat.ey, b.src_P.as<double>(), P * N, SIG.as<double2>(),
-                wsurf.as<double2>(), GS.as<double2>(), PART.as<double2>(), s);
-    if (time_nsum) {
-      HIP_CHECK(hipEventRecord(e1, s));
-      nsum_ev.push_back(e0);
-      nsum_ev.push_back(e1);
-    }
+    nsum(psurf, wsurf, GS.as<double2>());
     launch_dft_ld(W, P, M, GS.as<double2>(), psurf.ntarget_pad, GH.as<double2>(), -1, 1.0 / P, s);
     launch_axpby_op(W, MP, x, GH.as<double2>(), nullptr, out, s);
     // the wall rows reuse SIG computed above
-    launch_nsum(pwalls, W, b.k, lat.ex, lat.ey, b.src_P.as<double>(), P * N, SIG.as<double2>(),
-                wwalls.as<double2>(), WR.as<double2>(), PART.as<double2>(), s);
+    nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
     PinvJob j{};
     j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
@@ -524,6 +547,10 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       timing->jacobi_launches = S.gp.jacobi_launches;
       timing->jacobi_bytes = S.gp.jacobi_bytes;
       timing->jacobi_flops = S.gp.jacobi_flops;
+      timing->near_fill_ms = S.near_fill_ms;
+      double nb = 0.0;
+      for (double x : S.nsum_bytes) nb += x;
+      timing->near_bytes = S.nsum_bytes.empty() ? 0.0 : nb / (double)S.nsum_bytes.size();
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (notconv) {

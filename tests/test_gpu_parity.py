@@ -200,13 +200,17 @@ def test_neighbour_sum_parity(mfs, ctx, small_oracle):
         assert rel(gu[0], ref) < 1e-12
 
 
-def test_periodic_solve_parity_small(mfs, ctx, small_oracle):
+@pytest.mark.parametrize("near", ["dense", "on_the_fly"])
+def test_periodic_solve_parity_small(mfs, ctx, small_oracle, near):
     """Whole periodic path on the GPU (Q fill and factorisation, batched
     GMRES with the neighbour sums, recovery) for two incidences against the
-    oracle: Bragg amplitudes and cell fields to 1e-10."""
+    oracle: Bragg amplitudes and cell fields to 1e-10, with the near-field
+    kernel values stored once (default) and evaluated every iteration."""
     pr, g, out = small_oracle
     b = pr.body
     op = make_op(mfs, ctx, b)
+    if near == "on_the_fly":
+        op.set_near_field_budget(0)
     op.factor_modes(1e-10)
     L = _lat(mfs, pr.lattice)
     res = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=1e-12, maxit=100,
@@ -217,7 +221,7 @@ def test_periodic_solve_parity_small(mfs, ctx, small_oracle):
         ea = np.max(np.abs(r.a - o["res"]["a"])) / np.max(np.abs(o["res"]["a"]))
         eb = np.max(np.abs(r.b - o["res"]["b"])) / np.max(np.abs(o["res"]["b"]))
         eu = np.linalg.norm(r.field - o["u"]) / np.linalg.norm(o["u"])
-        log(f"[periodic] wave {i} iters gpu {r.iters} oracle {o['res']['iters']} a {ea:.2e} b {eb:.2e} "
+        log(f"[periodic {near}] wave {i} iters gpu {r.iters} oracle {o['res']['iters']} a {ea:.2e} b {eb:.2e} "
             f"u {eu:.2e} flux gpu {r.eps_flux:.2e} oracle {o['flux']:.2e}")
         assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
         assert r.eps_flux < 1e-6
