@@ -92,6 +92,81 @@ def run_gpu(pr: W.Problem, steps: int, warmup: int):
     return t_total, recs
 
 
+def run_serving(pr: W.Problem, nreq: int, nplain: int, slots: int):
+    """Serving configuration: requests of the seeded stream against the
+    resident factored k = 10 operator.  Plain baseline: the first nplain
+    requests as one-at-a-time solves (mfs_solve_incident with one wave).
+    Served: all nreq submitted at once to a server with `slots` slots
+    (saturated throughput X_sat), then the same requests as a Poisson stream
+    at 0.8 X_sat (latency = completion - submission, measured by the server)."""
+    import torch
+    import paper_1506_05083_amd as mfs
+
+    b, lat = pr.body, pr.lattice
+    ctx = mfs.create(0)
+    geom = mfs.polar_geometry(b.shape.a, b.shape.eps, b.shape.j, b.M, b.N, b.tau, b.colloc)
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    op = mfs.build_operator(ctx, [mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, geom)])
+    op.factor_modes(1e-10)
+    waves, gaps = W.serving_stream(nreq)
+    kw = dict(tol=pr.gmres_tol, maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_iters = []
+    for w in waves[:nplain]:
+        r = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi)], **kw)[0]
+        plain_iters.append(r.iters)
+    t_plain = time.perf_counter() - t0
+    srv = mfs.Server(ctx, op, L, slots=slots, admit_batch=min(8, slots), hbm_budget=200 << 30, **kw)
+
+    def drain(tickets, submit_at=None):
+        """Submit (at the given times, if any) and collect; returns wall time, latencies, results."""
+        t_start = time.perf_counter()
+        out, lat_ms = {}, {}
+        todo = list(range(len(waves))) if submit_at is not None else []
+        live = dict(tickets)
+        while todo or live:
+            now = time.perf_counter() - t_start
+            while todo and submit_at[todo[0]] <= now:
+                i = todo.pop(0)
+                live[i] = srv.submit(waves[i].theta, waves[i].phi)
+            for i in list(live):
+                r = srv.poll(live[i])
+                if r is not None:
+                    out[i], lat_ms[i] = r[0], r[1]
+                    assert r[2], f"request {i} did not converge"
+                    del live[i]
+            time.sleep(0.0005)
+        return time.perf_counter() - t_start, lat_ms, out
+
+    t_sat, lat_sat, res_sat = drain({i: srv.submit(w.theta, w.phi) for i, w in enumerate(waves)})
+    x_sat = nreq / t_sat
+    rate = 0.8 * x_sat
+    arrivals = np.cumsum(gaps) / rate
+    t_poi, lat_poi, res_poi = drain({}, submit_at=arrivals)
+    srv.close()
+    lp = np.array([lat_poi[i] for i in range(nreq)])
+    ls = np.array([lat_sat[i] for i in range(nreq)])
+    same = max(float(np.max(np.abs(res_sat[i].a - res_poi[i].a)) / np.max(np.abs(res_poi[i].a)))
+               for i in range(nreq))
+    return {
+        "requests": nreq, "slots": slots, "plain_requests": nplain,
+        "plain_solves_per_s": nplain / t_plain,
+        "served_saturated_solves_per_s": x_sat,
+        "speedup_vs_plain": x_sat / (nplain / t_plain),
+        "saturated_latency_p50_ms": float(np.percentile(ls, 50)),
+        "saturated_latency_p99_ms": float(np.percentile(ls, 99)),
+        "poisson_rate_per_s": rate,
+        "poisson_solves_per_s": nreq / t_poi,
+        "poisson_latency_p50_ms": float(np.percentile(lp, 50)),
+        "poisson_latency_p99_ms": float(np.percentile(lp, 99)),
+        "max_amplitude_diff_saturated_vs_poisson": same,
+        "gmres_iters_mean": float(np.mean([r.iters for r in res_poi.values()])),
+        "stream": "seeded request stream (directions seed 4, exponential gaps seed 40), first "
+                  f"{nreq} of the serving configuration's 10,000",
+    }
+
+
 def cpu_baseline(pr: W.Problem):
     """The oracle, as it stands, on a bounded sample of the same workload
     (about 20 s of CPU work), scaled to incident-wave solves per second with
@@ -180,6 +255,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving measurement (0 skips it)")
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device to device (the reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -287,6 +365,9 @@ def main():
         "roofline": roofline,
         "roofline_other": other,
     }
+    if args.serve_requests > 0:
+        line["serving"] = run_serving(W.periodic_k10(1), args.serve_requests, min(8, args.serve_requests),
+                                      args.serve_slots)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pr)
     print(json.dumps(line))

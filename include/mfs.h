@@ -244,6 +244,60 @@ mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t body,
                               const double *targets, int32_t ntargets, int32_t q_field,
                               mfs_result *res, mfs_solve_timing *timing);
 
+/* ------------------------------------------------------------- serving
+ * A server keeps the factored operator of one body and the lattice resident
+ * and solves incident waves as they arrive (continuous batching): a fixed
+ * pool of `slots` waves iterates in lockstep GMRES on eq. (iter), one batched
+ * operator application per iteration for every wave in flight; a wave that
+ * arrives is factored (its Q fill and truncated Q^+, Sec. 4.2) on a second
+ * stream while the others iterate, joins the pool at the next iteration
+ * boundary once a slot and memory are free, and leaves it when it converges
+ * (its amplitudes and fields are then recovered as in mfs_solve_incident).
+ * Every wave's arithmetic is independent of the others in the pool, so a
+ * result is the same alone and in any mix (up to the rounding of its own Q
+ * factorisation, which is batched with the waves admitted with it).  Two
+ * host threads of the library drive the two streams. */
+typedef struct mfs_server mfs_server;
+
+typedef struct {
+  int32_t slots;          /* waves iterating at once, 1..16                   */
+  int32_t admit_batch;    /* waves factored together, 1..slots                */
+  int32_t queue_cap;      /* pending requests before submit returns EBUSY     */
+  double tol;             /* GMRES relative residual (eq. (iter))             */
+  int32_t maxit;          /* GMRES iteration cap per wave                     */
+  double rel_cutoff;      /* truncation of Q^+ (1e-10)                        */
+  const double *targets;  /* host [ntargets][3] field points of every result  */
+  int32_t ntargets;
+  int32_t q_field;        /* point-source nodes of the field evaluation       */
+  uint64_t hbm_budget;    /* device bytes the server may hold: the stored near
+                             field, the slots' Krylov bases and Q factors and
+                             the factorisation work of one admission group;
+                             requests wait while it would be exceeded          */
+} mfs_server_config;
+
+/* Start a server on op (factored) and body for lattice lat.  Copies the
+ * configuration and targets; fills the stored near field (within
+ * hbm_budget) before returning.  EINVAL for bad sizes, ESTATE if op is not
+ * factored, ENOMEM if the pool and one admission group do not fit. */
+mfs_status mfs_server_create(mfs_ctx *ctx, const mfs_op *op, int32_t body, const mfs_lattice *lat,
+                             const mfs_server_config *cfg, mfs_server **out);
+/* Queue one incident wave; ticket receives its id.  Non-blocking; EBUSY if
+ * queue_cap requests are already waiting. */
+mfs_status mfs_server_submit(mfs_server *srv, const mfs_wave *wave, uint64_t *ticket);
+/* Result of a finished request, as mfs_solve_incident would return it (res
+ * arrays provided by the caller; EINVAL with norders set if cap_orders is
+ * too small).  latency_ms (optional) receives completion minus submission
+ * time.  EBUSY: not finished yet; EINVAL: unknown ticket (or already
+ * collected); ENOTCONV: finished at maxit (res holds the last iterate);
+ * EDEVICE: the server failed (mfs_last_error has the reason). */
+mfs_status mfs_server_poll(mfs_server *srv, uint64_t ticket, mfs_result *res, double *latency_ms);
+/* Requests waiting, being factored, iterating, and finished but not yet
+ * collected (any pointer may be NULL). */
+mfs_status mfs_server_stats(mfs_server *srv, int32_t *pending, int32_t *admitting, int32_t *iterating,
+                            int32_t *finished);
+/* Stop the server (requests not finished are dropped) and free it. */
+void mfs_server_destroy(mfs_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

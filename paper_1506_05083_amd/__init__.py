@@ -60,6 +60,13 @@ class Result(C.Structure):
                 ("nq_cols", C.c_int32)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("admit_batch", C.c_int32), ("queue_cap", C.c_int32),
+                ("tol", C.c_double), ("maxit", C.c_int32), ("rel_cutoff", C.c_double),
+                ("targets", C.POINTER(C.c_double)), ("ntargets", C.c_int32), ("q_field", C.c_int32),
+                ("hbm_budget", C.c_uint64)]
+
+
 class SolveTiming(C.Structure):
     _fields_ = [("rhs", C.c_double), ("periodizer", C.c_double), ("gmres", C.c_double),
                 ("recover", C.c_double), ("total", C.c_double), ("nsum_avg", C.c_double),
@@ -93,6 +100,12 @@ _SIGS = {
                                     C.c_void_p, C.c_void_p]),
     "mfs_field_free": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp,
                                  C.c_int32, C.c_void_p, C.c_void_p]),
+    "mfs_server_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Lattice),
+                                    C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    "mfs_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Wave), C.POINTER(C.c_uint64)]),
+    "mfs_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Result), _dp]),
+    "mfs_server_stats": (C.c_int, [C.c_void_p, _ip, _ip, _ip, _ip]),
+    "mfs_server_destroy": (None, [C.c_void_p]),
     "mfs_solve_incident": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Lattice),
                                      C.c_int32, C.POINTER(Wave), C.c_double, C.c_int32, C.c_double,
                                      _dp, C.c_int32, C.c_int32, C.POINTER(Result),
@@ -366,6 +379,91 @@ def solve_incident(ctx: Context, op: Operator, lattice: Lattice, waves: Sequence
     if timing:
         return out, {k: getattr(tm, k) for k, _ in SolveTiming._fields_}
     return out
+
+
+def _result_slot(cap_orders: int, nt: int):
+    arrs = dict(m=np.zeros(cap_orders, np.int32), n=np.zeros(cap_orders, np.int32),
+                kz=np.zeros(cap_orders, np.complex128), a=np.zeros(cap_orders, np.complex128),
+                b=np.zeros(cap_orders, np.complex128), field=np.zeros(max(nt, 1), np.complex128))
+    r = Result()
+    r.cap_orders = cap_orders
+    r.m = _ptr(arrs["m"], _ip)
+    r.n = _ptr(arrs["n"], _ip)
+    for k in ("kz", "a", "b", "field"):
+        setattr(r, k, arrs[k].ctypes.data_as(_cp))
+    return r, arrs
+
+
+class Server:
+    """Continuous-batching server of incident-wave solves on a factored operator
+    (mfs_server_*): submit(theta, phi) -> ticket; poll(ticket) -> (WaveResult,
+    latency ms, converged) or None while the request is in flight."""
+
+    def __init__(self, ctx: Context, op: Operator, lattice: Lattice, slots: int = 8, admit_batch: int = 8,
+                 queue_cap: int = 1 << 20, tol: float = 1e-10, maxit: int = 100, rel_cutoff: float = 1e-10,
+                 targets: Optional[np.ndarray] = None, q_field: Optional[int] = None,
+                 hbm_budget: int = 200 << 30, body: int = 0, cap_orders: int = 4096):
+        import torch
+        b = op.bodies[body]
+        self.op, self.ctx, self.cap_orders = op, ctx, cap_orders
+        self._tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.float64)
+        self.nt = 0 if targets is None else self._tg.shape[0]
+        cfg = ServerConfig(slots, admit_batch, queue_cap, tol, maxit, rel_cutoff,
+                           None if self._tg is None else _ptr(self._tg), self.nt,
+                           q_field if q_field is not None else 2 * b.P, int(hbm_budget))
+        self._lat = lattice
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib().mfs_server_create(ctx.h, op.h, body, C.byref(lattice), C.byref(cfg), C.byref(h)))
+        self.h = h
+
+    def submit(self, theta: float, phi: float) -> Optional[int]:
+        """Queue one wave; None if the queue is full."""
+        t = C.c_uint64()
+        st = lib().mfs_server_submit(self.h, C.byref(Wave(float(theta), float(phi))), C.byref(t))
+        if st == MFS_EBUSY:
+            return None
+        _check(st)
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        r, arrs = _result_slot(self.cap_orders, self.nt)
+        lat = C.c_double()
+        st = lib().mfs_server_poll(self.h, ticket, C.byref(r), C.byref(lat))
+        if st == MFS_EBUSY:
+            return None
+        if st not in (MFS_OK, MFS_ENOTCONV):
+            _check(st)
+        n = r.norders
+        res = WaveResult(r.iters, r.resid, arrs["m"][:n].copy(), arrs["n"][:n].copy(), arrs["kz"][:n].copy(),
+                         arrs["a"][:n].copy(), arrs["b"][:n].copy(), arrs["field"][:self.nt].copy(),
+                         r.eps_flux, r.q_rank, r.nq_cols)
+        return res, lat.value, st == MFS_OK
+
+    def stats(self) -> dict:
+        v = [np.zeros(1, np.int32) for _ in range(4)]
+        _check(lib().mfs_server_stats(self.h, *[_ptr(x, _ip) for x in v]))
+        return dict(pending=int(v[0][0]), admitting=int(v[1][0]), iterating=int(v[2][0]), finished=int(v[3][0]))
+
+    def wait(self, ticket: int, timeout_s: float = 600.0, poll_s: float = 0.001):
+        """Block (polling) until ticket finishes."""
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not finished after {timeout_s} s")
+            time.sleep(poll_s)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mfs_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def lattice(ex, ey, z0, p, N0, M1) -> Lattice:

@@ -24,6 +24,15 @@ struct GradedPinv {
   double jacobi_flops = 0.0;
   // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
   const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
+  // free the factorisation's work, keeping what the apply reads (U in
+  // qc[w].fac, W in fin, the kept ranks in small)
+  void release_work() {
+    d_in.release(); d_qc.release(); d_rq.release(); d_rqu.release(); d_lq.release();
+    perm.release(); piv.release();
+    for (auto &q : qc) q.a.release();
+    rq.clear();
+    lq.clear();
+  }
 };
 
 // in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.

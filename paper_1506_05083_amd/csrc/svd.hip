@@ -86,7 +86,9 @@ constexpr int AT = 64;    // rows per workgroup of the rotation apply
 __device__ inline bool task_blocks(const MatDesc &d, int round, int pair, int &bi, int &bj, int &nb) {
   nb = (d.n + JB - 1) / JB;
   const int nbp = nb + (nb & 1);
-  if (pair >= nbp / 2) return false;
+  // a matrix runs its own nbp - 1 rounds, whatever else is in the batch, so
+  // that its factors do not depend on its batch-mates
+  if (pair >= nbp / 2 || round >= nbp - 1) return false;
   circle_pair(nbp, round, pair, bi, bj);
   return bi < nb || bj < nb;
 }
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict
 // 2. one workgroup per task: H = sum of the partials, one Jacobi sweep over
 //    its 32 columns on H, J = product of the rotations -> jbuf, rot = any rotation
 __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restrict__ descs,
-                                                        const int *__restrict__ act, int round, double tol,
+                                                        const int *__restrict__ act, int round, double tol_eps,
                                                         const double2 *__restrict__ hpart,
                                                         double2 *__restrict__ jbuf, int *__restrict__ rot,
                                                         int npair_max, int ntile_max) {
@@ -190,6 +192,9 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
   __shared__ int s_nrot;
   const int tid = threadIdx.x;
   const int ntile = (d.n + GT - 1) / GT;
+  // relative orthogonality reachable in floating point, ~ sqrt(n) eps of this
+  // matrix (the stopping rule of LAPACK's one-sided Jacobi)
+  const double tol = tol_eps * sqrt((double)d.n), tol2 = tol * tol;
   const double2 *hp = hpart + ((size_t)mat * npair_max + pair) * ntile_max * JC * JC;
   {
     double2 h[JC * JC / 256];
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
       const double a = Hs[p][p].x, b = Hs[q][q].x;
       const double2 gam = Hs[p][q];
       const double g2 = cabs2(gam);
-      const int on = g2 > tol * tol * a * b;
+      const int on = g2 > tol2 * a * b;
       if (on) {
         const double dd = b - a;
         const double qq = copysign(2.0, dd) / (fabs(dd) + sqrt(fma(dd, dd, 4.0 * g2)));
@@ -455,7 +460,7 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
   for (int i = 0; i < nmat; ++i) {
     const int n = h[i].n, nb = cdiv(n, JB), nbp = nb + (nb & 1);
     double cols = 0.0;
-    for (int r = 0; r < rounds; ++r)
+    for (int r = 0; r < nbp - 1; ++r)
       for (int pr = 0; pr < nbp / 2; ++pr) {
         const int mod = nbp - 1, rr = r % mod;
         const int p = pr == 0 ? rr : (rr + pr) % mod, q = pr == 0 ? nbp - 1 : (rr - pr + mod) % mod;
@@ -473,9 +478,8 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
   DevBuf hpart((size_t)nmat * npair_max * ntile_max * JC * JC * sizeof(double2));
   DevBuf jbuf((size_t)nmat * npair_max * JC * JC * sizeof(double2));
   DevBuf rotf((size_t)nmat * npair_max * sizeof(int));
-  // relative orthogonality reachable in floating point is ~ sqrt(n) eps (the
-  // stopping rule of LAPACK's one-sided Jacobi)
-  const double tol = 4.0 * sqrt((double)nmax) * 2.220446049250313e-16;
+  // rotation threshold 4 sqrt(n) eps, n of each matrix (set in the kernel)
+  const double tol = 4.0 * 2.220446049250313e-16;
   const int max_sweeps = 40;
   const bool dbg = getenv("MFS_DEBUG") != nullptr;
   int sweep = 0;

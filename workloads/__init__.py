@@ -174,6 +174,17 @@ def periodic_k10(nwaves: int = 8) -> Problem:
                    gmres_tol=1e-10)
 
 
+def serving_stream(count: int, seed_dirs: int = 4, seed_arrivals: int = 40):
+    """Request stream of the serving configuration against the k = 10
+    operator: incidences theta ~ U[0, pi/2), phi ~ U[0, 2 pi) from seed 4
+    (near-Wood draws redrawn), and unit-rate exponential inter-arrival gaps
+    from seed 40 (scale them by 1/rate for a Poisson stream of that rate)."""
+    pr = periodic_k10(1)
+    waves = sample_waves(pr.body.k, pr.lattice, count, seed=seed_dirs)
+    gaps = np.random.default_rng(seed_arrivals).exponential(1.0, size=count)
+    return waves, gaps
+
+
 def tiny_free_space() -> Problem:
     """A small sphere case for fast CPU tests: a = 0.5, k = 2, N = 16,
     M = 20 (Gauss), P = 8, q = 48."""
