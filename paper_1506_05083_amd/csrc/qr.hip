@@ -193,9 +193,12 @@ __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__
 __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, double2 *&B, int &ldb,
                                 int &nb_cols) {
   if (which == 0) {
-    B = d.a + (size_t)(k0 + nbp) * d.lda;
-    ldb = d.lda;
     nb_cols = d.n - k0 - nbp;
+    // after the last panel there are no trailing columns and column k0 + nbp
+    // is past the end of the matrix; masked loads (ld_or0) still read B[0],
+    // so B then points at the matrix's first column instead
+    B = d.a + (size_t)(nb_cols > 0 ? k0 + nbp : 0) * d.lda;
+    ldb = d.lda;
   } else {
     B = d.u;
     ldb = ldu_of(d);
