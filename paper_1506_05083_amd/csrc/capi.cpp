@@ -314,21 +314,24 @@ mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbod
     upload(b->srho, src.srho, src.N * sizeof(double), op->stream);
     upload(b->sz, src.sz, src.N * sizeof(double), op->stream);
     b->blocks.alloc((size_t)b->nd * src.N * b->ldA * sizeof(double2));
-    hipEvent_t f0, f1;
-    HIP_CHECK(hipEventCreate(&f0));
-    HIP_CHECK(hipEventCreate(&f1));
-    HIP_CHECK(hipEventRecord(f0, op->stream));
-    launch_fill(*b, op->stream);
-    HIP_CHECK(hipEventRecord(f1, op->stream));
-    HIP_CHECK(hipEventSynchronize(f1));
-    float fms = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&fms, f0, f1));
-    op->ms_fill += fms;
-    (void)hipEventDestroy(f0);
-    (void)hipEventDestroy(f1);
     source_points(*b, b->P, b->src_P, op->stream);
     op->bodies.push_back(std::move(b));
   }
+  // every body's distinct blocks in one persistent launch
+  std::vector<BodyData *> all;
+  for (auto &bp : op->bodies) all.push_back(bp.get());
+  hipEvent_t f0, f1;
+  HIP_CHECK(hipEventCreate(&f0));
+  HIP_CHECK(hipEventCreate(&f1));
+  HIP_CHECK(hipEventRecord(f0, op->stream));
+  launch_fill_all(all, op->stream);
+  HIP_CHECK(hipEventRecord(f1, op->stream));
+  HIP_CHECK(hipEventSynchronize(f1));
+  float fms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&fms, f0, f1));
+  op->ms_fill = fms;
+  (void)hipEventDestroy(f0);
+  (void)hipEventDestroy(f1);
   HIP_CHECK(hipStreamSynchronize(op->stream));
   *out = op.release();
   MFS_API_END
@@ -353,43 +356,87 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   MFS_REQUIRE(rel_cutoff >= 0.0 && rel_cutoff < 1.0, "rel_cutoff must be in [0, 1)");
   if (op->factored) MFS_THROW(MFS_ESTATE, "operator already factored");
   HIP_CHECK(hipSetDevice(op->ctx->device));
-  // every distinct block of every body in one batched pseudoinverse
-  std::vector<MatDesc> in;
-  for (auto &bp : op->bodies) {
-    BodyData &b = *bp;
+  hipStream_t s = op->stream;
+  // every distinct block of every body, the widest first, in batched chunks
+  // whose factorisation work fits in half of the free device memory
+  struct Item {
+    int body, d;
+    MatDesc m;
+    double bytes;
+  };
+  std::vector<Item> items;
+  for (int bi = 0; bi < (int)op->bodies.size(); ++bi) {
+    BodyData &b = *op->bodies[bi];
     for (int d = 0; d < b.nd; ++d) {
-      MatDesc m{};
-      m.a = b.blocks.as<double2>() + (size_t)d * b.N * b.ldA;
-      m.m = b.M;
-      m.n = b.N;
-      m.lda = b.ldA;
-      in.push_back(m);
+      Item it{};
+      it.body = bi;
+      it.d = d;
+      it.m.a = b.blocks.as<double2>() + (size_t)d * b.N * b.ldA;
+      it.m.m = b.M;
+      it.m.n = b.N;
+      it.m.lda = b.ldA;
+      // copies of the block and of U, the triangles and Jacobi factors, W
+      it.bytes = (3.0 * b.ldA * b.N + 8.0 * (double)b.N * b.N) * sizeof(double2);
+      items.push_back(it);
     }
   }
+  std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.m.n > y.m.n; });
+  size_t fr = 0, tot = 0;
+  HIP_CHECK(hipMemGetInfo(&fr, &tot));
+  const double budget = std::max(0.45 * (double)fr, (double)(1ull << 30));
   for (int i = 0; i < 3; ++i)
     if (!op->ev[i]) HIP_CHECK(hipEventCreate(&op->ev[i]));
-  op->gp = std::make_unique<GradedPinv>();
-  op->gp->ev_qr_done = op->ev[1];
-  HIP_CHECK(hipEventRecord(op->ev[0], op->stream));
-  graded_pinv(*op->gp, in, rel_cutoff, op->stream);
-  HIP_CHECK(hipEventRecord(op->ev[2], op->stream));
-  HIP_CHECK(hipStreamSynchronize(op->stream));
-  float ms_qr = 0, ms_svd = 0;
-  HIP_CHECK(hipEventElapsedTime(&ms_qr, op->ev[0], op->ev[1]));
-  HIP_CHECK(hipEventElapsedTime(&ms_svd, op->ev[1], op->ev[2]));
-  op->ms_qr = ms_qr;
-  op->ms_svd = ms_svd;
-  size_t bi = 0;
+  for (auto &bp : op->bodies) {
+    bp->h_descs.assign(bp->nd, MatDesc{});
+    bp->rank.assign(bp->nd, 0);
+    bp->h_sv.assign((size_t)bp->nd * bp->N, 0.0);
+  }
+  op->gps.clear();
+  op->ms_qr = op->ms_svd = 0.0;
+  size_t c0 = 0;
+  while (c0 < items.size()) {
+    size_t c1 = c0 + 1;
+    double used = items[c0].bytes;
+    while (c1 < items.size() && c1 - c0 < 60000 && used + items[c1].bytes <= budget) used += items[c1++].bytes;
+    std::vector<MatDesc> in;
+    for (size_t i = c0; i < c1; ++i) in.push_back(items[i].m);
+    auto g = std::make_unique<GradedPinv>();
+    g->ev_qr_done = op->ev[1];
+    HIP_CHECK(hipEventRecord(op->ev[0], s));
+    graded_pinv(*g, in, rel_cutoff, s);
+    HIP_CHECK(hipEventRecord(op->ev[2], s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    float ms_qr = 0, ms_svd = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms_qr, op->ev[0], op->ev[1]));
+    HIP_CHECK(hipEventElapsedTime(&ms_svd, op->ev[1], op->ev[2]));
+    op->ms_qr += ms_qr;
+    op->ms_svd += ms_svd;
+    for (size_t i = c0; i < c1; ++i) {
+      const Item &it = items[i];
+      BodyData &b = *op->bodies[it.body];
+      b.h_descs[it.d] = g->h_fin[i - c0];
+      b.rank[it.d] = g->kept[i - c0];
+      // the Jacobi factor holds the r leading singular values; the rest are
+      // below 1e-15 of the largest and stay zero
+      const MatDesc &l = g->h_lq[i - c0];
+      HIP_CHECK(hipMemcpy(b.h_sv.data() + (size_t)it.d * b.N, l.sv, std::min(l.n, b.N) * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    }
+    g->release_work();
+    op->gps.push_back(std::move(g));
+    c0 = c1;
+  }
+  size_t off = 0;
   for (auto &bp : op->bodies) {
     BodyData &b = *bp;
-    b.h_descs.assign(op->gp->h_fin.begin() + bi, op->gp->h_fin.begin() + bi + b.nd);
-    b.rank.assign(op->gp->kept.begin() + bi, op->gp->kept.begin() + bi + b.nd);
     b.descs.alloc(b.nd * sizeof(MatDesc));
-    upload(b.descs.p, b.h_descs.data(), b.nd * sizeof(MatDesc), op->stream);
-    bi += b.nd;
+    upload(b.descs.p, b.h_descs.data(), b.nd * sizeof(MatDesc), s);
+    if (ranks) std::copy(b.rank.begin(), b.rank.end(), ranks + off);
+    off += b.nd;
   }
-  HIP_CHECK(hipStreamSynchronize(op->stream));
-  if (ranks) std::copy(op->gp->kept.begin(), op->gp->kept.end(), ranks);
+  HIP_CHECK(hipStreamSynchronize(s));
+  // the factors are all the apply reads: the filled blocks are released
+  for (auto &bp : op->bodies) bp->blocks.release();
   op->factored = true;
   op->cutoff = rel_cutoff;
   MFS_API_END
@@ -416,15 +463,7 @@ mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out) {
   BodyData &b = body_of(op, body);
   if (!op->factored) MFS_THROW(MFS_ESTATE, "operator not factored");
   MFS_REQUIRE(out != nullptr, "null output");
-  size_t bi = 0;
-  for (int i = 0; i < body; ++i) bi += op->bodies[i]->nd;
-  for (int d = 0; d < b.nd; ++d) {
-    const MatDesc &l = op->gp->h_lq[bi + d];
-    std::fill(out + (size_t)d * b.N, out + (size_t)(d + 1) * b.N, 0.0);
-    // the Jacobi factor holds the r leading singular values; the rest are
-    // below 1e-15 of the largest and reported as zero
-    HIP_CHECK(hipMemcpy(out + (size_t)d * b.N, l.sv, std::min(l.n, b.N) * sizeof(double), hipMemcpyDeviceToHost));
-  }
+  std::copy(b.h_sv.begin(), b.h_sv.end(), out);
   MFS_API_END
 }
 

@@ -20,7 +20,7 @@ struct mfs_op {
   std::vector<std::unique_ptr<mfs::BodyData>> bodies;
   bool factored = false;
   double cutoff = 1e-10;
-  std::unique_ptr<mfs::GradedPinv> gp;   // factors of all distinct blocks
+  std::vector<std::unique_ptr<mfs::GradedPinv>> gps;   // factors of the distinct blocks, by chunk
   mfs::DevBuf work;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double ms_fill = 0.0, ms_qr = 0.0, ms_svd = 0.0;

@@ -17,6 +17,8 @@
 // the chunk into its P/2+1 (strided by 4) mode accumulators using the
 // cosine weights staged from a per-operator table.  FP64 VALU bound: one
 // rsqrt and one sincos per kernel sample.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mfs {
@@ -46,30 +48,33 @@ __global__ void fill_table_kernel(int q, int nd, double *tab) {
   }
 }
 
-__global__ __launch_bounds__(256) void fill_kernel(int M, int N, int q, int nd, int ldA, double k,
-                                                   const double *__restrict__ rho,
-                                                   const double *__restrict__ zc,
-                                                   const double *__restrict__ nrho,
-                                                   const double *__restrict__ nzc,
-                                                   const double *__restrict__ srho,
-                                                   const double *__restrict__ szc,
-                                                   const double *__restrict__ tab,
-                                                   double2 *__restrict__ A) {
-  __shared__ double2 gs[LC][TP];
-  __shared__ double wt[LC * 105];
+// One body's share of the batched fill.
+struct FillJob {
+  int M, N, q, nd, ldA;
+  double k;
+  const double *rho, *z, *nrho, *nz, *srho, *sz;
+  const double *tab;
+  double2 *A;
+  long tile0;      // first tile of this body in the batch's tile list
+};
+
+// Tile `tile` (64 (m, j) pairs) of job J; all 256 threads take part.
+__device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double *wt) {
+  const int M = J.M, N = J.N, q = J.q, nd = J.nd, ldA = J.ldA;
+  const double k = J.k;
   const int tid = threadIdx.x;
   const int pl = tid & 63;
   const int grp = tid >> 6;   // wave index: uniform within a wave
-  const long pair = (long)blockIdx.x * TP + pl;
+  const long pair = tile * TP + pl;
   const bool valid = pair < (long)M * N;
   const int m = valid ? (int)(pair % M) : 0;
   const int j = valid ? (int)(pair / M) : 0;
-  const double r = rho[m], rs = srho[j];
-  const double dz = zc[m] - szc[j];
+  const double r = J.rho[m], rs = J.srho[j];
+  const double dz = J.z[m] - J.sz[j];
   const double Ac = r * r + rs * rs + dz * dz;
   const double Bc = 2.0 * r * rs;
-  const double Cc = r * nrho[m] + dz * nzc[m];
-  const double Dc = rs * nrho[m];
+  const double Cc = r * J.nrho[m] + dz * J.nz[m];
+  const double Dc = rs * J.nrho[m];
   const double inv4pi = 0.25 / kPi;
   const int L = q / 2 + 1;
   const int ld = nd + 1;
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(256) void fill_kernel(int M, int N, int q, int nd, 
   for (int l0 = 0; l0 < L; l0 += LC) {
     const int lc = min(LC, L - l0);
     __syncthreads();
-    for (int idx = tid; idx < lc * ld; idx += 256) wt[idx] = tab[(size_t)l0 * ld + idx];
+    for (int idx = tid; idx < lc * ld; idx += 256) wt[idx] = J.tab[(size_t)l0 * ld + idx];
     __syncthreads();
     for (int ll = grp; ll < LC; ll += 4) {
       double2 g = cz(0.0, 0.0);
@@ -114,11 +119,44 @@ __global__ __launch_bounds__(256) void fill_kernel(int M, int N, int q, int nd, 
       }
     }
   }
-  if (!valid) return;
+  if (valid) {
 #pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    const int n = grp + 4 * s;
-    if (n < nd) A[((size_t)n * N + j) * ldA + m] = acc[s];
+    for (int s = 0; s < MAXS; ++s) {
+      const int n = grp + 4 * s;
+      if (n < nd) J.A[((size_t)n * N + j) * ldA + m] = acc[s];
+    }
+  }
+}
+
+// Persistent fill of every body of a batch: a fixed grid of workgroups takes
+// tiles from a global counter until the batch's ntiles are done (jobs are in
+// order of tile0, the costliest bodies first, so the tail is made of cheap
+// tiles).  Every workgroup leaves once the counter passes ntiles.
+__global__ __launch_bounds__(256) void fill_batch_kernel(const FillJob *__restrict__ jobs, int njobs,
+                                                         long ntiles, unsigned long long *__restrict__ counter) {
+  __shared__ double2 gs[LC][TP];
+  __shared__ double wt[LC * 105];
+  __shared__ long s_tile;
+  __shared__ int s_job;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const long t = (long)atomicAdd(counter, 1ULL);
+      int lo = 0, hi = njobs - 1;   // last job with tile0 <= t
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      s_tile = t;
+      s_job = lo;
+    }
+    __syncthreads();
+    const long t = s_tile;
+    const int jb = s_job;
+    __syncthreads();   // s_tile / s_job read by all before thread 0 overwrites them
+    if (t >= ntiles) return;
+    const FillJob J = jobs[jb];
+    fill_tile(J, t - J.tile0, gs, wt);
   }
 }
 
@@ -178,21 +216,48 @@ __global__ __launch_bounds__(256) void rhs_kernel(int M, int P, const double *__
 
 }  // namespace
 
-void launch_fill(BodyData &b, hipStream_t s) {
-  MFS_REQUIRE(b.nd <= 4 * MAXS, "P/2+1 exceeds the fill kernel's mode capacity (P <= 206)");
-  const int L = b.q / 2 + 1;
-  DevBuf tab((size_t)L * (b.nd + 1) * sizeof(double));
-  hipLaunchKernelGGL(fill_table_kernel, dim3(cdiv(L * (b.nd + 1), 256)), dim3(256), 0, s, b.q,
-                     b.nd, tab.as<double>());
+void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s) {
+  const int nb = (int)bodies.size();
+  if (nb == 0) return;
+  std::vector<int> order(nb);
+  for (int i = 0; i < nb; ++i) order[i] = i;
+  // costliest first: work of a pair ~ (q/2+1)(P/2+1)
+  auto cost = [&](int i) { return (double)(bodies[i]->q / 2 + 1) * (bodies[i]->nd + 1); };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<DevBuf> tabs(nb);
+  std::vector<FillJob> jobs(nb);
+  long tiles = 0;
+  for (int o = 0; o < nb; ++o) {
+    BodyData &b = *bodies[order[o]];
+    MFS_REQUIRE(b.nd <= 4 * MAXS, "P/2+1 exceeds the fill kernel's mode capacity (P <= 206)");
+    const int L = b.q / 2 + 1;
+    tabs[o].alloc((size_t)L * (b.nd + 1) * sizeof(double));
+    hipLaunchKernelGGL(fill_table_kernel, dim3(cdiv(L * (b.nd + 1), 256)), dim3(256), 0, s, b.q, b.nd,
+                       tabs[o].as<double>());
+    FillJob &J = jobs[o];
+    J.M = b.M; J.N = b.N; J.q = b.q; J.nd = b.nd; J.ldA = b.ldA; J.k = b.k;
+    J.rho = b.rho; J.z = b.z; J.nrho = b.nrho; J.nz = b.nz; J.srho = b.srho; J.sz = b.sz;
+    J.tab = tabs[o].as<double>();
+    J.A = b.blocks.as<double2>();
+    J.tile0 = tiles;
+    tiles += ((long)b.M * b.N + TP - 1) / TP;
+  }
   HIP_CHECK(hipGetLastError());
-  const long npair = (long)b.M * b.N;
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdiv((int)npair, TP)), dim3(256), 0, s, b.M, b.N,
-                     b.q, b.nd, b.ldA, b.k, b.rho, b.z, b.nrho, b.nz, b.srho, b.sz,
-                     tab.as<double>(), b.blocks.as<double2>());
+  DevBuf jd(jobs.size() * sizeof(FillJob)), ctr(sizeof(unsigned long long));
+  HIP_CHECK(hipMemcpyAsync(jd.p, jobs.data(), jobs.size() * sizeof(FillJob), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemsetAsync(ctr.p, 0, sizeof(unsigned long long), s));
+  int dev = 0, ncu = 256;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const long grid = std::min<long>(tiles, (long)ncu * 4);
+  hipLaunchKernelGGL(fill_batch_kernel, dim3((unsigned)grid), dim3(256), 0, s, jd.as<FillJob>(), nb, tiles,
+                     ctr.as<unsigned long long>());
   HIP_CHECK(hipGetLastError());
-  // the table is freed on return; make sure the kernels are done with it
+  // the tables and job list are freed on return; make sure the kernel is done with them
   HIP_CHECK(hipStreamSynchronize(s));
 }
+
+void launch_fill(BodyData &b, hipStream_t s) { launch_fill_all({&b}, s); }
 
 void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out, hipStream_t s) {
   const size_t sh = (size_t)(b.P + RM * b.P) * sizeof(double2);

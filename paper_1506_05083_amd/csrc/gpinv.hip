@@ -355,6 +355,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
                      g.perm.as<int>(), nmax);
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
+  if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
   // 3. column-pivoted QR of the n2 x n2 triangle
   g.rq.resize(W);
   g.h_rq.resize(W);
@@ -395,7 +396,6 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(build_t_kernel, dim3(W, cdiv(n2max, kQRNB)), dim3(256), 0, s, g.d_rq.as<MatDesc>());
     HIP_CHECK(hipGetLastError());
-    if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
     HIP_CHECK(hipStreamSynchronize(s));   // qn is released here
   }
   // 3. rows of R to keep

@@ -17,7 +17,7 @@ struct GradedPinv {
   std::vector<MatDesc> h_qc, h_rq, h_rqu, h_lq, h_fin;
   std::vector<double> maxcol;
   std::vector<int> cols, rows, kept;
-  hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the two QR stages
+  hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the unpivoted blocked QR
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;
   double jacobi_bytes = 0.0;

@@ -61,11 +61,14 @@ struct BodyData {
   DevBuf descs;       // MatDesc[nd] on device
   std::vector<MatDesc> h_descs;
   std::vector<int> rank;
+  std::vector<double> h_sv;   // [nd][N] singular values after mfs_factor_modes (descending, zero-filled)
   DevBuf src_P;       // point sources at q = P angles, SoA x y z [P*N] each
 };
 
 // ---------------------------------------------------------- launchers
 void launch_fill(BodyData &b, hipStream_t s);
+// every body's blocks in one persistent launch (work queue of 64-pair tiles)
+void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s);
 void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out, hipStream_t s);
 // out[r][b][x] = scale * sum_l in[r][l][x] e^{sgn 2 pi i b l / P}, r < nr, x < X
 void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, double scale,

@@ -118,6 +118,44 @@ def test_factor_singular_values_and_ranks(mfs, ctx):
     log(f"[factor] ranks {list(ranks)}")
 
 
+def test_batched_build_uneven_bodies(mfs, ctx):
+    """Several obstacles of uneven M, N, P, q and k filled in one persistent
+    launch and factored in one batch: every body's singular values and its
+    free-space field (RHS, apply, point-source field) against the oracle."""
+    bodies = [W.Body(W.Shape(0.3, 0.1, 3), N=40, M=48, P=24, q=160, k=5.0, tau=0.2),
+              W.Body(W.Shape(0.25, 0.05, 2), N=30, M=36, P=16, q=120, k=7.0, tau=0.15),
+              W.Body(W.Shape(0.35), N=24, M=30, P=8, q=96, k=3.0, tau=0.2)]
+    specs = []
+    for b in bodies:
+        sh = b.shape
+        g = mfs.polar_geometry(sh.a, sh.eps, sh.j, b.M, b.N, b.tau, b.colloc)
+        specs.append(mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, g))
+    op = mfs.build_operator(ctx, specs)
+    ranks = op.factor_modes(1e-10)
+    off = 0
+    tg = W.fibonacci_sphere(16, 2.0)
+    for i, b in enumerate(bodies):
+        g = geometry.build_geometry(b)
+        A = onebody.modal_blocks(b, g)
+        sv = op.singular_values(i)
+        worst = 0.0
+        for n in range(b.P // 2 + 1):
+            s = np.linalg.svd(A[n], compute_uv=False)
+            worst = max(worst, float(np.max(np.abs(sv[n] - s)) / s[0]))
+            assert abs(int(ranks[off + n]) - int(np.sum(s > 1e-10 * s[0]))) <= 1, (i, n)
+        off += b.P // 2 + 1
+        w = W.sample_waves(b.k, None, 1, seed=20 + i)[0]
+        kv = W.wave_vector(b.k, w)[None, :]
+        fh = mfs.rhs_modes(op, kv, body=i)
+        c = mfs.apply_solution_op(op, fh, body=i)
+        u = mfs.field_free(op, c, 2 * b.P, tg, body=i).cpu().numpy()[0]
+        co = onebody.solve_modes(A, onebody.rhs_modes(b, g, w))
+        uo = onebody.field(b, g, co, tg, 2 * b.P)
+        err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+        log(f"[batch] body {i}: N={b.N} M={b.M} P={b.P} sv err {worst:.2e} field err {err:.2e}")
+        assert worst < 1e-13 and err < 1e-10
+
+
 @pytest.mark.parametrize("name", ["tiny", "sphere"])
 def test_free_space_fields(mfs, ctx, name):
     """Whole one-body path on the GPU (fill, QR + Jacobi truncation, RHS,

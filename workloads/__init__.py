@@ -185,6 +185,43 @@ def serving_stream(count: int, seed_dirs: int = 4, seed_arrivals: int = 40):
     return waves, gaps
 
 
+def even_5smooth_at_least(x: float) -> int:
+    """Smallest even 2^a 3^b 5^c >= x (a length the angle FFTs factor well)."""
+    n = max(2, int(math.ceil(x)))
+    while True:
+        if n % 2 == 0:
+            r = n
+            for f in (2, 3, 5):
+                while r % f == 0:
+                    r //= f
+            if r == 1:
+                return n
+        n += 1
+
+
+def batch_obstacles(count: int = 256, seed: int = 3) -> List[Body]:
+    """Batched-build configuration: `count` independent obstacles, each drawn
+    in this order from seed 3: a ~ U[0.2, 0.4], eps ~ U[0, 0.15],
+    j ~ U{2..5}, N ~ U{100..600}, P ~ U{32, 64, 96, 128, 160},
+    k ~ U[5, 30]; M = ceil(1.2 N), midpoint collocation, tau = 0.1, and
+    q the smallest even 5-smooth length >= max(P, P/2 + 370) (the fill
+    convergence of the k = 10 body at tau = 0.1 with the margin of P/2
+    for the highest mode)."""
+    rng = np.random.default_rng(seed)
+    out: List[Body] = []
+    for _ in range(count):
+        a = float(rng.uniform(0.2, 0.4))
+        eps = float(rng.uniform(0.0, 0.15))
+        j = int(rng.integers(2, 6))
+        N = int(rng.integers(100, 601))
+        P = int(rng.choice([32, 64, 96, 128, 160]))
+        k = float(rng.uniform(5.0, 30.0))
+        M = int(math.ceil(1.2 * N))
+        q = even_5smooth_at_least(max(P, P / 2 + 370))
+        out.append(Body(Shape(a, eps, j), N=N, M=M, P=P, q=q, k=k, tau=0.1, colloc="mid"))
+    return out
+
+
 def tiny_free_space() -> Problem:
     """A small sphere case for fast CPU tests: a = 0.5, k = 2, N = 16,
     M = 20 (Gauss), P = 8, q = 48."""
