@@ -282,6 +282,19 @@ mfs_status mfs_polar_geometry(const mfs_polar_spec *spec, double *rho, double *z
   MFS_API_END
 }
 
+mfs_status mfs_cup_geometry(const mfs_cup_spec *spec, double *rho, double *z, double *nrho, double *nz,
+                            double *srho, double *sz) {
+  MFS_API_BEGIN
+  MFS_REQUIRE(spec && rho && z && nrho && nz && srho && sz, "null pointer");
+  MFS_REQUIRE(spec->M > 0 && spec->N > 0, "bad cup spec: M and N must be positive");
+  MFS_REQUIRE(spec->outer > 0 && spec->half > 0 && spec->half < 1 && spec->b > 0 && spec->b < kPi,
+              "bad cup spec: need outer > 0, 0 < half < 1, 0 < b < pi");
+  MFS_REQUIRE(spec->tau >= 0 && spec->tau <= spec->half, "bad cup spec: need 0 <= tau <= half");
+  MFS_REQUIRE(spec->colloc == 0 || spec->colloc == 1, "colloc must be 0 or 1");
+  cup_geometry(*spec, rho, z, nrho, nz, srho, sz);
+  MFS_API_END
+}
+
 mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbodies, void *stream,
                               mfs_op **out) {
   MFS_API_BEGIN
@@ -403,7 +416,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
     auto g = std::make_unique<GradedPinv>();
     g->ev_qr_done = op->ev[1];
     HIP_CHECK(hipEventRecord(op->ev[0], s));
-    graded_pinv(*g, in, rel_cutoff, s);
+    graded_pinv(*g, in, rel_cutoff, true, s);
     HIP_CHECK(hipEventRecord(op->ev[2], s));
     HIP_CHECK(hipStreamSynchronize(s));
     float ms_qr = 0, ms_svd = 0;

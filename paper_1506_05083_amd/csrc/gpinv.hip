@@ -5,27 +5,32 @@
 //
 //  1. columns with norm below 1e-15 of the largest are set aside (their
 //     coefficients are zero; the perturbation is below the SVD's own
-//     rounding level eps*sqrt(n)*s_max);
-//  2. blocked Householder QR without pivoting, Q = Q_1 R_1, which takes the
-//     tall matrix (7200 rows for the k = 10 periodizer) down to its n2 x n2
-//     triangle with matrix-product work;
-//  3. Householder QR with column pivoting of the triangle, R_1 P = Q_2 R (the
-//     largest remaining column moves to the front at every step; unblocked,
-//     one pivot/reflector launch and one trailing-update launch per column,
-//     the partial column norms recomputed exactly by the update; the pivots
-//     are those of pivoted QR of Q itself, since R_1 and Q have the same
-//     column inner products), compact-WY T factors per 32-column panel;
-//     trailing rows of R whose joint Frobenius norm is below 1e-15 of the
-//     largest column norm are dropped: R ~ R_top (r x n2);
-//  4. LQ of R_top via QR of R_top^H = Z L^H;
-//  5. one-sided Jacobi SVD of the r x r factor L = U_L S V_L^H, truncated at
+//     rounding level eps*sqrt(n)*s_max), and the rest are ordered by
+//     decreasing norm;
+//  2. blocked Householder QR without pivoting of the ordered columns,
+//     Q P = Q_1 R_1, which takes the tall matrix (7200 rows for the k = 10
+//     periodizer) down to its n2 x n2 triangle with matrix-product work;
+//     optionally (`pivot`) a column-pivoted Householder QR of that
+//     triangle, R_1 P_2 = Q_2 R (the largest remaining column moves to the
+//     front at every step: one pivot/reflector launch and one trailing
+//     update launch per column, compact-WY T factors per 32-column panel);
+//     trailing rows of the triangle (R_1, or R) whose joint Frobenius norm
+//     is below 1e-15 of the largest column norm are dropped: ~ R_top (r x n2);
+//  3. LQ of R_top via QR of R_top^H = Z L^H;
+//  4. one-sided Jacobi SVD of the r x r factor L = U_L S V_L^H, truncated at
 //     rel_cutoff * s_max as in the paper;
-//  6. Q^+ = P (Z V_L S^{-1}) (Q_1 [Q_2 [U_L; 0]; 0])^H: U and
-//     W = P Z V_L S^{-1} are formed explicitly for the two-stage apply.
-// Column-pivoted QR followed by LQ is the standard preconditioning that makes
-// one-sided Jacobi converge in a handful of sweeps (7 instead of ~30 on the
-// per-mode MFS blocks); the result is the same truncated pseudoinverse the
-// paper prescribes, to rounding.
+//  5. Q^+ = P (Z V_L S^{-1}) (Q_1 [U_L; 0])^H, with Q_2 and P_2 in between
+//     when pivoting: U and W = P Z V_L S^{-1} are formed explicitly for the
+//     two-stage apply.
+// Ordering and LQ are the preconditioning that makes one-sided Jacobi
+// converge in a handful of sweeps.  For the strongly graded periodizer the
+// norm ordering alone does it (10 sweeps on the k = 10 Q, as with the
+// pivoted triangle, against no convergence in 40 without the ordering), and
+// the unblocked pivoted QR, O(n^3) in matrix-vector steps, would not scale
+// to its ~10^4 columns at high k.  The per-mode MFS blocks are
+// rank-deficient without being graded by column, and there the pivoted
+// triangle cuts the Jacobi work by about 3x.  Either way the result is the
+// same truncated pseudoinverse the paper prescribes, to rounding.
 #include <algorithm>
 #include <cmath>
 
@@ -298,7 +303,7 @@ static void upload_descs(DevBuf &buf, const std::vector<MatDesc> &h, hipStream_t
   HIP_CHECK(hipMemcpyAsync(buf.p, h.data(), h.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
 }
 
-void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, hipStream_t s) {
+void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, bool pivot, hipStream_t s) {
   const int W = (int)in.size();
   int nmax = 0, mmax = 0;
   for (auto &d : in) { nmax = std::max(nmax, d.n); mmax = std::max(mmax, d.m); }
@@ -315,12 +320,15 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.maxcol.assign(W, 0.0);
   for (int w = 0; w < W; ++w) {
     const int n = in[w].n;
+    const double *nw = hn.data() + (size_t)w * nmax;
     double mx = 0.0;
-    for (int c = 0; c < n; ++c) mx = std::max(mx, hn[(size_t)w * nmax + c]);
+    for (int c = 0; c < n; ++c) mx = std::max(mx, nw[c]);
     g.maxcol[w] = mx;
     std::vector<int> idx;
     for (int c = 0; c < n; ++c)
-      if (hn[(size_t)w * nmax + c] >= 1e-15 * mx && mx > 0.0) idx.push_back(c);
+      if (nw[c] >= 1e-15 * mx && mx > 0.0) idx.push_back(c);
+    // largest norm first; ties keep their column order
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return nw[x] > nw[y]; });
     n2[w] = (int)idx.size();
     MFS_REQUIRE(n2[w] >= 1, "graded pseudoinverse: matrix is zero");
     MFS_REQUIRE(n2[w] <= in[w].m, "graded pseudoinverse: more independent columns than rows");
@@ -328,7 +336,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   }
   g.perm.alloc(perm.size() * sizeof(int));
   HIP_CHECK(hipMemcpyAsync(g.perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  int n2max = *std::max_element(n2.begin(), n2.end());
+  const int n2max = *std::max_element(n2.begin(), n2.end());
   // 2. QR without pivoting of the selected, ordered columns
   g.qc.resize(W);
   g.h_qc.resize(W);
@@ -356,36 +364,41 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
   if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
-  // 3. column-pivoted QR of the n2 x n2 triangle
-  g.rq.resize(W);
-  g.h_rq.resize(W);
-  for (int w = 0; w < W; ++w) {
-    const int n = n2[w], ldr = round_up(n, 16);
-    const int npan = cdiv(n, kQRNB);
-    auto &st = g.rq[w];
-    st.a.alloc((size_t)ldr * n * sizeof(double2));
-    st.fac.alloc(((size_t)n + (size_t)npan * kQRNB * kQRNB) * sizeof(double2));
-    MatDesc d{};
-    double2 *p = st.fac.as<double2>();
-    d.a = st.a.as<double2>(); d.m = n; d.n = n; d.lda = ldr;
-    d.tau = p; p += n;
-    d.T = p;
-    d.flag = flags + 3 * W + w;
-    d.rank = flags + W + w;
-    g.h_rq[w] = d;
-  }
-  upload_descs(g.d_rq, g.h_rq, s);
-  hipLaunchKernelGGL(copy_r_kernel, dim3(1024, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_rq.as<MatDesc>());
-  HIP_CHECK(hipGetLastError());
+  // the triangle that the row selection and the LQ read: R_1, or with
+  // pivoting R from the column-pivoted QR R_1 P_2 = Q_2 R
+  const MatDesc *tri = g.d_qc.as<MatDesc>();
   {
-    DevBuf qn((size_t)W * nmax * sizeof(double));
-    hipLaunchKernelGGL(colnorm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
-                       qn.as<double>(), nmax);
     std::vector<int> ident((size_t)W * nmax);
     for (int w = 0; w < W; ++w)
       for (int i = 0; i < nmax; ++i) ident[(size_t)w * nmax + i] = i;
     g.piv.alloc(ident.size() * sizeof(int));
     HIP_CHECK(hipMemcpyAsync(g.piv.p, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  if (pivot) {
+    g.rq.resize(W);
+    g.h_rq.resize(W);
+    for (int w = 0; w < W; ++w) {
+      const int n = n2[w], ldr = round_up(n, 16);
+      const int npan = cdiv(n, kQRNB);
+      auto &st = g.rq[w];
+      st.a.alloc((size_t)ldr * n * sizeof(double2));
+      st.fac.alloc(((size_t)n + (size_t)npan * kQRNB * kQRNB) * sizeof(double2));
+      MatDesc d{};
+      double2 *p = st.fac.as<double2>();
+      d.a = st.a.as<double2>(); d.m = n; d.n = n; d.lda = ldr;
+      d.tau = p; p += n;
+      d.T = p;
+      d.flag = flags + 3 * W + w;
+      d.rank = flags + W + w;
+      g.h_rq[w] = d;
+    }
+    upload_descs(g.d_rq, g.h_rq, s);
+    hipLaunchKernelGGL(copy_r_kernel, dim3(1024, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_rq.as<MatDesc>());
+    HIP_CHECK(hipGetLastError());
+    DevBuf qn((size_t)W * nmax * sizeof(double));
+    hipLaunchKernelGGL(colnorm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
+                       qn.as<double>(), nmax);
     for (int k = 0; k < n2max; ++k) {
       hipLaunchKernelGGL(qrcp_pivot_kernel, dim3(W), dim3(PK), 0, s, g.d_rq.as<MatDesc>(), k, qn.as<double>(),
                          g.piv.as<int>(), nmax);
@@ -397,11 +410,11 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     hipLaunchKernelGGL(build_t_kernel, dim3(W, cdiv(n2max, kQRNB)), dim3(256), 0, s, g.d_rq.as<MatDesc>());
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));   // qn is released here
+    tri = g.d_rq.as<MatDesc>();
   }
-  // 3. rows of R to keep
+  // rows of the triangle to keep
   DevBuf rn((size_t)W * n2max * sizeof(double));
-  hipLaunchKernelGGL(rownorm_kernel, dim3(cdiv(n2max, 256), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
-                     rn.as<double>(), n2max);
+  hipLaunchKernelGGL(rownorm_kernel, dim3(cdiv(n2max, 256), W), dim3(256), 0, s, tri, rn.as<double>(), n2max);
   HIP_CHECK(hipGetLastError());
   std::vector<double> hr((size_t)W * n2max);
   HIP_CHECK(hipMemcpyAsync(hr.data(), rn.p, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -419,7 +432,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   }
   g.rows = rr;
   g.cols = n2;
-  // 4. QR of R_top^H (n2 x r)  and  5. Jacobi on L = (R factor)^H
+  // 3. QR of R_top^H (n2 x r)  and  4. Jacobi on L = (R factor)^H
   g.lq.resize(W);
   g.h_lq.resize(W);
   for (int w = 0; w < W; ++w) {
@@ -447,8 +460,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     g.h_lq[w] = d;
   }
   upload_descs(g.d_lq, g.h_lq, s);
-  hipLaunchKernelGGL(transpose_top_kernel, dim3(1024, W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
-                     g.d_lq.as<MatDesc>());
+  hipLaunchKernelGGL(transpose_top_kernel, dim3(1024, W), dim3(256), 0, s, tri, g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_lq.as<MatDesc>(), g.h_lq, s);
   const JacStats js = jac_run(g.d_lq.as<MatDesc>(), g.h_lq, 1, rel_cutoff, s);
@@ -457,21 +469,24 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.jacobi_bytes = js.bytes;
   g.jacobi_flops = js.flops;
   jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
-  // 6. explicit factors
+  // 5. explicit factors
   const int rmax = *std::max_element(rr.begin(), rr.end());
   int kmax = 0;
   for (int k : g.kept) kmax = std::max(kmax, k);
   hipLaunchKernelGGL(prep_uv_kernel, dim3(rmax, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
-  // U = Q_1 [Q_2 [U_L; 0]; 0]: the reflectors of the pivoted triangle act on
-  // the first n2 rows of the left factor, then those of the tall QR
-  g.h_rqu = g.h_rq;
-  for (int w = 0; w < W; ++w) {
-    g.h_rqu[w].u = g.h_qc[w].u;
-    g.h_rqu[w].ldu = g.h_qc[w].lda;
+  // U = Q_1 [U_L; 0], or Q_1 [Q_2 [U_L; 0]; 0] with pivoting (the
+  // reflectors of the pivoted triangle act on the first n2 rows first);
+  // V = Z V_L, before the column orders are undone in W
+  if (pivot) {
+    g.h_rqu = g.h_rq;
+    for (int w = 0; w < W; ++w) {
+      g.h_rqu[w].u = g.h_qc[w].u;
+      g.h_rqu[w].ldu = g.h_qc[w].lda;
+    }
+    upload_descs(g.d_rqu, g.h_rqu, s);
+    qr_form_u(g.d_rqu.as<MatDesc>(), g.h_rqu, kmax, s);
   }
-  upload_descs(g.d_rqu, g.h_rqu, s);
-  qr_form_u(g.d_rqu.as<MatDesc>(), g.h_rqu, kmax, s);
   qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, kmax, s);
   qr_form_u(g.d_lq.as<MatDesc>(), g.h_lq, kmax, s);
   g.fin.resize(W);

@@ -35,7 +35,9 @@ struct GradedPinv {
   }
 };
 
-// in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.
-void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, hipStream_t s);
+// in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.  pivot: take
+// the column-pivoted QR of the triangle before the LQ (per-mode MFS blocks);
+// without it the norm ordering alone preconditions Jacobi (periodizer Q).
+void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, bool pivot, hipStream_t s);
 
 }  // namespace mfs

@@ -121,7 +121,7 @@ struct Solver {
     qdescs.alloc(W * sizeof(MatDesc));
     upload(qdescs.p, h_qdescs.data(), W * sizeof(MatDesc), s);
     HIP_CHECK(hipStreamSynchronize(s));   // ordbufs are released on return
-    graded_pinv(gp, h_qdescs, rel_cutoff, s);
+    graded_pinv(gp, h_qdescs, rel_cutoff, false, s);
     qrank = gp.kept;
     setup_bvals();
   }
