@@ -73,6 +73,22 @@ typedef struct {
   double tau;
 } mfs_polar_spec;
 
+/* Cup generating curve of Fig. 1(c): with u = pi - t, x = u - pi/2,
+ *   r = 1 - half erf(x/half),
+ *   theta = b - half + 2 (1 - (b - half)/pi) s(x),
+ *   s(x) = x erf(x/half) + (half/sqrt(pi)) e^{-x^2/half^2}  (rounded |x|),
+ *   rho = c r sin theta, z = c r cos theta,  c = outer/(1 + half):
+ * a shell of half-thickness `half` about the unit sphere with an opening of
+ * half-angle b about +z, scaled to outer radius `outer`; t = 0 is the inner
+ * bottom pole.  Sources, collocation and tau as for mfs_polar_spec (the
+ * complex erf of the sources is evaluated for tau <= half). */
+typedef struct {
+  double outer, half, b;
+  int32_t colloc;
+  int32_t M, N;
+  double tau;
+} mfs_cup_spec;
+
 /* Rectangular lattice e_x, e_y; unit cell |z| <= z0; periodizer: harmonic
  * degree p, Rayleigh-Bloch cutoff kappa_x^2 + kappa_y^2 <= (pi N0)^2, M1 x M1
  * Gauss nodes per wall (M1 even) (Sec. 4, Sec. 4.1). */
@@ -136,6 +152,12 @@ void mfs_destroy(mfs_ctx *ctx);
  * rho, z, nrho, nz [spec->M] and srho, sz [spec->N] (Sec. 3, Sec. 3.2). */
 mfs_status mfs_polar_geometry(const mfs_polar_spec *spec, double *rho, double *z,
                               double *nrho, double *nz, double *srho, double *sz);
+
+/* Host helper: geometry of the cup (Fig. 1(c)) into the same caller arrays.
+ * EINVAL for outer <= 0, half outside (0, 1), b outside (0, pi), tau outside
+ * [0, half], M or N < 1, or colloc not 0/1; nothing is written then. */
+mfs_status mfs_cup_geometry(const mfs_cup_spec *spec, double *rho, double *z,
+                            double *nrho, double *nz, double *srho, double *sz);
 
 /* (a) Modal fill (eqs. (ringkernelderiv), (ptr)): for each body, the P/2+1
  * distinct blocks A'_n, n = 0..P/2 (A'_{-n} = A'_n) of size M x N,

@@ -2,8 +2,16 @@
 Sec. 3.2 of the paper).
 
 The body is the rotation about the z axis of a curve (rho(t), z(t)),
-t in [0, pi], with z'(0) = z'(pi) = 0 (Sec. 3, start).  The polar family
-used here is rho = r(t) sin t, z = r(t) cos t with r(t) = a (1 + eps cos j t).
+t in [0, pi], with z'(0) = z'(pi) = 0 (Sec. 3, start).  Two families:
+  * polar: rho = r(t) sin t, z = r(t) cos t with r(t) = a (1 + eps cos j t);
+  * the cup of Fig. 1(c): radius r(u) = 1 - a erf((u - pi/2)/a) and polar
+    angle theta(u) = b - a + 2 (1 - (b - a)/pi) s_a(u - pi/2), with s_a the
+    a-rounded absolute value s_a(x) = x erf(x/a) + (a/sqrt(pi)) e^{-x^2/a^2},
+    rho = c r sin theta, z = c r cos theta, c = outer/(1 + a).
+Both are traversed clockwise in the (rho, z) half plane (t = 0 at the top
+pole for the polar family, at the inner bottom pole for the cup, which takes
+u = pi - t), so that (-z', rho')/s is the outward normal and Z(t - i tau)
+lies inside the body for tau > 0.
 """
 from __future__ import annotations
 
@@ -11,8 +19,9 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.special import erf
 
-from workloads import Body, Shape
+from workloads import Body, CupShape, Shape
 
 
 def radius(shape: Shape, t):
@@ -24,10 +33,25 @@ def radius_dt(shape: Shape, t):
     return -shape.a * shape.eps * shape.j * np.sin(shape.j * t)
 
 
-def curve_Z(shape: Shape, t):
-    """The curve as one complex function Z(t) = rho(t) + i z(t)
-    = r(t) (sin t + i cos t).  Evaluating it at complex t gives the
-    complexified source points of Sec. 3.2, method (c)."""
+def cup_parts(sh: CupShape, t):
+    """Cup radius r and polar angle theta (Fig. 1(c)) at u = pi - t, and the
+    scale c; t may be complex (the formulas continue analytically)."""
+    a, b = sh.half, sh.b
+    x = (math.pi - t) - math.pi / 2
+    r = 1.0 - a * erf(x / a)
+    s_a = x * erf(x / a) + (a / math.sqrt(math.pi)) * np.exp(-(x / a) ** 2)
+    th = b - a + 2.0 * (1.0 - (b - a) / math.pi) * s_a
+    return r, th, sh.outer / (1.0 + a)
+
+
+def curve_Z(shape, t):
+    """The curve as one complex function Z(t) = rho(t) + i z(t):
+    r(t) (sin t + i cos t) for the polar family, c r (sin theta + i cos theta)
+    for the cup.  Evaluating it at complex t gives the complexified source
+    points of Sec. 3.2, method (c)."""
+    if isinstance(shape, CupShape):
+        r, th, c = cup_parts(shape, t)
+        return c * r * (np.sin(th) + 1j * np.cos(th))
     return radius(shape, t) * (np.sin(t) + 1j * np.cos(t))
 
 
@@ -63,9 +87,21 @@ def source_params(N: int) -> np.ndarray:
     return math.pi * (np.arange(1, N + 1) - 0.5) / N
 
 
-def curve_points(sh: Shape, t: np.ndarray):
+def curve_points(sh, t: np.ndarray):
     """rho, z, outward unit normal (n = (-z', rho')/s for this orientation,
     Sec. 3) and speed s at real parameters t."""
+    if isinstance(sh, CupShape):
+        a = sh.half
+        r, th, c = cup_parts(sh, t)
+        x = (math.pi - t) - math.pi / 2
+        # d/dt = -d/du:  dr/du = -(2/sqrt(pi)) e^{-x^2/a^2},  ds_a/dx = erf(x/a)
+        r_t = (2.0 / math.sqrt(math.pi)) * np.exp(-(x / a) ** 2)
+        th_t = -2.0 * (1.0 - (sh.b - a) / math.pi) * erf(x / a)
+        rho, z = c * r * np.sin(th), c * r * np.cos(th)
+        drho = c * (r_t * np.sin(th) + r * np.cos(th) * th_t)
+        dz = c * (r_t * np.cos(th) - r * np.sin(th) * th_t)
+        s = np.hypot(drho, dz)
+        return rho, z, -dz / s, drho / s, s
     r = radius(sh, t)
     rp = radius_dt(sh, t)
     rho = r * np.sin(t)

@@ -44,6 +44,11 @@ class PolarSpec(C.Structure):
                 ("M", C.c_int32), ("N", C.c_int32), ("tau", C.c_double)]
 
 
+class CupSpec(C.Structure):
+    _fields_ = [("outer", C.c_double), ("half", C.c_double), ("b", C.c_double), ("colloc", C.c_int32),
+                ("M", C.c_int32), ("N", C.c_int32), ("tau", C.c_double)]
+
+
 class Lattice(C.Structure):
     _fields_ = [("ex", C.c_double), ("ey", C.c_double), ("z0", C.c_double), ("p", C.c_int32),
                 ("N0", C.c_double), ("M1", C.c_int32)]
@@ -82,6 +87,7 @@ _SIGS = {
     "mfs_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "mfs_destroy": (None, [C.c_void_p]),
     "mfs_polar_geometry": (C.c_int, [C.POINTER(PolarSpec), _dp, _dp, _dp, _dp, _dp, _dp]),
+    "mfs_cup_geometry": (C.c_int, [C.POINTER(CupSpec), _dp, _dp, _dp, _dp, _dp, _dp]),
     "mfs_build_operator": (C.c_int, [C.c_void_p, C.POINTER(Body), C.c_int32, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
     "mfs_destroy_op": (None, [C.c_void_p]),
@@ -164,6 +170,24 @@ def polar_geometry(a: float, eps: float, j: int, M: int, N: int, tau: float, col
     _check(lib().mfs_polar_geometry(C.byref(spec), _ptr(out["rho"]), _ptr(out["z"]), _ptr(out["nrho"]),
                                     _ptr(out["nz"]), _ptr(out["srho"]), _ptr(out["sz"])))
     return out
+
+
+def cup_geometry(outer: float, half: float, b: float, M: int, N: int, tau: float, colloc: str = "mid"):
+    """Host geometry of the cup of Fig. 1(c) (the library's own implementation)."""
+    spec = CupSpec(outer, half, b, 1 if colloc == "gauss" else 0, M, N, tau)
+    out = {k: np.zeros(M) for k in ("rho", "z", "nrho", "nz")}
+    out.update({k: np.zeros(N) for k in ("srho", "sz")})
+    _check(lib().mfs_cup_geometry(C.byref(spec), _ptr(out["rho"]), _ptr(out["z"]), _ptr(out["nrho"]),
+                                  _ptr(out["nz"]), _ptr(out["srho"]), _ptr(out["sz"])))
+    return out
+
+
+def body_geometry(shape, M: int, N: int, tau: float, colloc: str = "mid"):
+    """Host geometry for a shape description with fields (a, eps, j) (polar)
+    or (outer, half, b) (cup)."""
+    if hasattr(shape, "outer"):
+        return cup_geometry(shape.outer, shape.half, shape.b, M, N, tau, colloc)
+    return polar_geometry(shape.a, shape.eps, shape.j, M, N, tau, colloc)
 
 
 class Context:

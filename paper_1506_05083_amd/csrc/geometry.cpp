@@ -1,5 +1,6 @@
-// Host-side geometry of the method: the polar generating curve with its
-// normals and complexified MFS sources (Sec. 3, Sec. 3.2), Gauss-Legendre
+// Host-side geometry of the method: the polar and cup generating curves
+// (Sec. 3, Fig. 1) with their normals and complexified MFS sources
+// (Sec. 3.2), Gauss-Legendre
 // nodes (collocation in t, wall grids of Sec. 4.1), the unit-cell walls and
 // the Rayleigh-Bloch orders of eqs. (rb1)-(rb2).
 #include "geometry.hpp"
@@ -80,6 +81,82 @@ void polar_geometry(const mfs_polar_spec &s, double *rho, double *z, double *nrh
     // Z(t) = rho + i z = r(t) (sin t + i cos t), continued to t_j - i tau
     const cplx tc(kPi * (j + 0.5) / s.N, -s.tau);
     const cplx Z = radius(s, tc) * (std::sin(tc) + cplx(0.0, 1.0) * std::cos(tc));
+    srho[j] = Z.real();
+    sz[j] = Z.imag();
+  }
+}
+
+// sin(w)/w
+static double sinc(double w) {
+  if (std::fabs(w) < 1e-4) return 1.0 - w * w / 6.0 + w * w * w * w / 120.0;
+  return std::sin(w) / w;
+}
+
+// erf(x + iy) by the series of Abramowitz & Stegun 7.1.29:
+//   erf(x) + e^{-x^2}/(2 pi x) [(1 - cos 2xy) + i sin 2xy]
+//   + (2/pi) e^{-x^2} sum_{n >= 1} e^{-n^2/4}/(n^2 + 4x^2) (f_n + i g_n),
+//   f_n = 2x - 2x cosh(ny) cos(2xy) + n sinh(ny) sin(2xy),
+//   g_n = 2x cosh(ny) sin(2xy) + n sinh(ny) cos(2xy),
+// whose error is about 1e-16 of |erf| for the |y| <= 1 used here.  The
+// second term is written with sinc so that x = 0 needs no special case.
+static cplx erf_complex(cplx z) {
+  const double x = z.real(), y = z.imag();
+  const double ex = std::exp(-x * x);
+  const double xy = x * y;
+  const double s1 = sinc(xy);
+  double re = std::erf(x) + ex * x * y * y * s1 * s1 / kPi;
+  double im = ex * y * sinc(2.0 * xy) / kPi;
+  const double c2 = std::cos(2.0 * xy), s2 = std::sin(2.0 * xy);
+  double sr = 0.0, si = 0.0;
+  for (int n = 1; n <= 40; ++n) {
+    const double w = std::exp(-0.25 * n * n) / (n * n + 4.0 * x * x);
+    const double ch = std::cosh(n * y), sh = std::sinh(n * y);
+    sr += w * (2.0 * x - 2.0 * x * ch * c2 + n * sh * s2);
+    si += w * (2.0 * x * ch * s2 + n * sh * c2);
+  }
+  re += 2.0 / kPi * ex * sr;
+  im += 2.0 / kPi * ex * si;
+  return {re, im};
+}
+
+// Cup of Fig. 1(c) at u = pi - t (x = u - pi/2 = pi/2 - t): radius
+// r = 1 - a erf(x/a), polar angle theta = b - a + kap s_a(x) with
+// kap = 2 (1 - (b - a)/pi) and s_a(x) = x erf(x/a) + (a/sqrt(pi)) e^{-x^2/a^2}.
+void cup_geometry(const mfs_cup_spec &s, double *rho, double *z, double *nrho, double *nz, double *srho,
+                  double *sz) {
+  const double a = s.half, b = s.b, c = s.outer / (1.0 + a);
+  const double kap = 2.0 * (1.0 - (b - a) / kPi);
+  const double rsp = 1.0 / std::sqrt(kPi);
+  std::vector<double> t(s.M);
+  if (s.colloc == 1) {
+    std::vector<double> x, w;
+    gauss_legendre(s.M, x, w);
+    for (int m = 0; m < s.M; ++m) t[m] = kPi * (x[m] + 1.0) / 2.0;
+  } else {
+    for (int m = 0; m < s.M; ++m) t[m] = kPi * (m + 0.5) / s.M;
+  }
+  for (int m = 0; m < s.M; ++m) {
+    const double x = 0.5 * kPi - t[m];
+    const double e = std::erf(x / a), g = std::exp(-(x / a) * (x / a));
+    const double r = 1.0 - a * e;
+    const double th = b - a + kap * (x * e + a * rsp * g);
+    const double r_t = 2.0 * rsp * g;   // dr/dt (dx/dt = -1)
+    const double th_t = -kap * e;       // dtheta/dt
+    rho[m] = c * r * std::sin(th);
+    z[m] = c * r * std::cos(th);
+    const double dr = c * (r_t * std::sin(th) + r * std::cos(th) * th_t);
+    const double dz = c * (r_t * std::cos(th) - r * std::sin(th) * th_t);
+    const double sp = std::hypot(dr, dz);
+    nrho[m] = -dz / sp;   // outward: the curve runs clockwise in the (rho, z) half plane
+    nz[m] = dr / sp;
+  }
+  for (int j = 0; j < s.N; ++j) {
+    // Z = c r (sin theta + i cos theta) continued to t_j - i tau
+    const cplx x(0.5 * kPi - kPi * (j + 0.5) / s.N, s.tau);
+    const cplx e = erf_complex(x / a);
+    const cplx r = 1.0 - a * e;
+    const cplx th = b - a + kap * (x * e + a * rsp * std::exp(-(x / a) * (x / a)));
+    const cplx Z = c * r * (std::sin(th) + cplx(0.0, 1.0) * std::cos(th));
     srho[j] = Z.real();
     sz[j] = Z.imag();
   }

@@ -62,3 +62,24 @@ def test_missing_library_fails_loudly(lib, monkeypatch, tmp_path):
     monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError):
         lib.lib()
+
+
+@pytest.mark.parametrize("N,M,tau,colloc", [(450, 540, 0.05, "mid"), (60, 72, 0.05, "gauss"), (120, 144, 0.2, "mid")])
+def test_host_cup_geometry_matches_oracle(lib, N, M, tau, colloc):
+    """The library's cup (its own complex erf) against the oracle's (scipy's)."""
+    sh = W.CupShape()
+    b = W.Body(sh, N=N, M=M, P=8, q=16, k=1.0, tau=tau, colloc=colloc)
+    g = lib.body_geometry(sh, M, N, tau, colloc)
+    o = geometry.build_geometry(b)
+    for k in ("rho", "z", "nrho", "nz", "srho", "sz"):
+        assert np.max(np.abs(g[k] - getattr(o, k))) < 1e-14, k
+
+
+@pytest.mark.parametrize("bad", [dict(outer=-1.0), dict(half=1.5), dict(b=4.0), dict(tau=0.5)])
+def test_invalid_cup_rejected_on_host(lib, bad):
+    kw = dict(outer=0.35, half=0.2, b=0.5, M=12, N=10, tau=0.05)
+    kw.update(bad)
+    with pytest.raises(lib.MfsError) as e:
+        lib.cup_geometry(**kw)
+    assert e.value.status == lib.MFS_EINVAL
+    assert "cup" in str(e.value)

@@ -38,9 +38,27 @@ class Shape:
 
 
 @dataclass(frozen=True)
+class CupShape:
+    """The "cup" body of the paper's Fig. 1(c): a spherical shell of mid radius
+    1 and half-thickness `half` (in units of the mid radius) with a rounded
+    opening of half-angle `b` about the +z axis, given parametrically by a
+    radius r(t) and a polar angle theta(t) built from erf; scaled here so that
+    the outer radius is `outer`.  Only the parameters live here; the curve is
+    evaluated by the oracle and by the library, each in its own code."""
+    outer: float = 0.35
+    half: float = 0.2
+    b: float = math.pi / 6
+
+    def radius(self, theta):
+        """Radius of the sphere that encloses the body (used only to keep test
+        points outside it)."""
+        return np.full(np.shape(theta), self.outer, dtype=float)
+
+
+@dataclass(frozen=True)
 class Body:
     """One axisymmetric obstacle and its one-body discretisation (Sec. 3)."""
-    shape: Shape
+    shape: "Shape | CupShape"
     N: int              # MFS sources on the generating curve
     M: int              # collocation points on the generating curve
     P: int              # azimuthal modes, even
