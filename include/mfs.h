@@ -259,7 +259,9 @@ mfs_status mfs_set_near_field_budget(mfs_op *op, uint64_t max_bytes);
  * point sources; eps_flux.  Blocking.  Returns ENOTCONV if some wave hit
  * maxit (its result holds the last iterate), EINVAL if a result's
  * cap_orders is too small (norders is set so the caller can retry).
- * timing (optional) receives stage times. */
+ * timing (optional) receives stage times.  With the environment variable
+ * MFS_PROGRESS set, the stages and every fifth GMRES iteration are reported
+ * on stderr. */
 mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t body,
                               const mfs_lattice *lat, int32_t nwaves, const mfs_wave *waves,
                               double tol, int32_t maxit, double rel_cutoff,

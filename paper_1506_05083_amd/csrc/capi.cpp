@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -15,6 +18,18 @@ namespace mfs {
 static thread_local std::string g_error;
 void set_error(const std::string &msg) { g_error = msg; }
 const std::string &get_error() { return g_error; }
+
+void progress(const char *fmt, ...) {
+  static const bool on = std::getenv("MFS_PROGRESS") != nullptr;
+  if (!on) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[mfs] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  va_end(ap);
+  std::fflush(stderr);
+}
 
 void DevBuf::alloc(size_t n) {
   release();
@@ -416,7 +431,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
     auto g = std::make_unique<GradedPinv>();
     g->ev_qr_done = op->ev[1];
     HIP_CHECK(hipEventRecord(op->ev[0], s));
-    graded_pinv(*g, in, rel_cutoff, true, s);
+    graded_pinv(*g, in, rel_cutoff, 0, s);
     HIP_CHECK(hipEventRecord(op->ev[2], s));
     HIP_CHECK(hipStreamSynchronize(s));
     float ms_qr = 0, ms_svd = 0;

@@ -16,6 +16,10 @@ namespace mfs {
 void set_error(const std::string &msg);
 const std::string &get_error();
 
+// Stage progress on stderr when the environment sets MFS_PROGRESS (long
+// solves report what they are doing; printf-style, one line, flushed).
+void progress(const char *fmt, ...);
+
 struct Error {
   mfs_status st;
   std::string msg;

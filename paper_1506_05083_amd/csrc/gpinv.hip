@@ -23,11 +23,12 @@
 //     when pivoting: U and W = P Z V_L S^{-1} are formed explicitly for the
 //     two-stage apply.
 // Ordering and LQ are the preconditioning that makes one-sided Jacobi
-// converge in a handful of sweeps.  For the strongly graded periodizer the
-// norm ordering alone does it (10 sweeps on the k = 10 Q, as with the
-// pivoted triangle, against no convergence in 40 without the ordering), and
-// the unblocked pivoted QR, O(n^3) in matrix-vector steps, would not scale
-// to its ~10^4 columns at high k.  The per-mode MFS blocks are
+// converge in a handful of sweeps.  On the strongly graded k = 10 periodizer
+// (n2 = 1257) the norm ordering alone does it (10 sweeps, as with the
+// pivoted triangle, against no convergence in 40 without the ordering), so
+// the pivoted QR's 2 n2 launches are saved; on the k = 2 pi 13 periodizer
+// (n2 = 9701) the pivoted triangle takes Jacobi from ~25 sweeps to ~14 for
+// about 3.6 s of matrix-vector work.  The per-mode MFS blocks are
 // rank-deficient without being graded by column, and there the pivoted
 // triangle cuts the Jacobi work by about 3x.  Either way the result is the
 // same truncated pseudoinverse the paper prescribes, to rounding.
@@ -303,7 +304,8 @@ static void upload_descs(DevBuf &buf, const std::vector<MatDesc> &h, hipStream_t
   HIP_CHECK(hipMemcpyAsync(buf.p, h.data(), h.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
 }
 
-void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, bool pivot, hipStream_t s) {
+void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
+                 hipStream_t s) {
   const int W = (int)in.size();
   int nmax = 0, mmax = 0;
   for (auto &d : in) { nmax = std::max(nmax, d.n); mmax = std::max(mmax, d.m); }
@@ -337,6 +339,8 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.perm.alloc(perm.size() * sizeof(int));
   HIP_CHECK(hipMemcpyAsync(g.perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, s));
   const int n2max = *std::max_element(n2.begin(), n2.end());
+  const bool pivot = n2max >= pivot_min_cols;
+  g.pivoted = pivot;
   // 2. QR without pivoting of the selected, ordered columns
   g.qc.resize(W);
   g.h_qc.resize(W);

@@ -18,6 +18,7 @@ struct GradedPinv {
   std::vector<double> maxcol;
   std::vector<int> cols, rows, kept;
   hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the unpivoted blocked QR
+  bool pivoted = false;              // the triangle went through the pivoted QR
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;
   double jacobi_bytes = 0.0;
@@ -35,9 +36,15 @@ struct GradedPinv {
   }
 };
 
-// in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.  pivot: take
-// the column-pivoted QR of the triangle before the LQ (per-mode MFS blocks);
-// without it the norm ordering alone preconditions Jacobi (periodizer Q).
-void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, bool pivot, hipStream_t s);
+// in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.  The
+// column-pivoted QR of the triangle is taken before the LQ when the widest
+// kept triangle has at least pivot_min_cols columns (0: always); below that
+// the norm ordering alone preconditions Jacobi.
+void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
+                 hipStream_t s);
+
+// Widest periodizer triangle factored without the pivoted QR (measured:
+// 1257 columns at k = 10 gain nothing from it, 9701 at k = 2 pi 13 gain 30%).
+constexpr int kQPivotMinCols = 2048;
 
 }  // namespace mfs

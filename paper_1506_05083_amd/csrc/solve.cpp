@@ -98,6 +98,7 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
     S.setup_periodizer(rel_cutoff);
     HIP_CHECK(hipEventRecord(ev[2], s));
     S.setup_sums();
+    progress("near sums ready (%s)", S.psurf.dense.p ? "stored" : "on the fly");
 
     // ---------------- GMRES (unrestarted, CGS2, lockstep over waves)
     const int MP = S.MP;
@@ -202,6 +203,11 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
         }
       }
       jdone = j + 1;
+      if (j % 5 == 4 || !any_active) {
+        double worst = 0.0;
+        for (int w = 0; w < W; ++w) worst = std::max(worst, resid[w]);
+        progress("GMRES iteration %d: largest relative residual %.2e", j + 1, worst);
+      }
       if (any_active) {
         upload(SCd, scale.data(), W * sizeof(double), s);
         launch_scale(W, MP, Zb, MP, V + (size_t)(j + 1) * MP, ldw, SCd, s);

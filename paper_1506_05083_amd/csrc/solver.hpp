@@ -121,8 +121,11 @@ struct Solver {
     qdescs.alloc(W * sizeof(MatDesc));
     upload(qdescs.p, h_qdescs.data(), W * sizeof(MatDesc), s);
     HIP_CHECK(hipStreamSynchronize(s));   // ordbufs are released on return
-    graded_pinv(gp, h_qdescs, rel_cutoff, false, s);
+    progress("periodizer: Q filled for %d waves, %d x %d at most; factoring", W, rows, NQmax);
+    graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s);
     qrank = gp.kept;
+    progress("periodizer: factored (%s triangle; Jacobi %.0f ms, %d launches)", gp.pivoted ? "pivoted" : "ordered",
+             gp.jacobi_ms, gp.jacobi_launches);
     setup_bvals();
   }
 

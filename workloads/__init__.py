@@ -192,6 +192,46 @@ def periodic_k10(nwaves: int = 8) -> Problem:
                    gmres_tol=1e-10)
 
 
+def cup_free_space() -> Problem:
+    """The cup of Fig. 1(c) (outer radius 0.35) in free space, k = 6, N = 120,
+    M = 144, P = 32, tau = 0.1, q = 320 (Theorem 1 rate 0.122); one random
+    direction (seed 12); 32 test points on |x| = 1."""
+    b = Body(CupShape(), N=120, M=144, P=32, q=320, k=6.0, tau=0.1, colloc="mid")
+    return Problem("cup_free_space", b, None, (sample_direction_sphere(12),),
+                   fibonacci_sphere(32, 1.0), q_field=320)
+
+
+def small_periodic_cup(nwaves: int = 2) -> Problem:
+    """A small periodic cup case that the oracle solves in seconds: unit
+    lattice, the cup of Fig. 1(c) scaled to outer radius 0.35, k = 6,
+    N = 60, M = 72, P = 16, tau = 0.1, q = 320 (Theorem 1: the smallest rate
+    over the (collocation, source) pairs is 0.13, q >= P/2 + 37/0.13);
+    z0 = 0.6, p = 12, N0 = 8, M1 = 14; incidences from seed 9."""
+    shape = CupShape()
+    b = Body(shape, N=60, M=72, P=16, q=320, k=6.0, tau=0.1, colloc="mid")
+    lat = Lattice(1.0, 1.0, 0.6, p=12, N0=8, M1=14)
+    waves = tuple(sample_waves(b.k, lat, nwaves, seed=9))
+    return Problem("small_periodic_cup", b, lat, waves, cell_grid(lat, shape, n=3), q_field=320)
+
+
+def cup_periodic_large(nwaves: int = 8) -> Problem:
+    """The large configuration: sound-hard cups of Fig. 1(c) (outer radius
+    0.35) on the unit square lattice at k = 2 pi 13 (13 wavelengths per
+    period); N = 450, M = 540 (midpoint), P = 144 (NP = 64800), tau = 0.05,
+    q = 540 (Theorem 1: the smallest rate over the (collocation, source)
+    pairs is 0.0829, q >= P/2 + 37/0.0829); z0 = 0.6, periodizer p = 90
+    (k times the cell-corner radius 0.93 is 76), N0 = 30 (Bragg orders out
+    to |kappa_z| z0 ~ 26, as for the k = 10 workload), M1 = 56 (about 3.6
+    Gauss nodes per wavelength on the 13 x 15.6 wavelength walls);
+    incidences from seed 5; GMRES to 1e-10."""
+    shape = CupShape()
+    b = Body(shape, N=450, M=540, P=144, q=540, k=2 * math.pi * 13, tau=0.05, colloc="mid")
+    lat = Lattice(1.0, 1.0, 0.6, p=90, N0=30, M1=56)
+    waves = tuple(sample_waves(b.k, lat, nwaves, seed=5))
+    return Problem("cup_periodic_large", b, lat, waves, cell_grid(lat, shape), q_field=540,
+                   gmres_tol=1e-10)
+
+
 def serving_stream(count: int, seed_dirs: int = 4, seed_arrivals: int = 40):
     """Request stream of the serving configuration against the k = 10
     operator: incidences theta ~ U[0, pi/2), phi ~ U[0, 2 pi) from seed 4
