@@ -167,6 +167,8 @@ class Problem:
     q_field: int = 0      # trapezoid nodes used when evaluating u at targets
     gmres_tol: float = 1e-12
     maxit: int = 200
+    km: float = 0.0       # 0: sound-hard; > 0: transmission with this interior wavenumber
+    inner: np.ndarray = field(compare=False, repr=False, default=None)   # test points inside
 
 
 def sphere_free_space() -> Problem:
@@ -230,6 +232,27 @@ def cup_periodic_large(nwaves: int = 8) -> Problem:
     waves = tuple(sample_waves(b.k, lat, nwaves, seed=5))
     return Problem("cup_periodic_large", b, lat, waves, cell_grid(lat, shape), q_field=540,
                    gmres_tol=1e-10)
+
+
+def sphere_transmission() -> Problem:
+    """Penetrable sphere a = 0.5 in free space, k = 2 pi, interior
+    wavenumber km = 1.5 k; discretisation of the free-space sphere (60 Gauss
+    collocation nodes, N = 40, tau = ln(1/0.7) so the exterior field's
+    sources sit at 0.35 and the interior field's at 0.714), P = 32, q = 128;
+    one random direction (seed 1); 32 test points on |x| = 2 and 16 inside
+    on |x| = 0.25."""
+    b = Body(Shape(0.5), N=40, M=60, P=32, q=128, k=2 * math.pi, tau=math.log(1 / 0.7), colloc="gauss")
+    return Problem("sphere_transmission", b, None, (sample_direction_sphere(1),), fibonacci_sphere(32, 2.0),
+                   q_field=128, km=1.5 * 2 * math.pi, inner=fibonacci_sphere(16, 0.25))
+
+
+def small_periodic_transmission(nwaves: int = 2) -> Problem:
+    """The small periodic body (r = 0.3 (1 + 0.1 cos 3t), N = 40, M = 48,
+    P = 24, q = 160, tau = 0.2, unit lattice, z0 = 0.6, p = 24, N0 = 10,
+    M1 = 20) as a transmission obstacle with k = 5 and km = 1.5 k;
+    incidences from seed 7."""
+    pr = small_periodic(nwaves=nwaves)
+    return replace(pr, name="small_periodic_transmission", km=1.5 * pr.body.k)
 
 
 def serving_stream(count: int, seed_dirs: int = 4, seed_arrivals: int = 40):
