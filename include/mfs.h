@@ -52,12 +52,22 @@ typedef struct mfs_op mfs_op;
  * M collocation points (rho_m, z_m) on the generating curve with outward unit
  * normals (nrho_m, nz_m); N MFS sources (srho_j > 0, sz_j) inside the body;
  * P azimuthal modes (even, >= 2); q trapezoid nodes for the ring-kernel fill
- * (eq. (ptr); even, q >= P); k > 0 the wavenumber.  M >= N. */
+ * (eq. (ptr); even, q >= P); k > 0 the wavenumber.  M >= N.
+ * km = 0: sound-hard body (eq. (neu)).  km > 0: transmission (eqs.
+ * (helmi)-(neup1.4), Sec. 3.4) with interior wavenumber km; the interior
+ * field is a second ring-source sum at km with the N sources
+ * (srho_out, sz_out) outside the body (tau negated).  The per-mode system is
+ * then 2M x 2N (eq. (trans)): rows [values; normal derivatives] of the M
+ * collocation points, columns [exterior; interior] coefficients, and every
+ * "[..][P][M]" surface array and "[..][P][N]" coefficient array below has
+ * 2M and 2N entries per mode instead. */
 typedef struct {
   int32_t M, N, P, q;
   double k;
   const double *rho, *z, *nrho, *nz; /* host [M] */
   const double *srho, *sz;           /* host [N] */
+  double km;                         /* 0, or the interior wavenumber       */
+  const double *srho_out, *sz_out;   /* host [N], km > 0 only               */
 } mfs_body;
 
 /* Polar generating curve r(t) = a (1 + eps cos(j t)), rho = r sin t,
@@ -81,7 +91,8 @@ typedef struct {
  * a shell of half-thickness `half` about the unit sphere with an opening of
  * half-angle b about +z, scaled to outer radius `outer`; t = 0 is the inner
  * bottom pole.  Sources, collocation and tau as for mfs_polar_spec (the
- * complex erf of the sources is evaluated for tau <= half). */
+ * complex erf of the sources is evaluated for |tau| <= half; tau < 0 puts the
+ * sources outside, for the interior field of a transmission body). */
 typedef struct {
   double outer, half, b;
   int32_t colloc;
@@ -155,23 +166,27 @@ mfs_status mfs_polar_geometry(const mfs_polar_spec *spec, double *rho, double *z
 
 /* Host helper: geometry of the cup (Fig. 1(c)) into the same caller arrays.
  * EINVAL for outer <= 0, half outside (0, 1), b outside (0, pi), tau outside
- * [0, half], M or N < 1, or colloc not 0/1; nothing is written then. */
+ * [-half, half], M or N < 1, or colloc not 0/1; nothing is written then. */
 mfs_status mfs_cup_geometry(const mfs_cup_spec *spec, double *rho, double *z,
                             double *nrho, double *nz, double *srho, double *sz);
 
 /* (a) Modal fill (eqs. (ringkernelderiv), (ptr)): for each body, the P/2+1
  * distinct blocks A'_n, n = 0..P/2 (A'_{-n} = A'_n) of size M x N,
  *   A'_n[m, j] = (1/q) sum_{l=0}^{q-1} dG/dn_x((rho_m,0,z_m); y_j(2 pi l/q)) e^{-i n 2 pi l/q},
- * G = e^{ikR}/(4 pi R) (eq. (G)).  Host arrays are copied; the operator owns
- * the blocks.  Returns EINVAL for P odd, q < P, q odd, M < N, srho <= 0 or
- * non-finite input. */
+ * G = e^{ikR}/(4 pi R) (eq. (G)); for a transmission body the 2M x 2N blocks
+ * [[A_n, -A^-_n], [A'_n, -A'^-_n]] of eq. (trans), A_n the value kernel
+ * (eq. (ringkernel)) and the minus blocks at km from the exterior sources.
+ * All bodies are filled in one persistent launch.  Host arrays are copied;
+ * the operator owns the blocks.  Returns EINVAL for P odd, q < P, q odd,
+ * M < N, srho <= 0, km < 0, missing exterior sources or non-finite input. */
 mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbodies,
                               void *stream, mfs_op **out);
 void mfs_destroy_op(mfs_op *op);
 
 /* Copy the filled blocks of one body, before factorisation, to dev
- * out [P/2+1][N][M] (column-major M x N per mode n = 0..P/2).  ESTATE after
- * mfs_factor_modes (the blocks are overwritten in place). */
+ * out [P/2+1][N][M] (column-major M x N per mode n = 0..P/2; [2N][2M] for a
+ * transmission body).  ESTATE after mfs_factor_modes (the blocks are
+ * released). */
 mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *stream);
 
 /* (b) Per-mode factorisation (Sec. 3 and Sec. 4.2): blocked Householder QR
@@ -188,7 +203,8 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks);
 mfs_status mfs_op_timing(const mfs_op *op, double *ms);
 
 /* Singular values (descending) of the distinct blocks of one body, host
- * out [P/2+1][N].  ESTATE before mfs_factor_modes. */
+ * out [P/2+1][N] ([P/2+1][2N] for a transmission body).  ESTATE before
+ * mfs_factor_modes. */
 mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out);
 
 /* (c) Solution-operator apply: c_n = A'_n^+ x_n for every mode of nrhs
@@ -199,12 +215,16 @@ mfs_status mfs_apply_solution_op(const mfs_op *op, int32_t body, int32_t nrhs,
 
 /* Right-hand side of eq. (linsys): f = -du^i/dn at the P x M surface points
  * then f_hat_n = (1/P) sum_l f(phi_l) e^{-i n phi_l} (eq. (fhatquad), q = P).
- * kvec: host [nwaves][3] wave vectors; out: dev [nwaves][P][M]. */
+ * For a transmission body [f_hat; f_hat'] of eq. (trans): f = -u^i in rows
+ * [0, M) and f' = -du^i/dn in rows [M, 2M) of every mode.
+ * kvec: host [nwaves][3] wave vectors; out: dev [nwaves][P][M] ([..][P][2M]). */
 mfs_status mfs_rhs_modes(const mfs_op *op, int32_t body, int32_t nwaves, const double *kvec,
                          mfs_c128 *out, void *stream);
 
 /* Point-source form (Sec. 4.1): sigma_{jl} = (1/qs) sum_n c_{nj} e^{+i n 2 pi l/qs}
- * for qs >= P.  c: dev [nrhs][P][N]; sigma: dev [nrhs][qs][N]. */
+ * for qs >= P.  c: dev [nrhs][P][N] (for a transmission body [nrhs][P][2N],
+ * of which the exterior coefficients, columns [0, N), are used);
+ * sigma: dev [nrhs][qs][N]. */
 mfs_status mfs_point_strengths(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
                                const mfs_c128 *c, mfs_c128 *sigma, void *stream);
 
@@ -233,11 +253,21 @@ mfs_status mfs_neighbour_sum(const mfs_op *op, int32_t body, const mfs_lattice *
                              mfs_c128 *out, void *stream);
 
 /* Free-space field u(x) = sum_{j,l} G(x, y_{jl}) sigma_{jl} of the qs-node
- * point form of mode coefficients c (dev [nrhs][P][N]) at host targets
- * [ntargets][3]; out: dev [nrhs][ntargets]. */
+ * point form of mode coefficients c (dev [nrhs][P][N]; for a transmission
+ * body the exterior columns of [nrhs][P][2N]) at host targets [ntargets][3]
+ * outside the body; out: dev [nrhs][ntargets]. */
 mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
                           const mfs_c128 *c, const double *targets, int32_t ntargets,
                           mfs_c128 *out, void *stream);
+
+/* Interior field u^- of a transmission body (Sec. 3.4): the ring sources at
+ * km from the exterior sources, coefficients the columns [N, 2N) of c
+ * (dev [nrhs][P][2N]), qs-node point form, at host targets [ntargets][3]
+ * inside the body; out: dev [nrhs][ntargets].  EINVAL for a sound-hard
+ * body. */
+mfs_status mfs_field_interior(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs,
+                              const mfs_c128 *c, const double *targets, int32_t ntargets,
+                              mfs_c128 *out, void *stream);
 
 /* Near-field policy of later mfs_solve_incident calls on op.  The kernel
  * values of the neighbour sums (the 8 images of A_else on the surface nodes

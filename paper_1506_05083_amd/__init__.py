@@ -36,7 +36,7 @@ _cp = C.POINTER(C128)
 class Body(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("P", C.c_int32), ("q", C.c_int32),
                 ("k", C.c_double), ("rho", _dp), ("z", _dp), ("nrho", _dp), ("nz", _dp),
-                ("srho", _dp), ("sz", _dp)]
+                ("srho", _dp), ("sz", _dp), ("km", C.c_double), ("srho_out", _dp), ("sz_out", _dp)]
 
 
 class PolarSpec(C.Structure):
@@ -104,6 +104,8 @@ _SIGS = {
     "mfs_neighbour_sum": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Lattice), C.c_int32, C.c_int32,
                                     C.c_void_p, _cp, C.c_int32, _dp, C.c_int32, C.c_int32,
                                     C.c_void_p, C.c_void_p]),
+    "mfs_field_interior": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp,
+                                     C.c_int32, C.c_void_p, C.c_void_p]),
     "mfs_field_free": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp,
                                  C.c_int32, C.c_void_p, C.c_void_p]),
     "mfs_server_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Lattice),
@@ -190,6 +192,15 @@ def body_geometry(shape, M: int, N: int, tau: float, colloc: str = "mid"):
     return polar_geometry(shape.a, shape.eps, shape.j, M, N, tau, colloc)
 
 
+def transmission_geometry(shape, M: int, N: int, tau: float, colloc: str = "mid"):
+    """Host geometry of a transmission body: the sources of the exterior
+    field inside (tau), those of the interior field outside (-tau, Sec. 3.4)."""
+    g = body_geometry(shape, M, N, tau, colloc)
+    go = body_geometry(shape, M, N, -tau, colloc)
+    g["srho_out"], g["sz_out"] = go["srho"], go["sz"]
+    return g
+
+
 class Context:
     def __init__(self, device: int = 0):
         h = C.c_void_p()
@@ -208,12 +219,25 @@ def create(device: int = 0) -> Context:
 
 @dataclass
 class BodySpec:
+    """km = 0: sound-hard; km > 0: transmission, geom then also holds the
+    exterior sources srho_out, sz_out (transmission_geometry)."""
     M: int
     N: int
     P: int
     q: int
     k: float
     geom: dict
+    km: float = 0.0
+
+    @property
+    def rows(self) -> int:
+        """Rows of one mode's system: M, or 2M for transmission."""
+        return 2 * self.M if self.km > 0 else self.M
+
+    @property
+    def cols(self) -> int:
+        """Columns of one mode's system: N, or 2N for transmission."""
+        return 2 * self.N if self.km > 0 else self.N
 
 
 class Operator:
@@ -226,8 +250,10 @@ class Operator:
         for i, b in enumerate(bodies):
             g = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in b.geom.items()}
             keep.append(g)
+            tr = b.km > 0
             arr[i] = Body(b.M, b.N, b.P, b.q, b.k, _ptr(g["rho"]), _ptr(g["z"]), _ptr(g["nrho"]),
-                          _ptr(g["nz"]), _ptr(g["srho"]), _ptr(g["sz"]))
+                          _ptr(g["nz"]), _ptr(g["srho"]), _ptr(g["sz"]), float(b.km),
+                          _ptr(g["srho_out"]) if tr else None, _ptr(g["sz_out"]) if tr else None)
         torch.cuda.synchronize()
         h = C.c_void_p()
         _check(lib().mfs_build_operator(ctx.h, arr, len(bodies), _stream(), C.byref(h)))
@@ -242,7 +268,7 @@ class Operator:
     def blocks(self, body: int = 0):
         import torch
         b = self.bodies[body]
-        out = torch.empty((b.P // 2 + 1, b.N, b.M), dtype=torch.complex128, device="cuda")
+        out = torch.empty((b.P // 2 + 1, b.cols, b.rows), dtype=torch.complex128, device="cuda")
         _check(lib().mfs_op_blocks(self.h, body, _dev(out), _stream()))
         torch.cuda.synchronize()
         return out
@@ -268,7 +294,7 @@ class Operator:
 
     def singular_values(self, body: int = 0) -> np.ndarray:
         b = self.bodies[body]
-        out = np.zeros((b.P // 2 + 1, b.N))
+        out = np.zeros((b.P // 2 + 1, b.cols))
         _check(lib().mfs_op_singular_values(self.h, body, _ptr(out)))
         return out
 
@@ -286,7 +312,7 @@ def apply_solution_op(op: Operator, x, body: int = 0):
     import torch
     b = op.bodies[body]
     x = x.contiguous()
-    out = torch.empty((x.shape[0], b.P, b.N), dtype=torch.complex128, device=x.device)
+    out = torch.empty((x.shape[0], b.P, b.cols), dtype=torch.complex128, device=x.device)
     _check(lib().mfs_apply_solution_op(op.h, body, x.shape[0], _dev(x), _dev(out), _stream()))
     return out
 
@@ -295,7 +321,7 @@ def rhs_modes(op: Operator, kvecs: np.ndarray, body: int = 0):
     import torch
     b = op.bodies[body]
     kv = np.ascontiguousarray(np.atleast_2d(kvecs), dtype=np.float64)
-    out = torch.empty((kv.shape[0], b.P, b.M), dtype=torch.complex128, device="cuda")
+    out = torch.empty((kv.shape[0], b.P, b.rows), dtype=torch.complex128, device="cuda")
     _check(lib().mfs_rhs_modes(op.h, body, kv.shape[0], _ptr(kv), _dev(out), _stream()))
     return out
 
@@ -334,6 +360,17 @@ def neighbour_sum(op: Operator, lattice: Lattice, sigma, ab: np.ndarray, target_
     _check(lib().mfs_neighbour_sum(op.h, body, C.byref(lattice), nrhs, qs, _dev(sigma), ab_arr,
                                    target_set, uptr, 0 if user is None else user.shape[0], want,
                                    _dev(out), _stream()))
+    return out
+
+
+def field_interior(op: Operator, c, qs: int, targets: np.ndarray, body: int = 0):
+    """Interior field u^- of a transmission body at targets inside it."""
+    c = c.contiguous()
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    import torch
+    out = torch.empty((c.shape[0], t.shape[0]), dtype=torch.complex128, device=c.device)
+    _check(lib().mfs_field_interior(op.h, body, c.shape[0], qs, _dev(c), _ptr(t), t.shape[0], _dev(out),
+                                    _stream()))
     return out
 
 

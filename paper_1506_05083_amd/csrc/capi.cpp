@@ -58,7 +58,8 @@ void upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
 
 // Source points y_jl = (srho_j cos phi_l, srho_j sin phi_l, sz_j), phi_l = 2 pi l / qs,
 // SoA x y z [qs*N], index l*N + j.
-void source_points(const BodyData &b, int qs, DevBuf &out, hipStream_t s) {
+void source_points_of(const BodyData &b, const std::vector<double> &srho, const std::vector<double> &sz, int qs,
+                      DevBuf &out, hipStream_t s) {
   std::vector<double> h((size_t)3 * qs * b.N);
   const size_t S = (size_t)qs * b.N;
   for (int l = 0; l < qs; ++l) {
@@ -66,14 +67,18 @@ void source_points(const BodyData &b, int qs, DevBuf &out, hipStream_t s) {
     const double ang = 2.0 * kPi * l / qs;
     const double c = std::cos(ang), sn = std::sin(ang);
     for (int j = 0; j < b.N; ++j) {
-      h[(size_t)l * b.N + j] = b.h_srho[j] * c;
-      h[S + (size_t)l * b.N + j] = b.h_srho[j] * sn;
-      h[2 * S + (size_t)l * b.N + j] = b.h_sz[j];
+      h[(size_t)l * b.N + j] = srho[j] * c;
+      h[S + (size_t)l * b.N + j] = srho[j] * sn;
+      h[2 * S + (size_t)l * b.N + j] = sz[j];
     }
   }
   out.alloc(h.size() * sizeof(double));
   upload(out.p, h.data(), h.size() * sizeof(double), s);
   HIP_CHECK(hipStreamSynchronize(s));
+}
+
+void source_points(const BodyData &b, int qs, DevBuf &out, hipStream_t s) {
+  source_points_of(b, b.h_srho, b.h_sz, qs, out, s);
 }
 
 // Build a neighbour-sum plan from host target groups.
@@ -112,6 +117,9 @@ void build_plan(NsumPlan &plan, const std::vector<NsumGroup> &groups_in,
   HIP_CHECK(hipStreamSynchronize(s));
 }
 
+// Surface targets of A_else: the P x M nodes (index l M + m) with their
+// normals; one group of normal derivatives, and for a transmission body a
+// second group of values at the same nodes.
 void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
   NsumGroup g{};
   g.nt = b.P * b.M;
@@ -135,7 +143,13 @@ void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
       t[5 * n + i] = b.h_nz[m];
     }
   }
-  build_plan(plan, {g}, {t}, s);
+  if (!b.trans()) {
+    build_plan(plan, {g}, {t}, s);
+  } else {
+    NsumGroup gv = g;
+    gv.deriv = 0;
+    build_plan(plan, {g, gv}, {t, t}, s);
+  }
 }
 
 // The 12 wall target groups R L Rx Lx F B Fy By T Tz D Dz (images and kinds).
@@ -236,6 +250,12 @@ static void validate_body(const mfs_body &b) {
               "non-finite geometry");
   for (int j = 0; j < b.N; ++j) MFS_REQUIRE(b.srho[j] > 0.0, "source rho must be > 0");
   for (int m = 0; m < b.M; ++m) MFS_REQUIRE(b.rho[m] > 0.0, "collocation rho must be > 0");
+  MFS_REQUIRE(b.km >= 0.0 && std::isfinite(b.km), "km must be 0 (sound-hard) or positive (transmission)");
+  if (b.km > 0.0) {
+    MFS_REQUIRE(b.srho_out && b.sz_out, "transmission needs the exterior sources srho_out, sz_out");
+    MFS_REQUIRE(finite_all(b.srho_out, b.N) && finite_all(b.sz_out, b.N), "non-finite geometry");
+    for (int j = 0; j < b.N; ++j) MFS_REQUIRE(b.srho_out[j] > 0.0, "source rho must be > 0");
+  }
 }
 
 BodyData &body_of(const mfs_op *op, int body) {
@@ -304,7 +324,7 @@ mfs_status mfs_cup_geometry(const mfs_cup_spec *spec, double *rho, double *z, do
   MFS_REQUIRE(spec->M > 0 && spec->N > 0, "bad cup spec: M and N must be positive");
   MFS_REQUIRE(spec->outer > 0 && spec->half > 0 && spec->half < 1 && spec->b > 0 && spec->b < kPi,
               "bad cup spec: need outer > 0, 0 < half < 1, 0 < b < pi");
-  MFS_REQUIRE(spec->tau >= 0 && spec->tau <= spec->half, "bad cup spec: need 0 <= tau <= half");
+  MFS_REQUIRE(std::fabs(spec->tau) <= spec->half, "bad cup spec: need |tau| <= half");
   MFS_REQUIRE(spec->colloc == 0 || spec->colloc == 1, "colloc must be 0 or 1");
   cup_geometry(*spec, rho, z, nrho, nz, srho, sz);
   MFS_API_END
@@ -322,26 +342,36 @@ mfs_status mfs_build_operator(mfs_ctx *ctx, const mfs_body *bodies, int32_t nbod
   for (int i = 0; i < nbodies; ++i) {
     const mfs_body &src = bodies[i];
     auto b = std::make_unique<BodyData>();
-    b->M = src.M; b->N = src.N; b->P = src.P; b->q = src.q; b->k = src.k;
+    b->M = src.M; b->N = src.N; b->P = src.P; b->q = src.q; b->k = src.k; b->km = src.km;
     b->nd = src.P / 2 + 1;
-    b->ldA = round_up(src.M, 16);
+    b->rows = b->trans() ? 2 * src.M : src.M;
+    b->cols = b->trans() ? 2 * src.N : src.N;
+    b->ldA = round_up(b->rows, 16);
     b->h_rho.assign(src.rho, src.rho + src.M);
     b->h_z.assign(src.z, src.z + src.M);
     b->h_nrho.assign(src.nrho, src.nrho + src.M);
     b->h_nz.assign(src.nz, src.nz + src.M);
     b->h_srho.assign(src.srho, src.srho + src.N);
     b->h_sz.assign(src.sz, src.sz + src.N);
-    b->geom.alloc((size_t)(4 * src.M + 2 * src.N) * sizeof(double));
+    b->geom.alloc((size_t)(4 * src.M + 4 * src.N) * sizeof(double));
     double *g = b->geom.as<double>();
     b->rho = g; b->z = g + src.M; b->nrho = g + 2 * src.M; b->nz = g + 3 * src.M;
     b->srho = g + 4 * src.M; b->sz = g + 4 * src.M + src.N;
+    if (b->trans()) {
+      b->h_srho2.assign(src.srho_out, src.srho_out + src.N);
+      b->h_sz2.assign(src.sz_out, src.sz_out + src.N);
+      b->srho2 = g + 4 * src.M + 2 * src.N;
+      b->sz2 = g + 4 * src.M + 3 * src.N;
+      upload(b->srho2, src.srho_out, src.N * sizeof(double), op->stream);
+      upload(b->sz2, src.sz_out, src.N * sizeof(double), op->stream);
+    }
     upload(b->rho, src.rho, src.M * sizeof(double), op->stream);
     upload(b->z, src.z, src.M * sizeof(double), op->stream);
     upload(b->nrho, src.nrho, src.M * sizeof(double), op->stream);
     upload(b->nz, src.nz, src.M * sizeof(double), op->stream);
     upload(b->srho, src.srho, src.N * sizeof(double), op->stream);
     upload(b->sz, src.sz, src.N * sizeof(double), op->stream);
-    b->blocks.alloc((size_t)b->nd * src.N * b->ldA * sizeof(double2));
+    b->blocks.alloc((size_t)b->nd * b->cols * b->ldA * sizeof(double2));
     source_points(*b, b->P, b->src_P, op->stream);
     op->bodies.push_back(std::move(b));
   }
@@ -372,8 +402,8 @@ mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *st
   BodyData &b = body_of(op, body);
   if (op->factored) MFS_THROW(MFS_ESTATE, "blocks were overwritten by mfs_factor_modes");
   MFS_REQUIRE(out != nullptr, "null output");
-  HIP_CHECK(hipMemcpy2DAsync(out, (size_t)b.M * sizeof(double2), b.blocks.p, (size_t)b.ldA * sizeof(double2),
-                             (size_t)b.M * sizeof(double2), (size_t)b.nd * b.N, hipMemcpyDeviceToDevice,
+  HIP_CHECK(hipMemcpy2DAsync(out, (size_t)b.rows * sizeof(double2), b.blocks.p, (size_t)b.ldA * sizeof(double2),
+                             (size_t)b.rows * sizeof(double2), (size_t)b.nd * b.cols, hipMemcpyDeviceToDevice,
                              static_cast<hipStream_t>(stream)));
   MFS_API_END
 }
@@ -399,12 +429,12 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
       Item it{};
       it.body = bi;
       it.d = d;
-      it.m.a = b.blocks.as<double2>() + (size_t)d * b.N * b.ldA;
-      it.m.m = b.M;
-      it.m.n = b.N;
+      it.m.a = b.blocks.as<double2>() + (size_t)d * b.cols * b.ldA;
+      it.m.m = b.rows;
+      it.m.n = b.cols;
       it.m.lda = b.ldA;
       // copies of the block and of U, the triangles and Jacobi factors, W
-      it.bytes = (3.0 * b.ldA * b.N + 8.0 * (double)b.N * b.N) * sizeof(double2);
+      it.bytes = (3.0 * b.ldA * b.cols + 8.0 * (double)b.cols * b.cols) * sizeof(double2);
       items.push_back(it);
     }
   }
@@ -417,7 +447,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   for (auto &bp : op->bodies) {
     bp->h_descs.assign(bp->nd, MatDesc{});
     bp->rank.assign(bp->nd, 0);
-    bp->h_sv.assign((size_t)bp->nd * bp->N, 0.0);
+    bp->h_sv.assign((size_t)bp->nd * bp->cols, 0.0);
   }
   op->gps.clear();
   op->ms_qr = op->ms_svd = 0.0;
@@ -447,7 +477,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
       // the Jacobi factor holds the r leading singular values; the rest are
       // below 1e-15 of the largest and stay zero
       const MatDesc &l = g->h_lq[i - c0];
-      HIP_CHECK(hipMemcpy(b.h_sv.data() + (size_t)it.d * b.N, l.sv, std::min(l.n, b.N) * sizeof(double),
+      HIP_CHECK(hipMemcpy(b.h_sv.data() + (size_t)it.d * b.cols, l.sv, std::min(l.n, b.cols) * sizeof(double),
                           hipMemcpyDeviceToHost));
     }
     g->release_work();
@@ -528,7 +558,7 @@ mfs_status mfs_point_strengths(const mfs_op *op, int32_t body, int32_t nrhs, int
   MFS_REQUIRE(nrhs >= 0 && qs >= b.P && (nrhs == 0 || (c && sigma)), "bad arguments");
   if (nrhs == 0) return MFS_OK;
   launch_point_strengths(nrhs, b.P, qs, b.N, reinterpret_cast<const double2 *>(c),
-                         reinterpret_cast<double2 *>(sigma), static_cast<hipStream_t>(stream));
+                         reinterpret_cast<double2 *>(sigma), static_cast<hipStream_t>(stream), b.cols);
   MFS_API_END
 }
 
@@ -602,18 +632,19 @@ mfs_status mfs_neighbour_sum(const mfs_op *op, int32_t body, const mfs_lattice *
   MFS_API_END
 }
 
-mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs, const mfs_c128 *c,
-                          const double *targets, int32_t ntargets, mfs_c128 *out, void *stream) {
-  MFS_API_BEGIN
-  BodyData &b = body_of(op, body);
-  MFS_REQUIRE(nrhs >= 1 && nrhs <= 16, "1 <= nrhs <= 16");
-  MFS_REQUIRE(qs >= b.P && c && targets && ntargets > 0 && out, "bad arguments");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+namespace {
+// u[r][t] = sum_{j,l} G_kk(x_t, y_jl) sigma_jl over the qs-node point form of
+// the ring sources (srho, sz), the coefficients being columns [col0, col0 + N)
+// of c [nrhs][P][cols].
+void ring_field(const BodyData &b, double kk, const std::vector<double> &srho, const std::vector<double> &sz,
+                int col0, int nrhs, int qs, const mfs_c128 *c, const double *targets, int ntargets, mfs_c128 *out,
+                hipStream_t s) {
   DevBuf srcbuf;
-  source_points(b, qs, srcbuf, s);
+  source_points_of(b, srho, sz, qs, srcbuf, s);
   const int S = qs * b.N;
   DevBuf sig((size_t)nrhs * S * sizeof(double2));
-  launch_point_strengths(nrhs, b.P, qs, b.N, reinterpret_cast<const double2 *>(c), sig.as<double2>(), s);
+  launch_point_strengths(nrhs, b.P, qs, b.N, reinterpret_cast<const double2 *>(c) + col0, sig.as<double2>(), s,
+                         b.cols);
   std::vector<double> u6((size_t)6 * ntargets, 0.0);
   for (int t = 0; t < ntargets; ++t)
     for (int k = 0; k < 3; ++k) u6[(size_t)6 * t + k] = targets[(size_t)3 * t + k];
@@ -627,13 +658,35 @@ mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t 
   const int nsplit = nsum_splits(plan, S);
   DevBuf tmp((size_t)nrhs * ntp * sizeof(double2) * (1 + nsplit));
   double2 *res = tmp.as<double2>();
-  launch_nsum(plan, nrhs, b.k, 1.0, 1.0, srcbuf.as<double>(), S, sig.as<double2>(), wd.as<double2>(), res,
+  launch_nsum(plan, nrhs, kk, 1.0, 1.0, srcbuf.as<double>(), S, sig.as<double2>(), wd.as<double2>(), res,
               res + (size_t)nrhs * ntp, s);
   double2 *o = reinterpret_cast<double2 *>(out);
   for (int r = 0; r < nrhs; ++r)
     HIP_CHECK(hipMemcpyAsync(o + (size_t)r * ntargets, res + (size_t)r * ntp, ntargets * sizeof(double2),
                              hipMemcpyDeviceToDevice, s));
   HIP_CHECK(hipStreamSynchronize(s));
+}
+}  // namespace
+
+mfs_status mfs_field_free(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs, const mfs_c128 *c,
+                          const double *targets, int32_t ntargets, mfs_c128 *out, void *stream) {
+  MFS_API_BEGIN
+  BodyData &b = body_of(op, body);
+  MFS_REQUIRE(nrhs >= 1 && nrhs <= 16, "1 <= nrhs <= 16");
+  MFS_REQUIRE(qs >= b.P && c && targets && ntargets > 0 && out, "bad arguments");
+  ring_field(b, b.k, b.h_srho, b.h_sz, 0, nrhs, qs, c, targets, ntargets, out, static_cast<hipStream_t>(stream));
+  MFS_API_END
+}
+
+mfs_status mfs_field_interior(const mfs_op *op, int32_t body, int32_t nrhs, int32_t qs, const mfs_c128 *c,
+                              const double *targets, int32_t ntargets, mfs_c128 *out, void *stream) {
+  MFS_API_BEGIN
+  BodyData &b = body_of(op, body);
+  if (!b.trans()) MFS_THROW(MFS_EINVAL, "the body is sound-hard: no interior field");
+  MFS_REQUIRE(nrhs >= 1 && nrhs <= 16, "1 <= nrhs <= 16");
+  MFS_REQUIRE(qs >= b.P && c && targets && ntargets > 0 && out, "bad arguments");
+  ring_field(b, b.km, b.h_srho2, b.h_sz2, b.N, nrhs, qs, c, targets, ntargets, out,
+             static_cast<hipStream_t>(stream));
   MFS_API_END
 }
 

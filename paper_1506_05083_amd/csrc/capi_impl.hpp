@@ -35,6 +35,9 @@ namespace mfs {
 
 void upload(void *dst, const void *src, size_t bytes, hipStream_t s);
 void source_points(const BodyData &b, int qs, DevBuf &out, hipStream_t s);
+// the same for a given source set (the exterior sources of a transmission body)
+void source_points_of(const BodyData &b, const std::vector<double> &srho, const std::vector<double> &sz, int qs,
+                      DevBuf &out, hipStream_t s);
 void build_plan(NsumPlan &plan, const std::vector<NsumGroup> &groups,
                 const std::vector<std::vector<double>> &tg, hipStream_t s);
 void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s);

@@ -18,11 +18,12 @@ namespace {
 constexpr int XT = 16;
 
 // out[r][o][x] = scale * sum_{i < Pin} in[r][i][x] * exp(sgn 2 pi i (ni(i) o mod Q) / Q)
-// with ni(i) = i, or the signed mode of bin i (period Pin) when in_modes.
+// with ni(i) = i, or the signed mode of bin i (period Pin) when in_modes;
+// in[r][i][x] at r ld_in + i ldi + x, out[r][o][x] at r ld_out + o ldo + x.
 __global__ __launch_bounds__(256) void dft_kernel(int Pin, int Pout, int Q, int X, int in_modes,
                                                   int sgn, double scale,
-                                                  const double2 *__restrict__ in, size_t ld_in,
-                                                  double2 *__restrict__ out) {
+                                                  const double2 *__restrict__ in, size_t ld_in, int ldi,
+                                                  double2 *__restrict__ out, size_t ld_out, int ldo) {
   extern __shared__ double2 sh[];
   double2 *tw = sh;            // [Q]
   double2 *tile = sh + Q;      // [Pin][XT]
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(256) void dft_kernel(int Pin, int Pout, int Q, int 
   for (int idx = threadIdx.x; idx < Pin * XT; idx += blockDim.x) {
     const int i = idx / XT, xx = idx % XT;
     const int x = x0 + xx;
-    tile[idx] = (x < X) ? in[(size_t)r * ld_in + (size_t)i * X + x] : cz(0.0, 0.0);
+    tile[idx] = (x < X) ? in[(size_t)r * ld_in + (size_t)i * ldi + x] : cz(0.0, 0.0);
   }
   __syncthreads();
   const int xx = threadIdx.x % XT;
@@ -50,33 +51,35 @@ __global__ __launch_bounds__(256) void dft_kernel(int Pin, int Pout, int Q, int 
       if (ph < 0) ph += Q;
       cfma(acc, tile[i * XT + xx], tw[ph]);
     }
-    if (x < X) out[((size_t)r * Pout + o) * X + x] = cscale(acc, scale);
+    if (x < X) out[(size_t)r * ld_out + (size_t)o * ldo + x] = cscale(acc, scale);
   }
 }
 
 }  // namespace
 
 void launch_dft_ld(int nr, int P, int X, const double2 *in, size_t ld_in, double2 *out, int sgn,
-                   double scale, hipStream_t s) {
+                   double scale, hipStream_t s, int ldo) {
   const size_t sh = (size_t)(P + P * XT) * sizeof(double2);
   MFS_REQUIRE(sh <= 64 * 1024, "P too large for the angle transform");
+  if (ldo <= 0) ldo = X;
   hipLaunchKernelGGL(dft_kernel, dim3(cdiv(X, XT), nr), dim3(256), sh, s, P, P, P, X, 0, sgn,
-                     scale, in, ld_in, out);
+                     scale, in, ld_in, X, out, (size_t)P * ldo, ldo);
   HIP_CHECK(hipGetLastError());
 }
 
 void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, double scale,
                 hipStream_t s) {
-  launch_dft_ld(nr, P, X, in, (size_t)P * X, out, sgn, scale, s);
+  launch_dft_ld(nr, P, X, in, (size_t)P * X, out, sgn, scale, s, X);
 }
 
 void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, double2 *sigma,
-                            hipStream_t s) {
+                            hipStream_t s, int ldc) {
   MFS_REQUIRE(qs >= P, "point strengths need qs >= P");
   const size_t sh = (size_t)(qs + P * XT) * sizeof(double2);
   MFS_REQUIRE(sh <= 64 * 1024, "qs too large for the strengths transform");
+  if (ldc <= 0) ldc = N;
   hipLaunchKernelGGL(dft_kernel, dim3(cdiv(N, XT), nr), dim3(256), sh, s, P, qs, qs, N, 1, +1,
-                     1.0 / qs, c, (size_t)P * N, sigma);
+                     1.0 / qs, c, (size_t)P * ldc, ldc, sigma, (size_t)qs * N, N);
   HIP_CHECK(hipGetLastError());
 }
 

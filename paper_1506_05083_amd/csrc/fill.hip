@@ -48,14 +48,18 @@ __global__ void fill_table_kernel(int q, int nd, double *tab) {
   }
 }
 
-// One body's share of the batched fill.
+// One sub-block of one body's mode blocks in the batched fill: the value
+// kernel G (eq. (ringkernel)) or its normal derivative (eq.
+// (ringkernelderiv)) at wavenumber k from the sources (srho, sz), times sign.
 struct FillJob {
   int M, N, q, nd, ldA;
-  double k;
+  int ncols;       // columns of one mode block (N, or 2N for transmission)
+  int value;       // 1: G, 0: dG/dn_x
+  double k, sign;
   const double *rho, *z, *nrho, *nz, *srho, *sz;
   const double *tab;
-  double2 *A;
-  long tile0;      // first tile of this body in the batch's tile list
+  double2 *A;      // entry (0, 0) of this sub-block in the mode-0 block
+  long tile0;      // first tile of this job in the batch's tile list
 };
 
 // Tile `tile` (64 (m, j) pairs) of job J; all 256 threads take part.
@@ -98,9 +102,15 @@ __device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double
         const double R = R2 * invR;
         double sn, cs;
         sincos(k * R, &sn, &cs);
-        const double t = dn * invR * invR * inv4pi;
-        // (cs + i sn) (i k - invR) t
-        g = cz(t * fma(-cs, invR, -sn * k), t * fma(cs, k, -sn * invR));
+        if (J.value) {
+          // (cs + i sn) / (4 pi R)
+          const double t = J.sign * invR * inv4pi;
+          g = cz(t * cs, t * sn);
+        } else {
+          const double t = J.sign * dn * invR * invR * inv4pi;
+          // (cs + i sn) (i k - invR) t
+          g = cz(t * fma(-cs, invR, -sn * k), t * fma(cs, k, -sn * invR));
+        }
       }
       gs[ll][pl] = g;
     }
@@ -123,7 +133,7 @@ __device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const int n = grp + 4 * s;
-      if (n < nd) J.A[((size_t)n * N + j) * ldA + m] = acc[s];
+      if (n < nd) J.A[((size_t)n * J.ncols + j) * ldA + m] = acc[s];
     }
   }
 }
@@ -160,11 +170,13 @@ __global__ __launch_bounds__(256) void fill_batch_kernel(const FillJob *__restri
   }
 }
 
-// f = -du^i/dn = -i (k.n) e^{i k.x} on the P x M surface nodes, folded into
-// f_hat_b = (1/P) sum_l f_l e^{-2 pi i b l / P}.  One workgroup per 8 rings
-// of one wave; twiddles from an exact table in LDS.
+// f = -du^i/dn = -i (k.n) e^{i k.x} (value = 0) or f = -u^i (value = 1, the
+// transmission case) on the P x M surface nodes, folded into
+// f_hat_b = (1/P) sum_l f_l e^{-2 pi i b l / P} and written at
+// out[(w P + b) ldo + m].  One workgroup per 8 rings of one wave; twiddles
+// from an exact table in LDS.
 constexpr int RM = 8;
-__global__ __launch_bounds__(256) void rhs_kernel(int M, int P, const double *__restrict__ rho,
+__global__ __launch_bounds__(256) void rhs_kernel(int M, int P, int ldo, int value, const double *__restrict__ rho,
                                                   const double *__restrict__ zc,
                                                   const double *__restrict__ nrho,
                                                   const double *__restrict__ nzc,
@@ -192,8 +204,8 @@ __global__ __launch_bounds__(256) void rhs_kernel(int M, int P, const double *__
       const double kn = kx * nrho[m] * cp + ky * nrho[m] * sp + kzv * nzc[m];
       double s, c;
       sincos(kx * x + ky * y + kzv * zc[m], &s, &c);
-      // -i kn (c + i s) = kn s - i kn c
-      v = cz(kn * s, -kn * c);
+      // -i kn (c + i s) = kn s - i kn c ; or -(c + i s)
+      v = value ? cz(-c, -s) : cz(kn * s, -kn * c);
     }
     f[idx] = v;
   }
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(int M, int P, const double *__
       ph += b;
       if (ph >= P) ph -= P;
     }
-    out[((size_t)w * P + b) * M + m] = cscale(acc, invP);
+    out[((size_t)w * P + b) * ldo + m] = cscale(acc, invP);
   }
 }
 
@@ -225,7 +237,7 @@ void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s) {
   auto cost = [&](int i) { return (double)(bodies[i]->q / 2 + 1) * (bodies[i]->nd + 1); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
   std::vector<DevBuf> tabs(nb);
-  std::vector<FillJob> jobs(nb);
+  std::vector<FillJob> jobs;
   long tiles = 0;
   for (int o = 0; o < nb; ++o) {
     BodyData &b = *bodies[order[o]];
@@ -234,13 +246,26 @@ void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s) {
     tabs[o].alloc((size_t)L * (b.nd + 1) * sizeof(double));
     hipLaunchKernelGGL(fill_table_kernel, dim3(cdiv(L * (b.nd + 1), 256)), dim3(256), 0, s, b.q, b.nd,
                        tabs[o].as<double>());
-    FillJob &J = jobs[o];
-    J.M = b.M; J.N = b.N; J.q = b.q; J.nd = b.nd; J.ldA = b.ldA; J.k = b.k;
-    J.rho = b.rho; J.z = b.z; J.nrho = b.nrho; J.nz = b.nz; J.srho = b.srho; J.sz = b.sz;
+    FillJob J{};
+    J.M = b.M; J.N = b.N; J.q = b.q; J.nd = b.nd; J.ldA = b.ldA; J.ncols = b.cols;
+    J.rho = b.rho; J.z = b.z; J.nrho = b.nrho; J.nz = b.nz;
     J.tab = tabs[o].as<double>();
-    J.A = b.blocks.as<double2>();
-    J.tile0 = tiles;
-    tiles += ((long)b.M * b.N + TP - 1) / TP;
+    double2 *A0 = b.blocks.as<double2>();
+    auto add = [&](int value, double k, double sign, const double *srho, const double *sz, double2 *A) {
+      J.value = value; J.k = k; J.sign = sign; J.srho = srho; J.sz = sz; J.A = A;
+      J.tile0 = tiles;
+      tiles += ((long)b.M * b.N + TP - 1) / TP;
+      jobs.push_back(J);
+    };
+    if (!b.trans()) {
+      add(0, b.k, 1.0, b.srho, b.sz, A0);
+    } else {
+      // eq. (trans): rows [values; normal derivatives], columns [exterior; interior]
+      add(1, b.k, 1.0, b.srho, b.sz, A0);
+      add(0, b.k, 1.0, b.srho, b.sz, A0 + b.M);
+      add(1, b.km, -1.0, b.srho2, b.sz2, A0 + (size_t)b.N * b.ldA);
+      add(0, b.km, -1.0, b.srho2, b.sz2, A0 + (size_t)b.N * b.ldA + b.M);
+    }
   }
   HIP_CHECK(hipGetLastError());
   DevBuf jd(jobs.size() * sizeof(FillJob)), ctr(sizeof(unsigned long long));
@@ -250,8 +275,8 @@ void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s) {
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const long grid = std::min<long>(tiles, (long)ncu * 4);
-  hipLaunchKernelGGL(fill_batch_kernel, dim3((unsigned)grid), dim3(256), 0, s, jd.as<FillJob>(), nb, tiles,
-                     ctr.as<unsigned long long>());
+  hipLaunchKernelGGL(fill_batch_kernel, dim3((unsigned)grid), dim3(256), 0, s, jd.as<FillJob>(), (int)jobs.size(),
+                     tiles, ctr.as<unsigned long long>());
   HIP_CHECK(hipGetLastError());
   // the tables and job list are freed on return; make sure the kernel is done with them
   HIP_CHECK(hipStreamSynchronize(s));
@@ -261,8 +286,16 @@ void launch_fill(BodyData &b, hipStream_t s) { launch_fill_all({&b}, s); }
 
 void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out, hipStream_t s) {
   const size_t sh = (size_t)(b.P + RM * b.P) * sizeof(double2);
-  hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(b.M, RM), nw), dim3(256), sh, s, b.M, b.P, b.rho, b.z,
-                     b.nrho, b.nz, kvec_dev, out);
+  if (!b.trans()) {
+    hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(b.M, RM), nw), dim3(256), sh, s, b.M, b.P, b.M, 0, b.rho, b.z,
+                       b.nrho, b.nz, kvec_dev, out);
+  } else {
+    // [f_hat; f_hat'] per mode: f = -u^i in rows [0, M), f' = -du^i/dn in rows [M, 2M)
+    hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(b.M, RM), nw), dim3(256), sh, s, b.M, b.P, b.rows, 1, b.rho, b.z,
+                       b.nrho, b.nz, kvec_dev, out);
+    hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(b.M, RM), nw), dim3(256), sh, s, b.M, b.P, b.rows, 0, b.rho, b.z,
+                       b.nrho, b.nz, kvec_dev, out + b.M);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

@@ -235,7 +235,7 @@ __global__ void zero_kernel(double2 *p, long n) {
 // dH_lm/dn at (rho_i, 0, z_i) with normal (nrho_i, 0, nz_i): out[lm][i].
 __global__ __launch_bounds__(64) void bfill_kernel(int M, int p, double k, const double *rho,
                                                    const double *z, const double *nrho,
-                                                   const double *nz, double2 *out) {
+                                                   const double *nz, double2 *out, int value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   double j[MAXP + 1], jp[MAXP + 1];
@@ -245,15 +245,16 @@ __global__ __launch_bounds__(64) void bfill_kernel(int M, int p, double k, const
   legendre_visit(p, s.ct, s.st, [&](int l, int m, double P, double dP) {
     const double dr = k * jp[l] * P, dth = j[l] * dP / s.r;
     // d/drho = st d/dr + ct/r d/dth ; d/dz = ct d/dr - st/r d/dth  (phi = 0)
-    const double v = nr * (s.st * dr + s.ct * dth) + nzz * (s.ct * dr - s.st * dth);
+    const double v = value ? j[l] * P : nr * (s.st * dr + s.ct * dth) + nzz * (s.ct * dr - s.st * dth);
     out[(size_t)lm_col(l, m) * M + i] = cz(v, 0.0);
     if (m > 0) out[(size_t)lm_col(l, -m) * M + i] = cz((m & 1) ? -v : v, 0.0);
   });
 }
 
-// out[r][b][i] -= sum over (l, mm) with mm = b (mod P) of B[lm][i] d[r][lm]
+// out[r][b][i] -= sum over (l, mm) with mm = b (mod P) of B[lm][i] d[r][lm];
+// out[r][b][i] at (r P + b) ldo + i
 __global__ void bapply_kernel(int nrhs, int P, int M, int p, const double2 *__restrict__ B,
-                              const double2 *__restrict__ d, int ldd, double2 *__restrict__ out) {
+                              const double2 *__restrict__ d, int ldd, double2 *__restrict__ out, int ldo) {
   const long total = (long)nrhs * P * M;
   for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long)gridDim.x * blockDim.x) {
@@ -271,7 +272,8 @@ __global__ void bapply_kernel(int nrhs, int P, int M, int p, const double2 *__re
         cfma(acc, B[(size_t)col * M + i], d[(size_t)r * ldd + col]);
       }
     }
-    out[idx] = csub(out[idx], acc);
+    const size_t o = ((size_t)r * P + b) * ldo + i;
+    out[o] = csub(out[o], acc);
   }
 }
 
@@ -319,17 +321,18 @@ void launch_qfill(const QFillArgs &a, hipStream_t s) {
 }
 
 void launch_bfill(int M, int p, double k, const double *rho, const double *z, const double *nrho,
-                  const double *nz, double2 *out, hipStream_t s) {
+                  const double *nz, double2 *out, hipStream_t s, int value) {
   MFS_REQUIRE(p <= MAXP, "harmonic degree p exceeds 96");
-  hipLaunchKernelGGL(bfill_kernel, dim3(cdiv(M, 64)), dim3(64), 0, s, M, p, k, rho, z, nrho, nz, out);
+  hipLaunchKernelGGL(bfill_kernel, dim3(cdiv(M, 64)), dim3(64), 0, s, M, p, k, rho, z, nrho, nz, out, value);
   HIP_CHECK(hipGetLastError());
 }
 
 void launch_bapply(int nrhs, int P, int M, int p, const double2 *B, const double2 *d, int ldd,
-                   double2 *out, hipStream_t s) {
+                   double2 *out, hipStream_t s, int ldo) {
   const long n = (long)nrhs * P * M;
+  if (ldo <= 0) ldo = M;
   hipLaunchKernelGGL(bapply_kernel, dim3((unsigned)std::min<long>(2048, (n + 255) / 256)), dim3(256), 0, s,
-                     nrhs, P, M, p, B, d, ldd, out);
+                     nrhs, P, M, p, B, d, ldd, out, ldo);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -50,18 +50,26 @@ struct MatDesc {
 constexpr int kQRNB = 32;   // Householder panel width
 
 // One body of an operator: geometry and its P/2+1 distinct mode blocks.
+// Sound-hard (km = 0): blocks A'_n, rows = M, cols = N.  Transmission
+// (km > 0, eq. (trans)): blocks [[A_n, -A^-_n], [A'_n, -A'^-_n]] of
+// rows = 2M (values, then normal derivatives) by cols = 2N (exterior
+// coefficients with the sources inside, then interior coefficients at km
+// with the sources srho2, sz2 outside).
 struct BodyData {
   int M, N, P, q, nd, ldA;
-  double k;
-  DevBuf geom;        // rho z nrho nz [M] each, srho sz [N] each
+  int rows, cols;
+  double k, km = 0.0;
+  DevBuf geom;        // rho z nrho nz [M] each, srho sz [N] each, then srho2 sz2 [N] each
   double *rho, *z, *nrho, *nz, *srho, *sz;
-  std::vector<double> h_rho, h_z, h_nrho, h_nz, h_srho, h_sz;
-  DevBuf blocks;      // [nd][N][ldA]
+  double *srho2 = nullptr, *sz2 = nullptr;
+  std::vector<double> h_rho, h_z, h_nrho, h_nz, h_srho, h_sz, h_srho2, h_sz2;
+  bool trans() const { return km > 0.0; }
+  DevBuf blocks;      // [nd][cols][ldA]
   DevBuf fac;         // tau, T, g, v, u, w, sv, perm, rank, flag for all nd blocks
   DevBuf descs;       // MatDesc[nd] on device
   std::vector<MatDesc> h_descs;
   std::vector<int> rank;
-  std::vector<double> h_sv;   // [nd][N] singular values after mfs_factor_modes (descending, zero-filled)
+  std::vector<double> h_sv;   // [nd][cols] singular values after mfs_factor_modes (descending, zero-filled)
   DevBuf src_P;       // point sources at q = P angles, SoA x y z [P*N] each
 };
 
@@ -73,9 +81,11 @@ void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out,
 // out[r][b][x] = scale * sum_l in[r][l][x] e^{sgn 2 pi i b l / P}, r < nr, x < X
 void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, double scale,
                 hipStream_t s);
-// sigma[r][l][j] = (1/qs) sum_n c[r][bin(n)][j] e^{+i n 2 pi l / qs}
+// sigma[r][l][j] = (1/qs) sum_n c[r][bin(n)][j] e^{+i n 2 pi l / qs}, j < N;
+// c has ldc entries per bin (N, or 2N for the exterior half of a
+// transmission body's coefficients)
 void launch_point_strengths(int nr, int P, int qs, int N, const double2 *c, double2 *sigma,
-                            hipStream_t s);
+                            hipStream_t s, int ldc = 0);
 
 struct JacStats {
   double ms = 0.0;       // time of the sweep launches (HIP events)
@@ -148,12 +158,14 @@ struct QFillArgs {
   int ldq;
 };
 void launch_qfill(const QFillArgs &a, hipStream_t s);
-// Btilde: values dH_lm/dn at the surface rings (phi = 0): out [NH][M]
+// Btilde: values dH_lm/dn (value = 0) or H_lm (value = 1) at the surface
+// rings (phi = 0): out [NH][M]
 void launch_bfill(int M, int p, double k, const double *rho, const double *z, const double *nrho,
-                  const double *nz, double2 *out, hipStream_t s);
-// out[r][bin][m] -= sum_{(l,mm): mm = bin mod P} B[(l,mm)][m] d[r][(l,mm)] ; d stride ldd
+                  const double *nz, double2 *out, hipStream_t s, int value = 0);
+// out[r][bin][m] -= sum_{(l,mm): mm = bin mod P} B[(l,mm)][m] d[r][(l,mm)] ; d stride ldd;
+// out has ldo entries per bin (M, or 2M with the value rows first)
 void launch_bapply(int nrhs, int P, int M, int p, const double2 *B, const double2 *d, int ldd,
-                   double2 *out, hipStream_t s);
+                   double2 *out, hipStream_t s, int ldo = 0);
 // u[r][t] += sum_lm H_lm(x_t) d[r][lm]
 void launch_harm_field(int nrhs, int nt, const double *xyz, int p, double k, const double2 *d,
                        int ldd, double2 *out, hipStream_t s);

@@ -476,7 +476,7 @@ mfs_status mfs_server_create(mfs_ctx *ctx, const mfs_op *op, int32_t body, const
     const double rows = 8.0 * lat->M1 * lat->M1;
     sv->wave_factor_bytes = (rows * NQb + (double)NQb * NQb) * sizeof(double2);
     sv->wave_work_bytes = (4.0 * rows * NQb + 8.0 * (double)NQb * NQb) * sizeof(double2);
-    const double basis = (double)W * (cfg->maxit + 1) * b.P * b.M * sizeof(double2);
+    const double basis = (double)W * (cfg->maxit + 1) * b.P * b.rows * sizeof(double2);
     const double need = basis + sv->wave_factor_bytes + sv->wave_work_bytes;
     if ((double)cfg->hbm_budget < need) MFS_THROW(MFS_ENOMEM, "server: hbm_budget below one wave in flight");
     sv->it.reset(new Solver(op, b, *lat, W, cfg->maxit, sv->s_it));

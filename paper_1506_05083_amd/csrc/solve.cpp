@@ -22,7 +22,7 @@ namespace mfs {
 
 void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double2 *x, double2 *out,
                      hipStream_t s) {
-  const size_t need = (size_t)b.nd * 32 * b.N * sizeof(double2);
+  const size_t need = (size_t)b.nd * 32 * b.cols * sizeof(double2);
   double2 *yw = op_workspace(op, need);
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = std::min(16, nrhs - r0);
@@ -32,12 +32,12 @@ void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double
     j.P = b.P;
     j.nrhs = nr;
     j.maxcols = 2 * nr;
-    j.maxr = b.N;
-    j.maxm = b.M;
-    j.maxn = b.N;
+    j.maxr = b.cols;
+    j.maxm = b.rows;
+    j.maxn = b.cols;
     j.descs = b.descs.as<MatDesc>();
-    j.x = x + (size_t)r0 * b.P * b.M;
-    j.out = out + (size_t)r0 * b.P * b.N;
+    j.x = x + (size_t)r0 * b.P * b.rows;
+    j.out = out + (size_t)r0 * b.P * b.cols;
     j.ywork = yw;
     launch_pinv_apply(j, s);
   }

@@ -16,8 +16,10 @@
 
 namespace mfs {
 
+// launch_dft with the input rows ld_in apart and the output bins ldo apart
+// (ldo <= 0: X)
 void launch_dft_ld(int nr, int P, int X, const double2 *in, size_t ld_in, double2 *out, int sgn,
-                   double scale, hipStream_t s);
+                   double scale, hipStream_t s, int ldo = 0);
 
 using cplx = std::complex<double>;
 
@@ -31,13 +33,14 @@ struct Solver {
   BodyData &b;
   mfs_lattice lat;
   int W, P, M, N, MP, NH, rows, ldq, NQmax, maxit;
+  int Mr, Nc;   // per-mode system rows and columns (2M x 2N for transmission)
   hipStream_t s;
   std::vector<cplx> al, be;
   std::vector<double> kv;
   std::vector<std::vector<RBOrder>> orders;
   // periodizer
   std::vector<QStore> Q;
-  DevBuf qflags, qdescs, Bvals, walls_soa;
+  DevBuf qflags, qdescs, Bvals, Bvals_v, walls_soa;
   std::vector<MatDesc> h_qdescs;
   std::vector<int> qrank;
   GradedPinv gp;
@@ -57,7 +60,7 @@ struct Solver {
 
   Solver(const mfs_op *o, BodyData &body, const mfs_lattice &l, int nw, int mi, hipStream_t st)
       : op(o), b(body), lat(l), W(nw), maxit(mi), s(st) {
-    P = b.P; M = b.M; N = b.N; MP = P * M;
+    P = b.P; M = b.M; N = b.N; Mr = b.rows; Nc = b.cols; MP = P * Mr;
     NH = (lat.p + 1) * (lat.p + 1);
     rows = 8 * lat.M1 * lat.M1;
     ldq = round_up(rows, 16);
@@ -164,7 +167,7 @@ struct Solver {
     V.alloc((size_t)W * (maxit + 1) * MP * sizeof(double2));
     Z.alloc((size_t)W * MP * sizeof(double2));
     XIN.alloc((size_t)W * MP * sizeof(double2));
-    C.alloc((size_t)W * P * N * sizeof(double2));
+    C.alloc((size_t)W * P * Nc * sizeof(double2));
     SIG.alloc((size_t)W * P * N * sizeof(double2));
     GS.alloc((size_t)W * psurf.ntarget_pad * sizeof(double2));
     GH.alloc((size_t)W * MP * sizeof(double2));
@@ -173,7 +176,7 @@ struct Solver {
     XI.alloc((size_t)W * NQmax * sizeof(double2));
     const size_t part = std::max((size_t)nsplit_s * W * psurf.ntarget_pad, (size_t)nsplit_w * W * pwalls.ntarget_pad);
     PART.alloc(part * sizeof(double2));
-    YW.alloc(std::max((size_t)b.nd * 2 * W * N, (size_t)W * NQmax) * sizeof(double2));
+    YW.alloc(std::max((size_t)b.nd * 2 * W * Nc, (size_t)W * NQmax) * sizeof(double2));
     H1.alloc((size_t)W * (maxit + 2) * 2 * sizeof(double2));
     SC.alloc((size_t)W * sizeof(double));
   }
@@ -189,10 +192,15 @@ struct Solver {
     upload(wwalls.p, w2.data(), w2.size() * sizeof(double2), s);
   }
 
-  // B~ (the harmonics' Neumann data on the surface rings), wave independent
+  // B~ (the harmonics' Neumann data on the surface rings, and for a
+  // transmission body their values), wave independent
   void setup_bvals() {
     Bvals.alloc((size_t)NH * M * sizeof(double2));
-    launch_bfill(M, lat.p, b.k, b.rho, b.z, b.nrho, b.nz, Bvals.as<double2>(), s);
+    launch_bfill(M, lat.p, b.k, b.rho, b.z, b.nrho, b.nz, Bvals.as<double2>(), s, 0);
+    if (b.trans()) {
+      Bvals_v.alloc((size_t)NH * M * sizeof(double2));
+      launch_bfill(M, lat.p, b.k, b.rho, b.z, b.nrho, b.nz, Bvals_v.as<double2>(), s, 1);
+    }
   }
 
   // Recovery of the waves w with iters[w] > 0 from their GMRES coefficients
@@ -219,7 +227,7 @@ struct Solver {
     if (ntargets > 0) {
       DevBuf srcf, sigf((size_t)W * q_field * b.N * sizeof(double2));
       source_points(b, q_field, srcf, s);
-      launch_point_strengths(W, b.P, q_field, b.N, C.as<double2>(), sigf.as<double2>(), s);
+      launch_point_strengths(W, b.P, q_field, b.N, C.as<double2>(), sigf.as<double2>(), s, Nc);
       std::vector<double> u6((size_t)6 * ntargets, 0.0);
       for (int t = 0; t < ntargets; ++t)
         for (int k = 0; k < 3; ++k) u6[(size_t)6 * t + k] = targets[(size_t)3 * t + k];
@@ -281,7 +289,7 @@ struct Solver {
 
   void pinv_A0(const double2 *x, double2 *out) {
     PinvJob j{};
-    j.mode = 0; j.nmat = b.nd; j.P = P; j.nrhs = W; j.maxcols = 2 * W; j.maxr = N; j.maxm = M; j.maxn = N;
+    j.mode = 0; j.nmat = b.nd; j.P = P; j.nrhs = W; j.maxcols = 2 * W; j.maxr = Nc; j.maxm = Mr; j.maxn = Nc;
     j.descs = b.descs.as<MatDesc>(); j.x = x; j.out = out; j.ywork = YW.as<double2>();
     launch_pinv_apply(j, s);
   }
@@ -306,7 +314,7 @@ struct Solver {
 
   // XI = Q^+ (C c) for mode coefficients in C
   void c_then_qpinv(const double2 *cmodes) {
-    launch_point_strengths(W, P, P, N, cmodes, SIG.as<double2>(), s);
+    launch_point_strengths(W, P, P, N, cmodes, SIG.as<double2>(), s, Nc);
     nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
     PinvJob j{};
@@ -319,9 +327,17 @@ struct Solver {
   // out = (I + A_else A_0^+ - B Q^+ C A_0^+) x
   void apply_op(const double2 *x, double2 *out) {
     pinv_A0(x, C.as<double2>());
-    launch_point_strengths(W, P, P, N, C.as<double2>(), SIG.as<double2>(), s);
+    launch_point_strengths(W, P, P, N, C.as<double2>(), SIG.as<double2>(), s, Nc);
     nsum(psurf, wsurf, GS.as<double2>());
-    launch_dft_ld(W, P, M, GS.as<double2>(), psurf.ntarget_pad, GH.as<double2>(), -1, 1.0 / P, s);
+    if (!b.trans()) {
+      launch_dft_ld(W, P, M, GS.as<double2>(), psurf.ntarget_pad, GH.as<double2>(), -1, 1.0 / P, s, M);
+    } else {
+      // values (second target group) into rows [0, M), normal derivatives into [M, 2M)
+      launch_dft_ld(W, P, M, GS.as<double2>() + psurf.groups[1].t0, psurf.ntarget_pad, GH.as<double2>(), -1,
+                    1.0 / P, s, Mr);
+      launch_dft_ld(W, P, M, GS.as<double2>() + psurf.groups[0].t0, psurf.ntarget_pad, GH.as<double2>() + M, -1,
+                    1.0 / P, s, Mr);
+    }
     launch_axpby_op(W, MP, x, GH.as<double2>(), nullptr, out, s);
     // the wall rows reuse SIG computed above
     nsum(pwalls, wwalls, WR.as<double2>());
@@ -331,7 +347,12 @@ struct Solver {
     j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
     j.descs = qpinv_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
     launch_pinv_apply(j, s);
-    launch_bapply(W, P, M, lat.p, Bvals.as<double2>(), XI.as<double2>(), NQmax, out, s);
+    if (!b.trans()) {
+      launch_bapply(W, P, M, lat.p, Bvals.as<double2>(), XI.as<double2>(), NQmax, out, s, M);
+    } else {
+      launch_bapply(W, P, M, lat.p, Bvals_v.as<double2>(), XI.as<double2>(), NQmax, out, s, Mr);
+      launch_bapply(W, P, M, lat.p, Bvals.as<double2>(), XI.as<double2>(), NQmax, out + M, s, Mr);
+    }
   }
 
   double nsum_avg_ms() {
