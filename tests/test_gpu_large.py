@@ -125,3 +125,42 @@ def test_large_solve_one_wave(large):
     assert r.iters < pr.maxit and r.resid <= pr.gmres_tol
     assert np.all(np.isfinite(r.a)) and np.all(np.isfinite(r.b)) and np.all(np.isfinite(r.field))
     assert r.eps_flux < 1e-6
+
+
+def test_large_transmission_one_wave(large):
+    """The transmission variant at full size (km = 1.5 k, 1080 x 900 mode
+    blocks): the four value/derivative sub-blocks at sampled rows against
+    the oracle's ring sums, then one incident wave to the GMRES tolerance
+    with the flux balanced."""
+    from oracle import transmission as T
+    mfs, _, ctx, _, _, _ = large
+    pr = W.cup_periodic_large_transmission(1)
+    b, lat = pr.body, pr.lattice
+    g = mfs.transmission_geometry(b.shape, b.M, b.N, b.tau, b.colloc)
+    op = mfs.build_operator(ctx, [mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, g, km=pr.km)])
+    blk = op.blocks().cpu().numpy().transpose(0, 2, 1)       # [nd][2M][2N]
+    gi, go = T.geometries(b)
+    rows = np.array([0, 137, 270, 539])
+    nd = b.P // 2 + 1
+    ref = np.empty((nd, 2 * rows.size, 2 * b.N), dtype=np.complex128)
+    for half, (kk, gg, sgn) in enumerate(((b.k, gi, 1.0), (pr.km, go, -1.0))):
+        x = np.stack([gi.rho[rows], np.zeros(rows.size), gi.z[rows]], -1)[:, None, None, :]
+        nx = np.stack([gi.nrho[rows], np.zeros(rows.size), gi.nz[rows]], -1)[:, None, None, :]
+        y = np.transpose(geometry.source_ring_points(gg, b.q), (1, 0, 2))[None]
+        for part, smp in enumerate((kernel.G(kk, x, y), kernel.dG_dnx(kk, x, nx, y))):
+            mh = np.transpose((np.fft.fft(smp, axis=2) / b.q)[:, :, :nd], (2, 0, 1))
+            ref[:, part * rows.size:(part + 1) * rows.size, half * b.N:(half + 1) * b.N] = sgn * mh
+    got = np.concatenate([blk[:, rows, :], blk[:, b.M + rows, :]], axis=1)
+    err = rel(got, ref)
+    log(f"[large trans] fill at {2 * rows.size} rows of {2 * b.M} x {2 * b.N} blocks, {nd} modes: {err:.2e}")
+    assert err < 1e-12
+    op.factor_modes(1e-10)
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    res, tm = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=pr.gmres_tol,
+                                 maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field, timing=True)
+    r = res[0]
+    log(f"[large trans] wave 0: iters {r.iters} resid {r.resid:.2e} eps_flux {r.eps_flux:.2e}; "
+        f"periodizer {tm['periodizer'] / 1e3:.1f} s, GMRES {tm['gmres'] / 1e3:.1f} s")
+    assert r.iters < pr.maxit and r.resid <= pr.gmres_tol
+    assert np.all(np.isfinite(r.a)) and np.all(np.isfinite(r.b)) and np.all(np.isfinite(r.field))
+    assert r.eps_flux < 1e-6

@@ -255,6 +255,15 @@ def small_periodic_transmission(nwaves: int = 2) -> Problem:
     return replace(pr, name="small_periodic_transmission", km=1.5 * pr.body.k)
 
 
+def cup_periodic_large_transmission(nwaves: int = 8) -> Problem:
+    """The large configuration's transmission variant: the same cups,
+    lattice and discretisation with interior wavenumber km = 1.5 k (the
+    doubled sets: 2M x 2N = 1080 x 900 per mode; the exterior sources of the
+    interior field need q >= 485 by Theorem 1, under the q = 540 taken)."""
+    pr = cup_periodic_large(nwaves)
+    return replace(pr, name="cup_periodic_large_transmission", km=1.5 * pr.body.k)
+
+
 def serving_stream(count: int, seed_dirs: int = 4, seed_arrivals: int = 40):
     """Request stream of the serving configuration against the k = 10
     operator: incidences theta ~ U[0, pi/2), phi ~ U[0, 2 pi) from seed 4
