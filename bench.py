@@ -132,6 +132,39 @@ def run_batch_build(count: int):
                         "P U{32,64,96,128,160}, k U[5,30], M = ceil(1.2N), tau = 0.1"}
 
 
+def run_large(nwaves: int, transmission: bool):
+    """Large configuration (cups at k = 2 pi 13, N = 450, M = 540, P = 144),
+    or its transmission variant (km = 1.5 k): operator build and
+    factorisation, then nwaves incidences in one batched solve (near sums on
+    the fly: the stored form would need 645 GB)."""
+    import torch
+    import paper_1506_05083_amd as mfs
+
+    pr = (W.cup_periodic_large_transmission if transmission else W.cup_periodic_large)(nwaves)
+    b, lat = pr.body, pr.lattice
+    ctx = mfs.create(0)
+    if transmission:
+        g = mfs.transmission_geometry(b.shape, b.M, b.N, b.tau, b.colloc)
+    else:
+        g = mfs.body_geometry(b.shape, b.M, b.N, b.tau, b.colloc)
+    print(f"[large] {pr.name}: {nwaves} incidences", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = mfs.build_operator(ctx, [mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, g, km=pr.km)])
+    op.factor_modes(1e-10)
+    t1 = time.perf_counter()
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    res, tm = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=pr.gmres_tol,
+                                 maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field, timing=True)
+    t2 = time.perf_counter()
+    ot = op.timing()
+    return {"workload": pr.name, "incidences": nwaves, "build_factor_s": t1 - t0, "solve_s": t2 - t1,
+            "solves_per_s": nwaves / (t2 - t0), "fill_ms": ot["fill"], "qr_ms": ot["qr"], "trunc_ms": ot["svd"],
+            "periodizer_ms": tm["periodizer"], "gmres_ms": tm["gmres"], "jacobi_ms": tm["jacobi_ms"],
+            "nsum_avg_ms": tm["nsum_avg"], "gmres_iters": [r.iters for r in res],
+            "eps_flux_max": max(r.eps_flux for r in res), "q_cols": max(r.nq_cols for r in res)}
+
+
 def run_serving(pr: W.Problem, nreq: int, nplain: int, slots: int):
     """Serving configuration: requests of the seeded stream against the
     resident factored k = 10 operator.  Plain baseline: the first nplain
@@ -302,7 +335,16 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device to device (the reference for the HBM byte counters)")
+    ap.add_argument("--only", choices=["batch", "large", "large-transmission"],
+                    help="run one other configuration's measurement alone and print its JSON line")
+    ap.add_argument("--large-waves", type=int, default=8)
     args = ap.parse_args()
+    if args.only == "batch":
+        print(json.dumps(run_batch_build(args.batch_obstacles)))
+        return
+    if args.only in ("large", "large-transmission"):
+        print(json.dumps(run_large(args.large_waves, args.only == "large-transmission")))
+        return
     if args.copy_probe:
         import torch
         n = 1 << 28                        # 2 GiB of float64 read, 2 GiB written
