@@ -129,6 +129,7 @@ struct NsumPlan {
   // optional dense near field (nsum_build_dense): kernel values of every
   // group, image, source and target, for the sources `dense_src` (S of them)
   DevBuf dense, koff;
+  DevBuf sigT;        // [S][MAXR] strengths of one launch, source-major (scratch of the dense sum)
   const double *dense_src = nullptr;
   int dense_S = 0;
   double dense_k = 0.0;

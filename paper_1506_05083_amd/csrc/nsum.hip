@@ -22,6 +22,7 @@ namespace {
 
 constexpr int SC = 128;     // sources per LDS chunk (32 per wave)
 constexpr int MAXR = 16;    // right-hand sides per launch
+constexpr int DU = 16;      // stored values in flight per wave in the dense sum
 
 // G(x - y) = e^{ikR} / (4 pi R) for (dx, dy, dz) = x - y, or its derivative
 // along the target direction (tx, ty, tz) when deriv is set
@@ -162,23 +163,43 @@ __global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict
   }
 }
 
+// sigT[s][r] = sigma[r][s] for r < nrhs, zero up to NR: the strengths of one
+// source side by side, so that a wave reads them with one uniform address.
+__global__ void sig_transpose_kernel(int nrhs, int NRp, int S, const double2 *__restrict__ sigma,
+                                     double2 *__restrict__ sigT) {
+  const long n = (long)S * NRp;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i % NRp);
+    const long sidx = i / NRp;
+    sigT[i] = r < nrhs ? sigma[(size_t)r * S + sidx] : cz(0.0, 0.0);
+  }
+}
+
+// Stored near field: every wave of a workgroup streams its own contiguous
+// quarter of the split's sources for the workgroup's 64 targets (one lane
+// per target, 16 B per lane and source, coalesced), eight non-temporal loads
+// in flight, and takes the NR strengths of each source from sigT through a
+// wave-uniform address (scalar loads: no LDS staging, no barrier in the
+// loop).  The four waves' partial sums meet in LDS at the end.
 template <int NR>
 __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                          const int *__restrict__ tile_group,
                                                          const size_t *__restrict__ koff,
                                                          const double2 *__restrict__ dense, int nrhs, int S,
-                                                         const double2 *__restrict__ sigma,
+                                                         const double2 *__restrict__ sigT,
                                                          const double2 *__restrict__ wts, int nsplit,
                                                          double2 *__restrict__ out) {
   extern __shared__ double shm[];
-  double2 *ssig = reinterpret_cast<double2 *>(shm);   // [NR][SC]
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = tile * 64 + lane;
   const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per, s_end = min(S, s_begin + per);
+  const int qw = (s_end - s_begin + 3) / 4;
+  const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
   const double2 *base = dense + koff[gi] + (size_t)((t - t0) >> 6) * nimg * S * 64 + lane;
   double2 tot[NR];
 #pragma unroll
@@ -188,41 +209,32 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
     const double2 *kim = base + (size_t)im * S * 64;
-    for (int c0 = s_begin; c0 < s_end; c0 += SC) {
-      const int nc = min(SC, s_end - c0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < NR * SC; idx += 256) {
-        const int r = idx / SC, ss = idx % SC;
-        ssig[idx] = (r < nrhs && ss < nc) ? sigma[(size_t)r * S + c0 + ss] : cz(0.0, 0.0);
+    for (int c0 = w_begin; c0 < w_end; c0 += DU) {
+      double2 kv[DU];
+#pragma unroll
+      for (int e = 0; e < DU; ++e) {
+        // streamed once per launch: non-temporal loads keep them out of the caches
+        const bool ok = c0 + e < w_end;
+        const double2 *pk = kim + (size_t)(ok ? c0 + e : c0) * 64;
+        double2 v;
+        v.x = __builtin_nontemporal_load(&pk->x);
+        v.y = __builtin_nontemporal_load(&pk->y);
+        const long long m = ok ? -1LL : 0LL;
+        kv[e] = cz(__longlong_as_double(__double_as_longlong(v.x) & m),
+                   __longlong_as_double(__double_as_longlong(v.y) & m));
       }
-      __syncthreads();
-      // this wave's quarter of the chunk, eight values in flight
-      const int sb = wv * (SC / 4);
-      for (int u = 0; u < SC / 4; u += 8) {
-        double2 kv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          // streamed once per launch: non-temporal loads keep them out of the caches
-          const bool ok = sb + u + e < nc;
-          const double2 *pk = kim + (ok ? (size_t)(c0 + sb + u + e) * 64 : 0);
-          double2 v;
-          v.x = __builtin_nontemporal_load(&pk->x);
-          v.y = __builtin_nontemporal_load(&pk->y);
-          const long long m = ok ? -1LL : 0LL;
-          kv[e] = cz(__longlong_as_double(__double_as_longlong(v.x) & m),
-                     __longlong_as_double(__double_as_longlong(v.y) & m));
-        }
+      for (int e = 0; e < DU; ++e) {
+        // a source past the wave's range (kv = 0) reads the last valid row
+        const double2 *sv = sigT + (size_t)min(c0 + e, w_end - 1) * NR;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[r], kv[e], ssig[r * SC + sb + u + e]);
+        for (int r = 0; r < NR; ++r) cfma(acc[r], kv[e], sv[r]);
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
       if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
   }
-  __syncthreads();
   double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
 #pragma unroll
   for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot[r];
@@ -268,10 +280,14 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
 template <int NR>
 void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *sigma, const double2 *w,
                          int nsplit, double2 *dst, hipStream_t s) {
-  const size_t sh = std::max((size_t)NR * SC * sizeof(double2), (size_t)4 * NR * 64 * sizeof(double2));
+  double2 *sigT = plan.sigT.as<double2>();
+  const long n = (long)S * NR;
+  hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
+                     nrhs, NR, S, sigma, sigT);
+  const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
   hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
                      plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
-                     plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigma, w, nsplit, dst);
+                     plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -289,9 +305,13 @@ void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double e
 
 }  // namespace
 
+// Source slices per tile: about five rounds of resident workgroups (256 CUs x
+// 3 workgroups of 256 threads for the stored-field sum), rounded down so that
+// the last round is (nearly) full: 240 surface tiles -> 16 slices, 3840
+// workgroups.
 int nsum_splits(const NsumPlan &plan, int S) {
   const int tiles = plan.ntarget_pad / 64;
-  int ns = std::max(1, cdiv(2048, tiles));
+  int ns = std::max(1, 3840 / tiles);
   ns = std::min(ns, std::max(1, S / 256));
   return ns;
 }
@@ -336,6 +356,7 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   HIP_CHECK(hipMemGetInfo(&fr, &tot));
   if (bytes + ((size_t)2 << 30) > fr) return false;   // keep 2 GiB of headroom
   plan.dense.alloc(bytes);
+  plan.sigT.alloc((size_t)S * MAXR * sizeof(double2));
   plan.koff.alloc(koff.size() * sizeof(size_t));
   HIP_CHECK(hipMemcpyAsync(plan.koff.p, koff.data(), koff.size() * sizeof(size_t), hipMemcpyHostToDevice, s));
   const int nsplit = nsum_splits(plan, S);

@@ -188,6 +188,115 @@ __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__
   }
 }
 
+// The whole panel at k0 of a matrix whose rows from k0 on fit one workgroup
+// (m - k0 <= blockDim.x <= 512): one row per thread with the row's panel
+// entries in registers, the NB column steps of bqr_col_kernel carried out
+// in turn with block-wide sums (wave sums, then across the waves in LDS)
+// instead of one launch each, so the panel is read and written once.  The
+// arithmetic of a step is that of bqr_col_kernel: x^H a_c over the rows
+// r >= j, |x(2:)|^2 over r > j, LAPACK's zlarfg reflector.
+constexpr int PTMAX = 512;             // threads (rows) of the one-launch panel
+constexpr int PWMAX = PTMAX / 64;
+__global__ __launch_bounds__(PTMAX) void bqr_panel_kernel(const MatDesc *__restrict__ descs, int k0) {
+  const MatDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  const int nbp = min(NB, d.n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  const int r = k0 + tid;
+  const bool live = r < d.m;
+  __shared__ double2 red[PWMAX][NPART];
+  __shared__ double2 fin[NPART];
+  __shared__ double2 srow[NB];
+  __shared__ double2 s_scale, s_tau, s_alpha;
+  __shared__ double s_beta;
+  __shared__ int s_refl;
+  double2 vals[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) vals[c] = ld_or0(d.a, (size_t)(k0 + c) * d.lda + r, live && c < nbp);
+  for (int s = 0; s < nbp; ++s) {
+    const int j = k0 + s;
+    double2 x = cz(0.0, 0.0);   // vals[s] without a run-time index into the array
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c == s) x = vals[c];
+    if (live && r == j) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c >= s && c < nbp) srow[c] = vals[c];
+    }
+    const double2 xr = (live && r >= j) ? x : cz(0.0, 0.0);
+    {
+      double q = (live && r > j) ? cabs2(x) : 0.0;
+      q = wave_sum(q);
+      if (lane == 0) red[wv][0] = cz(q, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c > s && c < nbp) {
+        double2 p = cz(0.0, 0.0);
+        cfmac(p, xr, vals[c]);
+        p = wave_sum(p);
+        if (lane == 0) red[wv][1 + c] = p;
+      }
+    }
+    __syncthreads();
+    if (tid < NPART && (tid == 0 || (tid - 1 > s && tid - 1 < nbp))) {
+      double2 t = red[0][tid];
+      for (int w = 1; w < nw; ++w) t = cadd(t, red[w][tid]);
+      fin[tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double ssum = fin[0].x;
+      const double2 alpha = srow[s];
+      s_alpha = alpha;
+      if (ssum == 0.0 && alpha.y == 0.0) {
+        s_refl = 0;
+        s_tau = cz(0.0, 0.0);
+        s_beta = alpha.x;
+        s_scale = cz(0.0, 0.0);
+      } else {
+        const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + ssum), alpha.x);
+        const double2 den = cz(alpha.x - beta, alpha.y);
+        const double dd = cabs2(den);
+        s_refl = 1;
+        s_tau = cz((beta - alpha.x) / beta, -alpha.y / beta);
+        s_beta = beta;
+        s_scale = cz(den.x / dd, -den.y / dd);
+      }
+      d.tau[j] = s_tau;
+    }
+    __syncthreads();
+    const double2 scale = s_scale, tau = s_tau, alpha = s_alpha;
+    const int refl = s_refl;
+    if (live && r >= j) {
+      const double2 v = (r == j) ? cz(1.0, 0.0) : (refl ? cmul(x, scale) : x);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c > s && c < nbp) {
+          // w_c = v^H a_c = a_c(j) + conj(scale) (x^H a_c - conj(alpha) a_c(j))
+          const double2 acj = srow[c];
+          double2 w = csub(fin[1 + c], cmul(cconj(alpha), acj));
+          w = cadd(acj, cmul(cconj(scale), w));
+          const double2 f = refl ? cmul(cconj(tau), w) : cz(0.0, 0.0);
+          vals[c] = csub(vals[c], cmul(v, f));
+        }
+      }
+      const double2 nv = (r == j) ? (refl ? cz(s_beta, 0.0) : alpha) : v;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c == s) vals[c] = nv;
+    }
+    __syncthreads();   // srow, fin and the scalars are rewritten by the next step
+  }
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nbp) d.a[(size_t)(k0 + c) * d.lda + r] = vals[c];
+  }
+}
+
 // Y columns: which = 0 -> trailing columns of the matrix after the panel,
 // which = 1 -> columns [0, rank) of d.u.
 __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, double2 *&B, int &ldb,
@@ -520,11 +629,17 @@ void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t 
   ApplyWork w;
   w.size(nmat, mmax, nmax);
   for (int k0 = 0; k0 < nmax; k0 += NB) {
-    const int nch = cdiv(std::max(mmax - k0, 1), CH);
     const int nbp = std::min(NB, nmax - k0);
-    for (int st = -1; st < nbp; ++st)
-      hipLaunchKernelGGL(bqr_col_kernel, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st, part.as<double2>(),
-                         side.as<double2>(), nchmax);
+    if (mmax - k0 <= PTMAX) {
+      // every matrix's remaining rows fit one workgroup: the panel in one launch
+      const int threads = round_up(std::max(mmax - k0, 1), 64);
+      hipLaunchKernelGGL(bqr_panel_kernel, dim3(nmat), dim3(threads), 0, s, descs, k0);
+    } else {
+      const int nch = cdiv(std::max(mmax - k0, 1), CH);
+      for (int st = -1; st < nbp; ++st)
+        hipLaunchKernelGGL(bqr_col_kernel, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st, part.as<double2>(),
+                           side.as<double2>(), nchmax);
+    }
     HIP_CHECK(hipGetLastError());
     apply_panel(descs, nmat, mmax, std::max(0, nmax - k0 - NB), k0, 0, 1, 1, w, true, s);
   }
