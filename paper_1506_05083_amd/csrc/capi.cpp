@@ -469,6 +469,10 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
     HIP_CHECK(hipEventElapsedTime(&ms_svd, op->ev[1], op->ev[2]));
     op->ms_qr += ms_qr;
     op->ms_svd += ms_svd;
+    int ldo = 0;
+    for (size_t i = c0; i < c1; ++i) ldo = std::max(ldo, items[i].m.n);
+    std::vector<double> sv;
+    g->singular_values(ldo, sv, s);
     for (size_t i = c0; i < c1; ++i) {
       const Item &it = items[i];
       BodyData &b = *op->bodies[it.body];
@@ -476,9 +480,8 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
       b.rank[it.d] = g->kept[i - c0];
       // the Jacobi factor holds the r leading singular values; the rest are
       // below 1e-15 of the largest and stay zero
-      const MatDesc &l = g->h_lq[i - c0];
-      HIP_CHECK(hipMemcpy(b.h_sv.data() + (size_t)it.d * b.cols, l.sv, std::min(l.n, b.cols) * sizeof(double),
-                          hipMemcpyDeviceToHost));
+      std::copy(sv.begin() + (i - c0) * ldo, sv.begin() + (i - c0) * ldo + std::min(ldo, b.cols),
+                b.h_sv.begin() + (size_t)it.d * b.cols);
     }
     g->release_work();
     op->gps.push_back(std::move(g));

@@ -139,6 +139,12 @@ __global__ void scatter_w_kernel(const MatDesc *__restrict__ ld, const MatDesc *
   for (int i = threadIdx.x; i < l.m; i += blockDim.x) w[pw[vw[i]]] = src[i];
 }
 
+// out[w][i] = singular value i of matrix w (zero past its n), ld entries per matrix
+__global__ void sv_gather_kernel(const MatDesc *__restrict__ ld, int ldo, double *__restrict__ out) {
+  const MatDesc l = ld[blockIdx.x];
+  for (int i = threadIdx.x; i < ldo; i += blockDim.x) out[(size_t)blockIdx.x * ldo + i] = i < l.n ? l.sv[i] : 0.0;
+}
+
 constexpr int PK = 512;   // threads of the pivot/reflector kernel
 
 // Step k of column-pivoted QR, part 1 (one workgroup per matrix): move the
@@ -299,6 +305,12 @@ __global__ __launch_bounds__(256) void build_t_kernel(const MatDesc *__restrict_
 
 }  // namespace
 
+// bytes of n complex entries rounded up to 256 (the arena alignment)
+static size_t arena_bytes(size_t n) { return (n * sizeof(double2) + 255) / 256 * 256; }
+static double2 *arena_at(const DevBuf &b, size_t off) {
+  return reinterpret_cast<double2 *>(static_cast<char *>(b.p) + off);
+}
+
 static void upload_descs(DevBuf &buf, const std::vector<MatDesc> &h, hipStream_t s) {
   buf.alloc(h.size() * sizeof(MatDesc));
   HIP_CHECK(hipMemcpyAsync(buf.p, h.data(), h.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
@@ -342,19 +354,30 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   const bool pivot = n2max >= pivot_min_cols;
   g.pivoted = pivot;
   // 2. QR without pivoting of the selected, ordered columns
-  g.qc.resize(W);
   g.h_qc.resize(W);
   g.small.alloc((size_t)4 * W * sizeof(int));
   int *flags = g.small.as<int>();
+  // one allocation per kind for the whole batch (a matrix's pieces at 256-byte
+  // aligned offsets): thousands of matrices cost no allocation each
+  std::vector<size_t> oa(W), of(W);
+  {
+    size_t ta = 0, tf = 0;
+    for (int w = 0; w < W; ++w) {
+      const int ldq = in[w].lda, n = n2[w], npan = cdiv(n, kQRNB);
+      oa[w] = ta;
+      ta += arena_bytes((size_t)ldq * n);
+      of[w] = tf;
+      tf += arena_bytes((size_t)n + (size_t)npan * kQRNB * kQRNB + (size_t)ldq * n);
+    }
+    g.qc_a.alloc(ta);
+    g.qc_fac.alloc(tf);
+  }
   for (int w = 0; w < W; ++w) {
     const int m = in[w].m, ldq = in[w].lda, n = n2[w];
     const int npan = cdiv(n, kQRNB);
-    auto &st = g.qc[w];
-    st.a.alloc((size_t)ldq * n * sizeof(double2));
-    st.fac.alloc(((size_t)n + (size_t)npan * kQRNB * kQRNB + (size_t)ldq * n) * sizeof(double2));
     MatDesc d{};
-    double2 *p = st.fac.as<double2>();
-    d.a = st.a.as<double2>(); d.m = m; d.n = n; d.lda = ldq;
+    double2 *p = arena_at(g.qc_fac, of[w]);
+    d.a = arena_at(g.qc_a, oa[w]); d.m = m; d.n = n; d.lda = ldq;
     d.tau = p; p += n;
     d.T = p; p += (size_t)npan * kQRNB * kQRNB;
     d.u = p;
@@ -380,17 +403,24 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     HIP_CHECK(hipStreamSynchronize(s));
   }
   if (pivot) {
-    g.rq.resize(W);
     g.h_rq.resize(W);
+    {
+      size_t ta = 0, tf = 0;
+      for (int w = 0; w < W; ++w) {
+        const int n = n2[w], ldr = round_up(n, 16), npan = cdiv(n, kQRNB);
+        oa[w] = ta;
+        ta += arena_bytes((size_t)ldr * n);
+        of[w] = tf;
+        tf += arena_bytes((size_t)n + (size_t)npan * kQRNB * kQRNB);
+      }
+      g.rq_a.alloc(ta);
+      g.rq_fac.alloc(tf);
+    }
     for (int w = 0; w < W; ++w) {
       const int n = n2[w], ldr = round_up(n, 16);
-      const int npan = cdiv(n, kQRNB);
-      auto &st = g.rq[w];
-      st.a.alloc((size_t)ldr * n * sizeof(double2));
-      st.fac.alloc(((size_t)n + (size_t)npan * kQRNB * kQRNB) * sizeof(double2));
       MatDesc d{};
-      double2 *p = st.fac.as<double2>();
-      d.a = st.a.as<double2>(); d.m = n; d.n = n; d.lda = ldr;
+      double2 *p = arena_at(g.rq_fac, of[w]);
+      d.a = arena_at(g.rq_a, oa[w]); d.m = n; d.n = n; d.lda = ldr;
       d.tau = p; p += n;
       d.T = p;
       d.flag = flags + 3 * W + w;
@@ -437,19 +467,28 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.rows = rr;
   g.cols = n2;
   // 3. QR of R_top^H (n2 x r)  and  4. Jacobi on L = (R factor)^H
-  g.lq.resize(W);
   g.h_lq.resize(W);
+  {
+    size_t ta = 0, tf = 0;
+    for (int w = 0; w < W; ++w) {
+      const int m = n2[w], n = rr[w];
+      const int ld2 = round_up(m, 16), ldg = round_up(n, 16), npan = cdiv(n, kQRNB);
+      oa[w] = ta;
+      ta += arena_bytes((size_t)ld2 * n);
+      of[w] = tf;
+      // tau, T, g, v, u, then sv and perm (2 n doubles' worth)
+      tf += arena_bytes((size_t)n + (size_t)npan * kQRNB * kQRNB + 2 * (size_t)n * ldg + (size_t)ld2 * n + n);
+    }
+    g.lq_a.alloc(ta);
+    g.lq_fac.alloc(tf);
+  }
   for (int w = 0; w < W; ++w) {
     const int m = n2[w], n = rr[w];
     const int ld2 = round_up(m, 16), ldg = round_up(n, 16);
     const int npan = cdiv(n, kQRNB);
-    auto &st = g.lq[w];
-    st.a.alloc((size_t)ld2 * n * sizeof(double2));
-    const size_t nc = (size_t)n + (size_t)npan * kQRNB * kQRNB + 2 * (size_t)n * ldg + (size_t)ld2 * n;
-    st.fac.alloc(nc * sizeof(double2) + (size_t)2 * n * sizeof(double));
-    double2 *p = st.fac.as<double2>();
+    double2 *p = arena_at(g.lq_fac, of[w]);
     MatDesc d{};
-    d.a = st.a.as<double2>(); d.m = m; d.n = n; d.lda = ld2;
+    d.a = arena_at(g.lq_a, oa[w]); d.m = m; d.n = n; d.lda = ld2;
     d.tau = p; p += n;
     d.T = p; p += (size_t)npan * kQRNB * kQRNB;
     d.g = p; p += (size_t)n * ldg;
@@ -493,15 +532,21 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   }
   qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, kmax, s);
   qr_form_u(g.d_lq.as<MatDesc>(), g.h_lq, kmax, s);
-  g.fin.resize(W);
   g.h_fin.resize(W);
+  {
+    size_t tf = 0;
+    for (int w = 0; w < W; ++w) {
+      of[w] = tf;
+      tf += arena_bytes((size_t)round_up(in[w].n, 16) * std::max(1, g.kept[w]));
+    }
+    g.fin_w.alloc(tf);
+  }
   for (int w = 0; w < W; ++w) {
     const int n = in[w].n, ldw = round_up(n, 16);
-    g.fin[w].alloc((size_t)ldw * std::max(1, g.kept[w]) * sizeof(double2));
     MatDesc d{};
     d.m = in[w].m; d.n = n; d.lda = g.h_qc[w].lda;
     d.u = g.h_qc[w].u;
-    d.w = g.fin[w].as<double2>();
+    d.w = arena_at(g.fin_w, of[w]);
     d.ldg = ldw;
     d.rank = flags + W + w;
     g.h_fin[w] = d;
@@ -512,6 +557,17 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
                        g.perm.as<int>(), g.piv.as<int>(), nmax);
     HIP_CHECK(hipGetLastError());
   }
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+void GradedPinv::singular_values(int ldo, std::vector<double> &out, hipStream_t s) const {
+  const int W = (int)h_lq.size();
+  out.assign((size_t)W * ldo, 0.0);
+  if (W == 0 || ldo <= 0) return;
+  DevBuf buf(out.size() * sizeof(double));
+  hipLaunchKernelGGL(sv_gather_kernel, dim3(W), dim3(256), 0, s, d_lq.as<MatDesc>(), ldo, buf.as<double>());
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemcpyAsync(out.data(), buf.p, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
 }
 

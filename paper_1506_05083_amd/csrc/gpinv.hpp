@@ -8,12 +8,11 @@
 namespace mfs {
 
 struct GradedPinv {
-  struct Store {
-    DevBuf a, fac;
-  };
   DevBuf d_in, d_qc, d_rq, d_rqu, d_lq, d_fin, perm, piv, small;
-  std::vector<Store> qc, rq, lq;
-  std::vector<DevBuf> fin;
+  // one allocation per kind for all matrices of the batch (per-matrix pieces
+  // at aligned offsets): the QR'd copies and their tau, T and U, the pivoted
+  // triangles, the LQ/Jacobi factors, and W
+  DevBuf qc_a, qc_fac, rq_a, rq_fac, lq_a, lq_fac, fin_w;
   std::vector<MatDesc> h_qc, h_rq, h_rqu, h_lq, h_fin;
   std::vector<double> maxcol;
   std::vector<int> cols, rows, kept;
@@ -26,14 +25,15 @@ struct GradedPinv {
   // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
   const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
   // free the factorisation's work, keeping what the apply reads (U in
-  // qc[w].fac, W in fin, the kept ranks in small)
+  // qc_fac, W in fin_w, the kept ranks in small)
   void release_work() {
     d_in.release(); d_qc.release(); d_rq.release(); d_rqu.release(); d_lq.release();
     perm.release(); piv.release();
-    for (auto &q : qc) q.a.release();
-    rq.clear();
-    lq.clear();
+    qc_a.release(); rq_a.release(); rq_fac.release(); lq_a.release(); lq_fac.release();
   }
+  // singular values of every matrix, [W][ldo] (descending, zero past n);
+  // before release_work.  Blocking.
+  void singular_values(int ldo, std::vector<double> &out, hipStream_t s) const;
 };
 
 // in[w]: matrix w (a, m, n, lda) only.  Fills g; blocking.  The

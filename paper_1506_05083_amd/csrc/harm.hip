@@ -135,7 +135,8 @@ __device__ inline int lm_col(int l, int m) { return l * l + l + m; }
 
 // One thread per (unit, node): units LR, FB (pairs of walls) and T, D; each
 // writes two rows of Q: value and normal-derivative (discrepancy or Cauchy).
-__global__ __launch_bounds__(64) void qfill_s_kernel(QFillArgs a) {
+__global__ __launch_bounds__(64) void qfill_s_kernel(const QFillArgs *__restrict__ args) {
+  const QFillArgs a = args[blockIdx.y];   // one incidence per grid row
   const int M1sq = a.M1 * a.M1;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 4 * M1sq) return;
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(64) void qfill_s_kernel(QFillArgs a) {
 }
 
 // -W blocks: rows of T (value, d/dz) for the a_mn columns and of D for b_mn.
-__global__ void qfill_w_kernel(QFillArgs a) {
+__global__ void qfill_w_kernel(const QFillArgs *__restrict__ args) {
+  const QFillArgs a = args[blockIdx.y];   // one incidence per grid row
   const int M1sq = a.M1 * a.M1;
   const int NH = (a.p + 1) * (a.p + 1);
   const long total = (long)4 * M1sq * a.nrb;
@@ -305,19 +307,30 @@ __global__ __launch_bounds__(64) void harm_field_kernel(int nrhs, int nt, const 
 
 }  // namespace
 
-void launch_qfill(const QFillArgs &a, hipStream_t s) {
-  MFS_REQUIRE(a.p <= MAXP, "harmonic degree p exceeds 96");
-  const int M1sq = a.M1 * a.M1;
-  const int NQ = (a.p + 1) * (a.p + 1) + 2 * a.nrb;
-  const long n = (long)a.ldq * NQ;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<long>(4096, (n + 255) / 256)), dim3(256), 0, s,
-                     a.Q, n);
-  hipLaunchKernelGGL(qfill_s_kernel, dim3(cdiv(4 * M1sq, 64)), dim3(64), 0, s, a);
-  const long nw = (long)4 * M1sq * a.nrb;
+void launch_qfill(const std::vector<QFillArgs> &h, hipStream_t s) {
+  const int W = (int)h.size();
+  if (W == 0) return;
+  const int M1sq = h[0].M1 * h[0].M1;
+  int nrbmax = 0;
+  for (const auto &a : h) {
+    MFS_REQUIRE(a.p <= MAXP, "harmonic degree p exceeds 96");
+    MFS_REQUIRE(a.M1 == h[0].M1 && a.p == h[0].p, "one wall grid and degree per batch");
+    nrbmax = std::max(nrbmax, a.nrb);
+    const long n = (long)a.ldq * ((a.p + 1) * (a.p + 1) + 2 * a.nrb);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<long>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                       a.Q, n);
+  }
+  DevBuf args(h.size() * sizeof(QFillArgs));
+  HIP_CHECK(hipMemcpyAsync(args.p, h.data(), h.size() * sizeof(QFillArgs), hipMemcpyHostToDevice, s));
+  // every incidence in one grid: the harmonics of a wall node are a long
+  // serial evaluation per thread, so the incidences side by side fill the chip
+  hipLaunchKernelGGL(qfill_s_kernel, dim3(cdiv(4 * M1sq, 64), W), dim3(64), 0, s, args.as<QFillArgs>());
+  const long nw = (long)4 * M1sq * nrbmax;
   if (nw > 0)
-    hipLaunchKernelGGL(qfill_w_kernel, dim3((unsigned)std::min<long>(4096, (nw + 255) / 256)), dim3(256),
-                       0, s, a);
+    hipLaunchKernelGGL(qfill_w_kernel, dim3((unsigned)std::min<long>(4096, (nw + 255) / 256), W), dim3(256), 0, s,
+                       args.as<QFillArgs>());
   HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(s));   // the argument array is released on return
 }
 
 void launch_bfill(int M, int p, double k, const double *rho, const double *z, const double *nrho,

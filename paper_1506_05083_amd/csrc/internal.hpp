@@ -158,7 +158,8 @@ struct QFillArgs {
   double2 *Q;             // column-major [8 M1^2][ldq]
   int ldq;
 };
-void launch_qfill(const QFillArgs &a, hipStream_t s);
+// Q of every incidence of a batch (same wall grid and degree), zeroed then filled
+void launch_qfill(const std::vector<QFillArgs> &h, hipStream_t s);
 // Btilde: values dH_lm/dn (value = 0) or H_lm (value = 1) at the surface
 // rings (phi = 0): out [NH][M]
 void launch_bfill(int M, int p, double k, const double *rho, const double *z, const double *nrho,

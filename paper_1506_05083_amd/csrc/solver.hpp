@@ -81,6 +81,7 @@ struct Solver {
     h_qdescs.resize(W);
     NQmax = 0;
     std::vector<DevBuf> ordbufs(W);
+    std::vector<QFillArgs> qargs(W);
     for (int w = 0; w < W; ++w) {
       const int nrb = (int)orders[w].size();
       const int NQ = NH + 2 * nrb;
@@ -119,8 +120,9 @@ struct Solver {
       a.wall = walls_soa.as<double>();
       a.kx = kxd; a.ky = kyd; a.kz = kzd;
       a.Q = d.a; a.ldq = ldq;
-      launch_qfill(a, s);
+      qargs[w] = a;
     }
+    launch_qfill(qargs, s);
     qdescs.alloc(W * sizeof(MatDesc));
     upload(qdescs.p, h_qdescs.data(), W * sizeof(MatDesc), s);
     HIP_CHECK(hipStreamSynchronize(s));   // ordbufs are released on return

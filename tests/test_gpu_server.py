@@ -151,3 +151,33 @@ def test_server_queue_full(mfs, setup):
                 assert srv.wait(t)[2]
     finally:
         srv.close()
+
+
+def test_server_transmission_matches_plain(mfs):
+    """A transmission operator (2M x 2N mode blocks) behind the server: each
+    request's result equals the one-at-a-time plain solve (the plain solve is
+    checked against the oracle in the transmission parity tests)."""
+    pr = W.small_periodic_transmission(nwaves=3)
+    b, lat = pr.body, pr.lattice
+    ctx = mfs.create(0)
+    g = mfs.transmission_geometry(b.shape, b.M, b.N, b.tau, b.colloc)
+    op = mfs.build_operator(ctx, [mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, g, km=pr.km)])
+    op.factor_modes(1e-10)
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    waves = [(w.theta, w.phi) for w in pr.waves]
+    ref = [mfs.solve_incident(ctx, op, L, [w], tol=1e-12, maxit=100, targets=pr.targets, q_field=pr.q_field)[0]
+           for w in waves]
+    srv = mfs.Server(ctx, op, L, slots=2, admit_batch=2, tol=1e-12, maxit=100, targets=pr.targets,
+                     q_field=pr.q_field, hbm_budget=48 << 30)
+    try:
+        tks = [srv.submit(*w) for w in waves]
+        got = [srv.wait(t) for t in tks]
+    finally:
+        srv.close()
+    for i, (res, lat_ms, ok) in enumerate(got):
+        assert ok
+        d = same(res, ref[i])
+        log(f"[server trans] wave {i}: iters {res.iters} (plain {ref[i].iters}) vs plain {d:.2e} "
+            f"eps_flux {res.eps_flux:.2e}")
+        assert d <= 1e-12
+        assert res.eps_flux < 1e-6
