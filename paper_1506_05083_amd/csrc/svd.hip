@@ -10,14 +10,15 @@
 // b + t|gamma|.  The same rotations accumulate V.  At convergence
 // G = U S with orthogonal columns, s_i = |g_i|.
 //
-// Blocked form for the GPU: the columns are cut into blocks of 16 and the
+// Blocked form for the GPU: the columns are cut into blocks of JB (16, or 32
+// once a batch's widest matrix has kJacWideMinCols columns) and the
 // round-robin (circle) schedule pairs the blocks, n_b - 1 rounds per sweep.
-// A task is a block pair (32 columns); a round is three launches over all
-// tasks of all matrices:
-//   1. jac_gram_kernel: partial H = G_IJ^H G_IJ (32 x 32) over 128-row
+// A task is a block pair (JC = 2 JB columns); a round is three launches over
+// all tasks of all matrices:
+//   1. jac_gram_kernel: partial H = G_IJ^H G_IJ (JC x JC) over 128-row
 //      tiles, every entry a dot product of two columns, staged through LDS;
 //   2. jac_inner_kernel (one workgroup per task): H summed over the tiles,
-//      one Jacobi sweep over the 32 columns carried out on H in LDS (the
+//      one Jacobi sweep over the JC columns carried out on H in LDS (the
 //      two-sided update H <- R^H H R of each rotation R, with the exact
 //      diagonal formulas above and the annihilated entry set to zero), the
 //      product J of the rotations accumulated alongside;
@@ -62,9 +63,8 @@ __global__ void jac_clear_flags(const MatDesc *__restrict__ descs, int nmat) {
   if (i < nmat) descs[i].flag[0] = 0;
 }
 
-constexpr int JB = 16;        // columns per block
-constexpr int JC = 2 * JB;    // columns per task
-constexpr int JR = 64;        // rows per LDS chunk
+constexpr int JR = 64;        // rows per LDS chunk of the Gram kernel
+constexpr int kJacWideMinCols = 2048;  // 32-column blocks from this width on
 
 __device__ inline void circle_pair(int np, int round, int pair, int &p, int &q) {
   const int mod = np - 1;
@@ -81,8 +81,9 @@ __device__ inline void circle_pair(int np, int round, int pair, int &p, int &q) 
 constexpr int GT = 128;   // rows per workgroup of the partial Gram matrices
 constexpr int AT = 64;    // rows per workgroup of the rotation apply
 
-// Blocks (bi, bj) of block pair `pair` of matrix d in this round; false if
-// the pair is out of range or both blocks are padding.
+// Blocks (bi, bj) of block pair `pair` of matrix d in this round (blocks of
+// JB columns); false if the pair is out of range or both blocks are padding.
+template <int JB>
 __device__ inline bool task_blocks(const MatDesc &d, int round, int pair, int &bi, int &bj, int &nb) {
   nb = (d.n + JB - 1) / JB;
   const int nbp = nb + (nb & 1);
@@ -93,18 +94,24 @@ __device__ inline bool task_blocks(const MatDesc &d, int round, int pair, int &b
   return bi < nb || bj < nb;
 }
 // column of local index a of the task (-1: past n or in the padding block)
+template <int JB>
 __device__ inline int task_col(int a, int bi, int bj, int nb, int n) {
   const int blk = a < JB ? bi : bj;
   const int c = blk * JB + (a & (JB - 1));
   return (blk < nb && c < n) ? c : -1;
 }
 
-// 1. partial Gram matrices: hpart[mat][pair][tile] = G_IJ(rows of tile)^H G_IJ(rows of tile)
-//    lane (ti, tj) -> entries H[ti + 8k][tj + 8k2]; wave -> rows wv, wv + 4, ... of a 64-row chunk
+// 1. partial Gram matrices: hpart[mat][pair][tile] = G_IJ(rows of tile)^H G_IJ(rows of tile).
+//    Lane (ti, tj) holds the entries H[oi + ti + 8k][oj + tj + 8k2], k, k2 < 4, of a
+//    32 x 32 piece: for JB = 16 the whole H with the waves splitting the rows of a
+//    chunk (summed in LDS at the end), for JB = 32 wave w's quadrant
+//    (oi, oj) = 32 (w >> 1, w & 1) over every row.
+template <int JB>
 __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict__ descs,
                                                        const int *__restrict__ act, int round,
                                                        double2 *__restrict__ hpart, int npair_max,
                                                        int ntile_max) {
+  constexpr int JC = 2 * JB;
   const int mat = blockIdx.z;
   if (!act[mat]) return;
   const MatDesc d = descs[mat];
@@ -116,11 +123,12 @@ __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   {
     int bi, bj, nb;
-    if (!task_blocks(d, round, blockIdx.y, bi, bj, nb)) return;
-    if (tid < JC) colx[tid] = task_col(tid, bi, bj, nb, n);
+    if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
+    if (tid < JC) colx[tid] = task_col<JB>(tid, bi, bj, nb, n);
   }
   __syncthreads();
   const int ti = lane >> 3, tj = lane & 7;
+  const int oi = JB == 32 ? 32 * (wv >> 1) : 0, oj = JB == 32 ? 32 * (wv & 1) : 0;
   double2 acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -138,12 +146,12 @@ __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict
 #pragma unroll
     for (int i = 0; i < JC * JR / 256; ++i) Gs[lane][wv + 4 * i] = pre[i];
     __syncthreads();
-    for (int rr = wv; rr < JR; rr += 4) {
+    for (int rr = JB == 32 ? 0 : wv; rr < JR; rr += JB == 32 ? 1 : 4) {
       double2 x[4], y[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        x[k] = Gs[rr][ti + 8 * k];
-        y[k] = Gs[rr][tj + 8 * k];
+        x[k] = Gs[rr][oi + ti + 8 * k];
+        y[k] = Gs[rr][oj + tj + 8 * k];
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -151,6 +159,14 @@ __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict
         for (int k2 = 0; k2 < 4; ++k2) cfmac(acc[k][k2], x[k], y[k2]);
     }
     __syncthreads();
+  }
+  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
+  if (JB == 32) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) out[(oi + ti + 8 * k) * JC + oj + tj + 8 * k2] = acc[k][k2];
+    return;
   }
   // sum the four waves in LDS (Gs reused as a 32 x 33 array)
   for (int w = 0; w < 4; ++w) {
@@ -165,24 +181,25 @@ __global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict
     }
     __syncthreads();
   }
-  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
   for (int idx = tid; idx < JC * JC; idx += 256) out[idx] = Gs[idx / JC][idx % JC];
 }
 
 // 2. one workgroup per task: H = sum of the partials, one Jacobi sweep over
-//    its 32 columns on H, J = product of the rotations -> jbuf, rot = any rotation
-__global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restrict__ descs,
+//    its JC columns on H, J = product of the rotations -> jbuf, rot = any rotation
+template <int JB>
+__global__ __launch_bounds__(JB * JB) void jac_inner_kernel(const MatDesc *__restrict__ descs,
                                                         const int *__restrict__ act, int round, double tol_eps,
                                                         const double2 *__restrict__ hpart,
                                                         double2 *__restrict__ jbuf, int *__restrict__ rot,
                                                         int npair_max, int ntile_max) {
+  constexpr int JC = 2 * JB, IT = JB * JB;   // one 2 x 2 block of H per thread
   const int mat = blockIdx.y;
   if (!act[mat]) return;
   const MatDesc d = descs[mat];
   const int pair = blockIdx.x;
   {
     int bi, bj, nb;
-    if (!task_blocks(d, round, pair, bi, bj, nb)) return;
+    if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
   }
   __shared__ double2 Hs[JC][JC + 1];
   __shared__ double2 Js[JC][JC + 1];
@@ -197,29 +214,29 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
   const double tol = tol_eps * sqrt((double)d.n), tol2 = tol * tol;
   const double2 *hp = hpart + ((size_t)mat * npair_max + pair) * ntile_max * JC * JC;
   {
-    double2 h[JC * JC / 256];
+    double2 h[JC * JC / IT];
 #pragma unroll
-    for (int u = 0; u < JC * JC / 256; ++u) h[u] = cz(0.0, 0.0);
+    for (int u = 0; u < JC * JC / IT; ++u) h[u] = cz(0.0, 0.0);
     for (int t = 0; t < ntile; ++t) {
 #pragma unroll
-      for (int u = 0; u < JC * JC / 256; ++u) h[u] = cadd(h[u], hp[(size_t)t * JC * JC + tid + 256 * u]);
+      for (int u = 0; u < JC * JC / IT; ++u) h[u] = cadd(h[u], hp[(size_t)t * JC * JC + tid + IT * u]);
     }
 #pragma unroll
-    for (int u = 0; u < JC * JC / 256; ++u) {
-      const int idx = tid + 256 * u;
+    for (int u = 0; u < JC * JC / IT; ++u) {
+      const int idx = tid + IT * u;
       Hs[idx / JC][idx % JC] = h[u];
       Js[idx / JC][idx % JC] = cz(idx / JC == idx % JC ? 1.0 : 0.0, 0.0);
     }
   }
   if (tid == 0) s_nrot = 0;
   __syncthreads();
-  // one sweep over the 32 columns on H.  Rotation of pair (p, q) from
+  // one sweep over the JC columns on H.  Rotation of pair (p, q) from
   // a = H_pp, b = H_qq, gamma = H_pq, d = b - a:
   //   q' = 2 sign(d) / (|d| + sqrt(d^2 + 4 |gamma|^2)),  t = q' |gamma|,
   //   c = 1 / sqrt(1 + t^2),  s e^{i th} = c q' gamma,  t |gamma| = q' |gamma|^2
   // (the formulas of the header with zeta = d / (2 |gamma|), |gamma| never formed).
   // H <- R^H H R acts on every 2 x 2 block (rows of pair i, columns of pair j)
-  // on its own: one thread per block, J <- J R alongside.
+  // on its own: JB x JB blocks over the threads, J <- J R alongside.
   for (int rnd = 0; rnd < JC - 1; ++rnd) {
     if (tid < JB) {
       int p, q;
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
       }
       {
         // H block (pair i rows, pair j columns)
-        const int bi = tid >> 4, bj = tid & 15;
+        const int bi = tid / JB, bj = tid % JB;
         int p, q, u, v;
         circle_pair(JC, rnd, bi, p, q);
         circle_pair(JC, rnd, bj, u, v);
@@ -287,7 +304,7 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
           }
           Hs[p][u] = h_pu; Hs[p][v] = h_pv; Hs[q][u] = h_qu; Hs[q][v] = h_qv;
         }
-        // J columns of pair bj, rows 2 (tid >> 4) and 2 (tid >> 4) + 1
+        // J columns of pair bj, rows 2 bi and 2 bi + 1
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int k = 2 * bi + e;
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
     __syncthreads();   // H, J and the flags of this round settled before the next
   }
   double2 *jo = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
-  for (int idx = tid; idx < JC * JC; idx += 256) jo[idx] = Js[idx / JC][idx % JC];
+  for (int idx = tid; idx < JC * JC; idx += IT) jo[idx] = Js[idx / JC][idx % JC];
   if (tid == 0) {
     rot[(size_t)mat * npair_max + pair] = s_nrot > 0;
     if (s_nrot > 0) atomicAdd(d.flag, 1);
@@ -313,10 +330,16 @@ __global__ __launch_bounds__(256) void jac_inner_kernel(const MatDesc *__restric
 
 // 3. G_IJ <- G_IJ J and V_IJ <- V_IJ J on 64-row tiles (tiles [0, nt) of G,
 //    [nt, 2 nt) of V); thread -> rows tx + 16a, columns 4 cq + b
-__global__ __launch_bounds__(128) void jac_apply_kernel(const MatDesc *__restrict__ descs,
-                                                        const int *__restrict__ act, int round,
-                                                        const double2 *__restrict__ jbuf,
-                                                        const int *__restrict__ rot, int npair_max) {
+template <int JB>
+constexpr int apply_threads() { return JB == 16 ? 128 : 256; }
+
+template <int JB>
+__global__ __launch_bounds__(apply_threads<JB>()) void jac_apply_kernel(const MatDesc *__restrict__ descs,
+                                                                        const int *__restrict__ act, int round,
+                                                                        const double2 *__restrict__ jbuf,
+                                                                        const int *__restrict__ rot,
+                                                                        int npair_max) {
+  constexpr int JC = 2 * JB, NT = apply_threads<JB>();
   const int mat = blockIdx.z;
   if (!act[mat]) return;
   const MatDesc d = descs[mat];
@@ -330,32 +353,32 @@ __global__ __launch_bounds__(128) void jac_apply_kernel(const MatDesc *__restric
   const int tid = threadIdx.x;
   {
     int bi, bj, nb;
-    if (!task_blocks(d, round, pair, bi, bj, nb)) return;
+    if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
     if (!rot[(size_t)mat * npair_max + pair]) return;
-    if (tid < JC) colx[tid] = task_col(tid, bi, bj, nb, n);
+    if (tid < JC) colx[tid] = task_col<JB>(tid, bi, bj, nb, n);
   }
   double2 *M = (int)blockIdx.x < nt ? d.g : d.v;
   const int r0 = ((int)blockIdx.x % nt) * AT;
   const double2 *ji = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
   __syncthreads();
   {
-    double2 pre[AT * JC / 128], jj[JC * JC / 128];
+    double2 pre[AT * JC / NT], jj[JC * JC / NT];
 #pragma unroll
-    for (int u = 0; u < AT * JC / 128; ++u) {
-      const int idx = tid + 128 * u, a = idx / AT, rr = idx % AT;
+    for (int u = 0; u < AT * JC / NT; ++u) {
+      const int idx = tid + NT * u, a = idx / AT, rr = idx % AT;
       const int c = colx[a], r = r0 + rr;
       pre[u] = ld_or0(M, (size_t)(c < 0 ? 0 : c) * d.ldg + r, c >= 0 && r < n);
     }
 #pragma unroll
-    for (int u = 0; u < JC * JC / 128; ++u) jj[u] = ji[tid + 128 * u];
+    for (int u = 0; u < JC * JC / NT; ++u) jj[u] = ji[tid + NT * u];
 #pragma unroll
-    for (int u = 0; u < AT * JC / 128; ++u) {
-      const int idx = tid + 128 * u;
+    for (int u = 0; u < AT * JC / NT; ++u) {
+      const int idx = tid + NT * u;
       Gs[idx % AT][idx / AT] = pre[u];
     }
 #pragma unroll
-    for (int u = 0; u < JC * JC / 128; ++u) {
-      const int idx = tid + 128 * u;
+    for (int u = 0; u < JC * JC / NT; ++u) {
+      const int idx = tid + NT * u;
       Js[idx / JC][idx % JC] = jj[u];
     }
   }
@@ -432,8 +455,11 @@ __global__ __launch_bounds__(256) void jac_sort_kernel(const MatDesc *__restrict
 
 }  // namespace
 
-JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
-                 hipStream_t s) {
+namespace {
+
+template <int JB>
+JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, hipStream_t s) {
+  constexpr int JC = 2 * JB;
   JacStats st;
   const int nmat = (int)h.size();
   int nmax = 0, nbpmax = 0;
@@ -488,11 +514,11 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
     HIP_CHECK(hipEventRecord(e0, s));
     for (int rnd = 0; rnd < rounds; ++rnd) {
-      hipLaunchKernelGGL(jac_gram_kernel, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
+      hipLaunchKernelGGL(jac_gram_kernel<JB>, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
                          act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
-      hipLaunchKernelGGL(jac_inner_kernel, dim3(npair_max, nmat), dim3(256), 0, s, descs, act.as<int>(), rnd,
+      hipLaunchKernelGGL(jac_inner_kernel<JB>, dim3(npair_max, nmat), dim3(JB * JB), 0, s, descs, act.as<int>(), rnd,
                          tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max);
-      hipLaunchKernelGGL(jac_apply_kernel, dim3(2 * atile_max, npair_max, nmat), dim3(128), 0, s, descs,
+      hipLaunchKernelGGL(jac_apply_kernel<JB>, dim3(2 * atile_max, npair_max, nmat), dim3(apply_threads<JB>()), 0, s, descs,
                          act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
     }
     HIP_CHECK(hipGetLastError());
@@ -525,6 +551,21 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
+}
+
+}  // namespace
+
+JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
+                 hipStream_t s) {
+  (void)rel_cutoff;
+  int nmax = 0;
+  for (const auto &d : h) nmax = std::max(nmax, d.n);
+  // 32-column blocks halve the passes over G and V per sweep (one per block
+  // round) at the price of an inner problem of twice as many rounds per
+  // task; that pays only once the passes over G and V dominate (measured:
+  // slower at 600 and 800 columns, faster at several thousand)
+  if (nmax >= kJacWideMinCols) return jac_run_t<32>(descs, h, init_mode, s);
+  return jac_run_t<16>(descs, h, init_mode, s);
 }
 
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,
