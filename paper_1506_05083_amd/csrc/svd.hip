@@ -414,6 +414,154 @@ __global__ __launch_bounds__(apply_threads<JB>()) void jac_apply_kernel(const Ma
   }
 }
 
+// FP64 matrix-core forms of steps 1 and 3 for 16-column blocks.  One
+// v_mfma_f64_16x16x4f64 multiplies a 16 x 4 block A (lane i + 16 k holds
+// A[i][k]) by a 4 x 16 block B (lane j + 16 k holds B[k][j]) into a 16 x 16
+// accumulator D (lane j + 16 g holds D[g + 4 v][j] in its v-th element).  A
+// complex product is four real ones on the split real and imaginary parts.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dx4 mfma_f64(double a, double b, dx4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// 1'. partial Gram matrix of one GT-row tile, one wave per workgroup.  The
+//     rows are the summation index: step s takes rows 4 s + k of the tile, and
+//     the fragment a lane loads (row 4 s + k of task column c) is at once its
+//     A operand (conj(G)^T) and its B operand (G), for the column blocks
+//     (0, 0), (0, 1) and (1, 1); block (1, 0) is the conjugate transpose of
+//     (0, 1).
+__global__ __launch_bounds__(64) void jac_gram_mfma_kernel(const MatDesc *__restrict__ descs,
+                                                           const int *__restrict__ act, int round,
+                                                           double2 *__restrict__ hpart, int npair_max,
+                                                           int ntile_max) {
+  constexpr int JB = 16, JC = 32, KB = 8;
+  const int mat = blockIdx.z;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int n = d.n;
+  const int rbeg = blockIdx.x * GT;
+  if (rbeg >= n) return;
+  int bi, bj, nb;
+  if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
+  const int l = threadIdx.x, c = l & 15, k = l >> 4;
+  const int c0 = task_col<JB>(c, bi, bj, nb, n), c1 = task_col<JB>(JB + c, bi, bj, nb, n);
+  const double2 *g0 = d.g + (size_t)max(c0, 0) * d.ldg, *g1 = d.g + (size_t)max(c1, 0) * d.ldg;
+  const int rend = min(n, rbeg + GT);
+  dx4 r00 = {0, 0, 0, 0}, i00 = r00, r01 = r00, i01 = r00, r11 = r00, i11 = r00;
+  for (int rb = rbeg; rb < rend; rb += 4 * KB) {   // uniform trip count
+    double2 x0[KB], x1[KB];
+#pragma unroll
+    for (int s = 0; s < KB; ++s) {
+      const int r = rb + 4 * s + k;
+      x0[s] = ld_or0(g0, r, r < rend && c0 >= 0);
+      x1[s] = ld_or0(g1, r, r < rend && c1 >= 0);
+    }
+#pragma unroll
+    for (int s = 0; s < KB; ++s) {
+      // conj(x_I)^T x_J: real part xr^T xr + xi^T xi, imaginary xr^T xi - xi^T xr
+      r00 = mfma_f64(x0[s].x, x0[s].x, r00);
+      r00 = mfma_f64(x0[s].y, x0[s].y, r00);
+      i00 = mfma_f64(x0[s].x, x0[s].y, i00);
+      i00 = mfma_f64(-x0[s].y, x0[s].x, i00);
+      r01 = mfma_f64(x0[s].x, x1[s].x, r01);
+      r01 = mfma_f64(x0[s].y, x1[s].y, r01);
+      i01 = mfma_f64(x0[s].x, x1[s].y, i01);
+      i01 = mfma_f64(-x0[s].y, x1[s].x, i01);
+      r11 = mfma_f64(x1[s].x, x1[s].x, r11);
+      r11 = mfma_f64(x1[s].y, x1[s].y, r11);
+      i11 = mfma_f64(x1[s].x, x1[s].y, i11);
+      i11 = mfma_f64(-x1[s].y, x1[s].x, i11);
+    }
+  }
+  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
+  const int j = l & 15, g = l >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = g + 4 * v;
+    out[i * JC + j] = cz(r00[v], i00[v]);
+    out[(JB + i) * JC + JB + j] = cz(r11[v], i11[v]);
+    out[i * JC + JB + j] = cz(r01[v], i01[v]);
+    out[(JB + j) * JC + i] = cz(r01[v], -i01[v]);
+  }
+}
+
+// 3'. G_IJ <- G_IJ J and V_IJ <- V_IJ J: one wave per 64-row tile (tiles
+//     [0, nt) of G, [nt, 2 nt) of V), four 16-row blocks and all 32 task
+//     columns, so that each fragment of J serves four row blocks; step s sums
+//     over task columns 4 s .. 4 s + 3.  The wave reads its rows of every
+//     column before it writes any, and tiles share no rows, so the update is
+//     in place.
+__global__ __launch_bounds__(64) void jac_apply_mfma_kernel(const MatDesc *__restrict__ descs,
+                                                            const int *__restrict__ act, int round,
+                                                            const double2 *__restrict__ jbuf,
+                                                            const int *__restrict__ rot, int npair_max) {
+  constexpr int JB = 16, JC = 32, KS = JC / 4, RB = AT / 16;
+  const int mat = blockIdx.z;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int n = d.n;
+  const int pair = blockIdx.y;
+  const int nt = (n + AT - 1) / AT;
+  if ((int)blockIdx.x >= 2 * nt) return;
+  int bi, bj, nb;
+  if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
+  if (!rot[(size_t)mat * npair_max + pair]) return;
+  const int l = threadIdx.x;
+  const int r0 = ((int)blockIdx.x % nt) * AT;
+  double2 *M = (int)blockIdx.x < nt ? d.g : d.v;
+  const double2 *ji = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
+  const int i = l & 15, k = l >> 4;
+  double2 b0[KS], b1[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    b0[s] = ji[(4 * s + k) * JC + i];
+    b1[s] = ji[(4 * s + k) * JC + JB + i];
+  }
+  dx4 re0[RB], im0[RB], re1[RB], im1[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    re0[rb] = dx4{0, 0, 0, 0};
+    im0[rb] = re0[rb];
+    re1[rb] = re0[rb];
+    im1[rb] = re0[rb];
+  }
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int col = task_col<JB>(4 * s + k, bi, bj, nb, n);
+    const double2 *mc = M + (size_t)max(col, 0) * d.ldg;
+    double2 a[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int r = r0 + 16 * rb + i;
+      a[rb] = ld_or0(mc, r, r < n && col >= 0);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      re0[rb] = mfma_f64(a[rb].x, b0[s].x, re0[rb]);
+      re0[rb] = mfma_f64(-a[rb].y, b0[s].y, re0[rb]);
+      im0[rb] = mfma_f64(a[rb].x, b0[s].y, im0[rb]);
+      im0[rb] = mfma_f64(a[rb].y, b0[s].x, im0[rb]);
+      re1[rb] = mfma_f64(a[rb].x, b1[s].x, re1[rb]);
+      re1[rb] = mfma_f64(-a[rb].y, b1[s].y, re1[rb]);
+      im1[rb] = mfma_f64(a[rb].x, b1[s].y, im1[rb]);
+      im1[rb] = mfma_f64(a[rb].y, b1[s].x, im1[rb]);
+    }
+  }
+  const int j = l & 15, g = l >> 4;
+  const int cA = task_col<JB>(j, bi, bj, nb, n), cB = task_col<JB>(JB + j, bi, bj, nb, n);
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + 16 * rb + g + 4 * v;
+      if (row < n) {
+        if (cA >= 0) M[(size_t)cA * d.ldg + row] = cz(re0[rb][v], im0[rb][v]);
+        if (cB >= 0) M[(size_t)cB * d.ldg + row] = cz(re1[rb][v], im1[rb][v]);
+      }
+    }
+}
+
 // Column norms, descending order (rank by counting, ties by index), kept rank.
 __global__ __launch_bounds__(256) void jac_sort_kernel(const MatDesc *__restrict__ descs,
                                                        double rel_cutoff) {
@@ -514,11 +662,19 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
     HIP_CHECK(hipEventRecord(e0, s));
     for (int rnd = 0; rnd < rounds; ++rnd) {
-      hipLaunchKernelGGL(jac_gram_kernel<JB>, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
-                         act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
+      if (JB == 16)
+        hipLaunchKernelGGL(jac_gram_mfma_kernel, dim3(ntile_max, npair_max, nmat), dim3(64), 0, s, descs,
+                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
+      else
+        hipLaunchKernelGGL(jac_gram_kernel<JB>, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
+                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
       hipLaunchKernelGGL(jac_inner_kernel<JB>, dim3(npair_max, nmat), dim3(JB * JB), 0, s, descs, act.as<int>(), rnd,
                          tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max);
-      hipLaunchKernelGGL(jac_apply_kernel<JB>, dim3(2 * atile_max, npair_max, nmat), dim3(apply_threads<JB>()), 0, s, descs,
+      if (JB == 16)
+        hipLaunchKernelGGL(jac_apply_mfma_kernel, dim3(2 * atile_max, npair_max, nmat), dim3(64), 0, s, descs,
+                           act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
+      else
+        hipLaunchKernelGGL(jac_apply_kernel<JB>, dim3(2 * atile_max, npair_max, nmat), dim3(apply_threads<JB>()), 0, s, descs,
                          act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
     }
     HIP_CHECK(hipGetLastError());
