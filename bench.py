@@ -407,8 +407,8 @@ def main():
     jac_flops = float(np.median([t["jacobi_flops"] / max(1, t["jacobi_launches"]) for t in tms]))
     jac_gbs = jac_bytes / (jac_launch_ms * 1e-3) / 1e9
     jac_tflops = jac_flops / (jac_launch_ms * 1e-3) / 1e12
-    jac_common = {"kernel": "jac_gram_kernel + jac_inner_kernel + jac_apply_kernel (periodizer "
-                            "pseudoinverse, 8 waves; per launch, three launches a round)",
+    jac_common = {"kernel": "jac_gram_mfma_kernel + jac_inner_kernel<16> + jac_apply_mfma_kernel "
+                            "(periodizer pseudoinverse, 8 waves; per launch, three launches a round)",
                   "traffic": None, "launch_ms": jac_launch_ms, "bytes_per_launch": jac_bytes,
                   "flops_per_launch": jac_flops, "flops_per_byte": jac_flops / max(jac_bytes, 1.0),
                   "share_of_step": jac_ms / ms_step}
