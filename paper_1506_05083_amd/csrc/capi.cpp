@@ -128,6 +128,18 @@ void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
   for (int a = -1; a <= 1; ++a)
     for (int c = -1; c <= 1; ++c)
       if (a != 0 || c != 0) { g.ia[g.nimg] = a; g.ib[g.nimg] = c; ++g.nimg; }
+  // The half-turn about the z axis maps the body onto itself, node (l, m)
+  // onto (l + P/2, m), source (l, j) onto (l + P/2, j) (both at angles
+  // 2 pi l / P, indices l M + m and l N + j) and the shift a e_x + b e_y onto
+  // its negative; kernel values and normal derivatives are invariant under
+  // it, so the images (a, b) and (-a, -b) share their stored values.
+  if (b.P % 2 == 0 && ((size_t)(b.P / 2) * b.M) % 64 == 0) {
+    g.mt = (b.P / 2) * b.M;
+    g.ms = (b.P / 2) * b.N;
+    for (int im = 0; im < g.nimg; ++im)
+      for (int jm = 0; jm < g.nimg; ++jm)
+        if (g.ia[jm] == -g.ia[im] && g.ib[jm] == -g.ib[im]) g.mir[im] = jm;
+  }
   std::vector<double> t((size_t)6 * g.nt);
   const size_t n = g.nt;
   for (int l = 0; l < b.P; ++l) {

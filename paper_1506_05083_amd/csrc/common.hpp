@@ -90,6 +90,17 @@ __device__ inline double2 ld_or0(const double2 *p, size_t i, bool ok) {
             __longlong_as_double(__double_as_longlong(v.y) & m));
 }
 
+// ----------------------------------------------------- FP64 matrix cores
+// One v_mfma_f64_16x16x4f64: D = A B + C with A 16 x 4 (lane i + 16 k holds
+// A[i][k]), B 4 x 16 (lane j + 16 k holds B[k][j]) and C, D 16 x 16 (lane
+// j + 16 g holds D[g + 4 v][j] in its v-th element; checked on gfx950 with
+// a one-instruction probe).  Every lane of the wave must be active.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dx4 mfma_f64(double a, double b, dx4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // ----------------------------------------------------- reductions
 // DPP lane move of a double (both 32-bit halves with the same pattern);
 // lanes whose source is outside the pattern, or whose row is masked off,

@@ -119,6 +119,13 @@ struct NsumGroup {
   int deriv;          // 0: value, 1: derivative along the target direction
   int nimg;
   int ia[9], ib[9];   // image shifts (a, b)
+  // Mirror pairing (0: none).  When the half-turn about the body's axis maps
+  // target t to t + mt (t < mt, mt a multiple of 64, nt = 2 mt) and source s
+  // to s + ms (mod S), image (a, b) onto image mir[.] = (-a, -b): the stored
+  // near field keeps the first mt targets only, and their values serve the
+  // other half through K_(-a,-b)[t + mt][s] = K_(a,b)[t][s + ms].
+  int mt, ms;
+  int mir[9];
 };
 struct NsumPlan {
   int ntarget_pad;    // targets padded per group to multiples of 64

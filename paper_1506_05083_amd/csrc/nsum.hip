@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
 // image and source are written once, per 64-target tile, image-major then
 // source-major with the tile's targets contiguous:
 //   dense[koff[g] + ((tile_g * nimg_g + img) * S + s) * 64 + lane],
-// so that every wave of the sum streams one contiguous range.
+// so that every wave of the sum streams one contiguous range; a mirror-paired
+// group (NsumGroup::mt) stores its first mt targets only.
 // The sums then stream them instead of evaluating them (they depend on the
 // geometry, the lattice and k only, not on the incident wave or the iterate).
 __global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict__ tgt, int ntp,
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
   const NsumGroup &g = groups[gi];
+  if (g.mt > 0 && tile * 64 - g.t0 >= g.mt) return;   // second half of a mirror pair: not stored
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = tile * 64 + lane;
   const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
@@ -177,11 +179,15 @@ __global__ void sig_transpose_kernel(int nrhs, int NRp, int S, const double2 *__
 
 // Stored near field: every wave of a workgroup streams its own contiguous
 // quarter of the split's sources for the workgroup's 64 targets (one lane
-// per target, 16 B per lane and source, coalesced), eight non-temporal loads
+// per target, 16 B per lane and source, coalesced), DUV non-temporal loads
 // in flight, and takes the NR strengths of each source from sigT through a
 // wave-uniform address (scalar loads: no LDS staging, no barrier in the
-// loop).  The four waves' partial sums meet in LDS at the end.
-template <int NR>
+// loop).  The four waves' partial sums meet in LDS at the end.  With MIR
+// (every group mirror-paired) the workgroup of a first-half tile also forms
+// the sums of its mirror targets t + mt from the same stored values, against
+// the strengths of the mirror sources s + ms and the weights of the mirror
+// images; second-half workgroups have nothing to do.
+template <int NR, bool MIR>
 __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                          const int *__restrict__ tile_group,
                                                          const size_t *__restrict__ koff,
@@ -189,6 +195,9 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
                                                          const double2 *__restrict__ sigT,
                                                          const double2 *__restrict__ wts, int nsplit,
                                                          double2 *__restrict__ out) {
+  // loads in flight per wave: the mirror form's second set of sums leaves
+  // registers for 8
+  constexpr int DUV = MIR ? 8 : DU;
   extern __shared__ double shm[];
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
@@ -196,23 +205,31 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = tile * 64 + lane;
   const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
+  const int mt = MIR ? groups[gi].mt : 0, ms = MIR ? groups[gi].ms : 0;
+  if (MIR && tile * 64 - t0 >= mt) return;   // served by the mirror tile
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per, s_end = min(S, s_begin + per);
   const int qw = (s_end - s_begin + 3) / 4;
   const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
   const double2 *base = dense + koff[gi] + (size_t)((t - t0) >> 6) * nimg * S * 64 + lane;
-  double2 tot[NR];
+  double2 tot[NR], tot2[MIR ? NR : 1];
 #pragma unroll
   for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
+  if (MIR)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tot2[r] = cz(0.0, 0.0);
   for (int im = 0; im < nimg; ++im) {
-    double2 acc[NR];
+    double2 acc[NR], acc2[MIR ? NR : 1];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
-    const double2 *kim = base + (size_t)im * S * 64;
-    for (int c0 = w_begin; c0 < w_end; c0 += DU) {
-      double2 kv[DU];
+    if (MIR)
 #pragma unroll
-      for (int e = 0; e < DU; ++e) {
+      for (int r = 0; r < NR; ++r) acc2[r] = cz(0.0, 0.0);
+    const double2 *kim = base + (size_t)im * S * 64;
+    for (int c0 = w_begin; c0 < w_end; c0 += DUV) {
+      double2 kv[DUV];
+#pragma unroll
+      for (int e = 0; e < DUV; ++e) {
         // streamed once per launch: non-temporal loads keep them out of the caches
         const bool ok = c0 + e < w_end;
         const double2 *pk = kim + (size_t)(ok ? c0 + e : c0) * 64;
@@ -224,16 +241,29 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
                    __longlong_as_double(__double_as_longlong(v.y) & m));
       }
 #pragma unroll
-      for (int e = 0; e < DU; ++e) {
+      for (int e = 0; e < DUV; ++e) {
         // a source past the wave's range (kv = 0) reads the last valid row
-        const double2 *sv = sigT + (size_t)min(c0 + e, w_end - 1) * NR;
+        const int sidx = min(c0 + e, w_end - 1);
+        const double2 *sv = sigT + (size_t)sidx * NR;
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], kv[e], sv[r]);
+        if (MIR) {
+          const int sm = sidx + ms >= S ? sidx + ms - S : sidx + ms;
+          const double2 *sv2 = sigT + (size_t)sm * NR;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc2[r], kv[e], sv2[r]);
+        }
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
       if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
+    if (MIR) {
+      const int jm = groups[gi].mir[im];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs) cfma(tot2[r], wts[((size_t)gi * 9 + jm) * nrhs + r], acc2[r]);
+    }
   }
   double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
 #pragma unroll
@@ -245,6 +275,19 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
     double2 v = red[(0 * NR + r) * 64 + l];
     for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
     out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = v;
+  }
+  if (MIR) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot2[r];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+      const int r = idx / 64, l = idx % 64;
+      if (r >= nrhs) continue;
+      double2 v = red[(0 * NR + r) * 64 + l];
+      for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
+      out[((size_t)split * nrhs + r) * ntp + tile * 64 + mt + l] = v;
+    }
   }
 }
 
@@ -277,6 +320,18 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
   }
 }
 
+// every group mirror-paired (the stored-field sum then runs the MIR form);
+// a plan mixing paired and unpaired groups is refused
+bool plan_mirrored(const NsumPlan &plan) {
+  bool any = false, all = true;
+  for (const auto &g : plan.groups) {
+    any = any || g.mt > 0;
+    all = all && g.mt > 0;
+  }
+  MFS_REQUIRE(any == all, "neighbour sum: mirror pairing must hold for every group or none");
+  return all;
+}
+
 template <int NR>
 void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *sigma, const double2 *w,
                          int nsplit, double2 *dst, hipStream_t s) {
@@ -285,9 +340,14 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
                      nrhs, NR, S, sigma, sigT);
   const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
-  hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
-                     plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
-                     plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+  if (plan_mirrored(plan))
+    hipLaunchKernelGGL((nsum_dense_kernel<NR, true>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                       plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
+                       plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+  else
+    hipLaunchKernelGGL((nsum_dense_kernel<NR, false>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                       plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
+                       plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -310,7 +370,10 @@ void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double e
 // the last round is (nearly) full: 240 surface tiles -> 16 slices, 3840
 // workgroups.
 int nsum_splits(const NsumPlan &plan, int S) {
-  const int tiles = plan.ntarget_pad / 64;
+  // tiles with work in the stored-field sum (a mirror pair's second half has none)
+  int tiles = 0;
+  for (const auto &g : plan.groups) tiles += (g.mt > 0 ? g.mt : round_up(std::max(g.nt, 1), 64)) / 64;
+  tiles = std::max(tiles, 1);
   int ns = std::max(1, 3840 / tiles);
   ns = std::min(ns, std::max(1, S / 256));
   return ns;
@@ -348,7 +411,7 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
     const NsumGroup &g = plan.groups[gi];
     koff[gi] = off;
-    off += (size_t)g.nimg * S * round_up(std::max(g.nt, 1), 64);
+    off += (size_t)g.nimg * S * (g.mt > 0 ? g.mt : round_up(std::max(g.nt, 1), 64));
   }
   const size_t bytes = off * sizeof(double2);
   if (bytes > max_bytes) return false;

@@ -414,16 +414,9 @@ __global__ __launch_bounds__(apply_threads<JB>()) void jac_apply_kernel(const Ma
   }
 }
 
-// FP64 matrix-core forms of steps 1 and 3 for 16-column blocks.  One
-// v_mfma_f64_16x16x4f64 multiplies a 16 x 4 block A (lane i + 16 k holds
-// A[i][k]) by a 4 x 16 block B (lane j + 16 k holds B[k][j]) into a 16 x 16
-// accumulator D (lane j + 16 g holds D[g + 4 v][j] in its v-th element).  A
-// complex product is four real ones on the split real and imaginary parts.
-typedef double dx4 __attribute__((ext_vector_type(4)));
-
-__device__ inline dx4 mfma_f64(double a, double b, dx4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// FP64 matrix-core forms of steps 1 and 3 for 16-column blocks (mfma_f64:
+// lane layout in common.hpp); a complex product is four real ones on the
+// split real and imaginary parts.
 
 // 1'. partial Gram matrix of one GT-row tile, one wave per workgroup.  The
 //     rows are the summation index: step s takes rows 4 s + k of the tile, and
