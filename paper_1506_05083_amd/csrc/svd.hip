@@ -15,15 +15,16 @@
 // round-robin (circle) schedule pairs the blocks, n_b - 1 rounds per sweep.
 // A task is a block pair (JC = 2 JB columns); a round is three launches over
 // all tasks of all matrices:
-//   1. jac_gram_kernel: partial H = G_IJ^H G_IJ (JC x JC) over 128-row
-//      tiles, every entry a dot product of two columns, staged through LDS;
+//   1. jac_gram_mfma_kernel (JB = 16) / jac_gram_mfma32_kernel (JB = 32):
+//      partial H = G_IJ^H G_IJ (JC x JC) over 128-row tiles on the FP64
+//      matrix cores, every entry a dot product of two columns;
 //   2. jac_inner_kernel (one workgroup per task): H summed over the tiles,
 //      one Jacobi sweep over the JC columns carried out on H in LDS (the
 //      two-sided update H <- R^H H R of each rotation R, with the exact
 //      diagonal formulas above and the annihilated entry set to zero), the
 //      product J of the rotations accumulated alongside;
-//   3. jac_apply_kernel: if any pair of the task rotated, G_IJ <- G_IJ J and
-//      V_IJ <- V_IJ J over 64-row tiles.
+//   3. jac_apply_mfma_kernel / jac_apply_mfma32_kernel: if any pair of the
+//      task rotated, G_IJ <- G_IJ J and V_IJ <- V_IJ J over row tiles.
 // The row tiles spread every round over the whole chip whatever the number
 // of tasks, and the apply streams G and V once per round.
 // Every pair of columns meets in some workgroup every sweep, pairs inside a
@@ -63,7 +64,6 @@ __global__ void jac_clear_flags(const MatDesc *__restrict__ descs, int nmat) {
   if (i < nmat) descs[i].flag[0] = 0;
 }
 
-constexpr int JR = 64;        // rows per LDS chunk of the Gram kernel
 constexpr int kJacWideMinCols = 2048;  // 32-column blocks from this width on
 
 __device__ inline void circle_pair(int np, int round, int pair, int &p, int &q) {
@@ -99,89 +99,6 @@ __device__ inline int task_col(int a, int bi, int bj, int nb, int n) {
   const int blk = a < JB ? bi : bj;
   const int c = blk * JB + (a & (JB - 1));
   return (blk < nb && c < n) ? c : -1;
-}
-
-// 1. partial Gram matrices: hpart[mat][pair][tile] = G_IJ(rows of tile)^H G_IJ(rows of tile).
-//    Lane (ti, tj) holds the entries H[oi + ti + 8k][oj + tj + 8k2], k, k2 < 4, of a
-//    32 x 32 piece: for JB = 16 the whole H with the waves splitting the rows of a
-//    chunk (summed in LDS at the end), for JB = 32 wave w's quadrant
-//    (oi, oj) = 32 (w >> 1, w & 1) over every row.
-template <int JB>
-__global__ __launch_bounds__(256) void jac_gram_kernel(const MatDesc *__restrict__ descs,
-                                                       const int *__restrict__ act, int round,
-                                                       double2 *__restrict__ hpart, int npair_max,
-                                                       int ntile_max) {
-  constexpr int JC = 2 * JB;
-  const int mat = blockIdx.z;
-  if (!act[mat]) return;
-  const MatDesc d = descs[mat];
-  const int n = d.n;
-  const int rbeg = blockIdx.x * GT;
-  if (rbeg >= n) return;
-  __shared__ int colx[JC];
-  __shared__ double2 Gs[JR][JC + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  {
-    int bi, bj, nb;
-    if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
-    if (tid < JC) colx[tid] = task_col<JB>(tid, bi, bj, nb, n);
-  }
-  __syncthreads();
-  const int ti = lane >> 3, tj = lane & 7;
-  const int oi = JB == 32 ? 32 * (wv >> 1) : 0, oj = JB == 32 ? 32 * (wv & 1) : 0;
-  double2 acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = cz(0.0, 0.0);
-  const int rend = min(n, rbeg + GT);
-  for (int r0 = rbeg; r0 < rend; r0 += JR) {
-    double2 pre[JC * JR / 256];
-#pragma unroll
-    for (int i = 0; i < JC * JR / 256; ++i) {
-      const int a = wv + 4 * i, r = r0 + lane;
-      const int c = colx[a];
-      pre[i] = ld_or0(d.g, (size_t)(c < 0 ? 0 : c) * d.ldg + r, c >= 0 && r < rend);
-    }
-#pragma unroll
-    for (int i = 0; i < JC * JR / 256; ++i) Gs[lane][wv + 4 * i] = pre[i];
-    __syncthreads();
-    for (int rr = JB == 32 ? 0 : wv; rr < JR; rr += JB == 32 ? 1 : 4) {
-      double2 x[4], y[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        x[k] = Gs[rr][oi + ti + 8 * k];
-        y[k] = Gs[rr][oj + tj + 8 * k];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) cfmac(acc[k][k2], x[k], y[k2]);
-    }
-    __syncthreads();
-  }
-  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
-  if (JB == 32) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) out[(oi + ti + 8 * k) * JC + oj + tj + 8 * k2] = acc[k][k2];
-    return;
-  }
-  // sum the four waves in LDS (Gs reused as a 32 x 33 array)
-  for (int w = 0; w < 4; ++w) {
-    if (wv == w) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-          double2 &h = Gs[ti + 8 * k][tj + 8 * k2];
-          h = (w == 0) ? acc[k][k2] : cadd(h, acc[k][k2]);
-        }
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < JC * JC; idx += 256) out[idx] = Gs[idx / JC][idx % JC];
 }
 
 // 2. one workgroup per task: H = sum of the partials, one Jacobi sweep over
@@ -328,92 +245,6 @@ __global__ __launch_bounds__(JB * JB) void jac_inner_kernel(const MatDesc *__res
   }
 }
 
-// 3. G_IJ <- G_IJ J and V_IJ <- V_IJ J on 64-row tiles (tiles [0, nt) of G,
-//    [nt, 2 nt) of V); thread -> rows tx + 16a, columns 4 cq + b
-template <int JB>
-constexpr int apply_threads() { return JB == 16 ? 128 : 256; }
-
-template <int JB>
-__global__ __launch_bounds__(apply_threads<JB>()) void jac_apply_kernel(const MatDesc *__restrict__ descs,
-                                                                        const int *__restrict__ act, int round,
-                                                                        const double2 *__restrict__ jbuf,
-                                                                        const int *__restrict__ rot,
-                                                                        int npair_max) {
-  constexpr int JC = 2 * JB, NT = apply_threads<JB>();
-  const int mat = blockIdx.z;
-  if (!act[mat]) return;
-  const MatDesc d = descs[mat];
-  const int n = d.n;
-  const int pair = blockIdx.y;
-  const int nt = (n + AT - 1) / AT;
-  if ((int)blockIdx.x >= 2 * nt) return;
-  __shared__ int colx[JC];
-  __shared__ double2 Gs[AT][JC + 1];
-  __shared__ double2 Js[JC][JC + 1];
-  const int tid = threadIdx.x;
-  {
-    int bi, bj, nb;
-    if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
-    if (!rot[(size_t)mat * npair_max + pair]) return;
-    if (tid < JC) colx[tid] = task_col<JB>(tid, bi, bj, nb, n);
-  }
-  double2 *M = (int)blockIdx.x < nt ? d.g : d.v;
-  const int r0 = ((int)blockIdx.x % nt) * AT;
-  const double2 *ji = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
-  __syncthreads();
-  {
-    double2 pre[AT * JC / NT], jj[JC * JC / NT];
-#pragma unroll
-    for (int u = 0; u < AT * JC / NT; ++u) {
-      const int idx = tid + NT * u, a = idx / AT, rr = idx % AT;
-      const int c = colx[a], r = r0 + rr;
-      pre[u] = ld_or0(M, (size_t)(c < 0 ? 0 : c) * d.ldg + r, c >= 0 && r < n);
-    }
-#pragma unroll
-    for (int u = 0; u < JC * JC / NT; ++u) jj[u] = ji[tid + NT * u];
-#pragma unroll
-    for (int u = 0; u < AT * JC / NT; ++u) {
-      const int idx = tid + NT * u;
-      Gs[idx % AT][idx / AT] = pre[u];
-    }
-#pragma unroll
-    for (int u = 0; u < JC * JC / NT; ++u) {
-      const int idx = tid + NT * u;
-      Js[idx / JC][idx % JC] = jj[u];
-    }
-  }
-  __syncthreads();
-  const int tx = tid & 15, cq = tid >> 4;
-  double2 o[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) o[x][y] = cz(0.0, 0.0);
-#pragma unroll 4
-  for (int a = 0; a < JC; ++a) {
-    double2 x[4], jv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[k] = Gs[tx + 16 * k][a];
-      jv[k] = Js[a][4 * cq + k];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) cfma(o[i][k], x[i], jv[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int c = colx[4 * cq + k];
-    if (c < 0) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = r0 + tx + 16 * i;
-      if (r < n) M[(size_t)c * d.ldg + r] = o[i][k];
-    }
-  }
-}
-
 // FP64 matrix-core forms of steps 1 and 3 for 16-column blocks (mfma_f64:
 // lane layout in common.hpp); a complex product is four real ones on the
 // split real and imaginary parts.
@@ -555,6 +386,157 @@ __global__ __launch_bounds__(64) void jac_apply_mfma_kernel(const MatDesc *__res
     }
 }
 
+// 1''. partial Gram matrix for 32-column blocks (64 task columns, four
+//      16-column fragments per step), two waves per GT-row tile: the ten
+//      block pairs (I <= J) of the Hermitian 64 x 64 matrix, five per wave
+//      (wave 0: (0,0) (0,1) (0,2) (0,3) (1,1); wave 1: (1,2) (1,3) (2,2)
+//      (2,3) (3,3)); the blocks below the diagonal are written as conjugate
+//      transposes.
+__device__ inline void gram32_pair(int w, int p, int &I, int &J) {
+  // pairs (I <= J) in row order, the first five to wave 0
+  const int q = 5 * w + p;
+  const int rows[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3}, cols[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+  I = rows[q];
+  J = cols[q];
+}
+
+__global__ __launch_bounds__(128) void jac_gram_mfma32_kernel(const MatDesc *__restrict__ descs,
+                                                              const int *__restrict__ act, int round,
+                                                              double2 *__restrict__ hpart, int npair_max,
+                                                              int ntile_max) {
+  constexpr int JB = 32, JC = 64, NF = 4, NP = 5;
+  const int mat = blockIdx.z;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int n = d.n;
+  const int rbeg = blockIdx.x * GT;
+  if (rbeg >= n) return;
+  int bi, bj, nb;
+  if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
+  const int l = threadIdx.x & 63, c = l & 15, k = l >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int cf[NF];
+  const double2 *gf[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    cf[f] = task_col<JB>(16 * f + c, bi, bj, nb, n);
+    gf[f] = d.g + (size_t)max(cf[f], 0) * d.ldg;
+  }
+  const int rend = min(n, rbeg + GT);
+  dx4 re[NP], im[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    re[p] = dx4{0, 0, 0, 0};
+    im[p] = re[p];
+  }
+  for (int rb = rbeg; rb < rend; rb += 4) {   // uniform trip count
+    const int r = rb + k;
+    double2 x[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) x[f] = ld_or0(gf[f], r, r < rend && cf[f] >= 0 && (w == 1 ? f > 0 : true));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      int I, J;
+      gram32_pair(w, p, I, J);
+      // I, J are wave-uniform: the selects below stay in registers
+      double2 xi = x[0], xj = x[0];
+#pragma unroll
+      for (int f = 1; f < NF; ++f) {
+        xi = csel(I == f, x[f], xi);
+        xj = csel(J == f, x[f], xj);
+      }
+      re[p] = mfma_f64(xi.x, xj.x, re[p]);
+      re[p] = mfma_f64(xi.y, xj.y, re[p]);
+      im[p] = mfma_f64(xi.x, xj.y, im[p]);
+      im[p] = mfma_f64(-xi.y, xj.x, im[p]);
+    }
+  }
+  double2 *out = hpart + (((size_t)mat * npair_max + blockIdx.y) * ntile_max + blockIdx.x) * JC * JC;
+  const int j = l & 15, g = l >> 4;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    int I, J;
+    gram32_pair(w, p, I, J);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = g + 4 * v;
+      out[(16 * I + i) * JC + 16 * J + j] = cz(re[p][v], im[p][v]);
+      if (I != J) out[(16 * J + j) * JC + 16 * I + i] = cz(re[p][v], -im[p][v]);
+    }
+  }
+}
+
+// 3''. G_IJ <- G_IJ J and V_IJ <- V_IJ J for 32-column blocks: one wave per
+//      16-row tile (tiles [0, nt) of G, [nt, 2 nt) of V) against all 64 task
+//      columns, step s summing over task columns
+//      4 s .. 4 s + 3 with the fragments of J read as they are needed.  The
+//      wave reads its rows of every column before it writes any, and tiles
+//      share no rows, so the update is in place.
+__global__ __launch_bounds__(64) void jac_apply_mfma32_kernel(const MatDesc *__restrict__ descs,
+                                                              const int *__restrict__ act, int round,
+                                                              const double2 *__restrict__ jbuf,
+                                                              const int *__restrict__ rot, int npair_max) {
+  constexpr int JB = 32, JC = 64, KS = JC / 4, NF = 4, RB = 1, TR = 16 * RB;
+  const int mat = blockIdx.z;
+  if (!act[mat]) return;
+  const MatDesc d = descs[mat];
+  const int n = d.n;
+  const int pair = blockIdx.y;
+  const int nt = (n + TR - 1) / TR;
+  if ((int)blockIdx.x >= 2 * nt) return;
+  int bi, bj, nb;
+  if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
+  if (!rot[(size_t)mat * npair_max + pair]) return;
+  const int l = threadIdx.x;
+  const int r0 = ((int)blockIdx.x % nt) * TR;
+  double2 *M = (int)blockIdx.x < nt ? d.g : d.v;
+  const double2 *ji = jbuf + ((size_t)mat * npair_max + pair) * JC * JC;
+  const int i = l & 15, k = l >> 4;
+  dx4 re[RB][NF], im[RB][NF];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int J = 0; J < NF; ++J) {
+      re[rb][J] = dx4{0, 0, 0, 0};
+      im[rb][J] = re[rb][J];
+    }
+#pragma unroll 2
+  for (int s = 0; s < KS; ++s) {
+    const int col = task_col<JB>(4 * s + k, bi, bj, nb, n);
+    const double2 *mc = M + (size_t)max(col, 0) * d.ldg;
+    double2 a[RB], b[NF];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int r = r0 + 16 * rb + i;
+      a[rb] = ld_or0(mc, r, r < n && col >= 0);
+    }
+#pragma unroll
+    for (int J = 0; J < NF; ++J) b[J] = ji[(4 * s + k) * JC + 16 * J + i];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int J = 0; J < NF; ++J) {
+        re[rb][J] = mfma_f64(a[rb].x, b[J].x, re[rb][J]);
+        re[rb][J] = mfma_f64(-a[rb].y, b[J].y, re[rb][J]);
+        im[rb][J] = mfma_f64(a[rb].x, b[J].y, im[rb][J]);
+        im[rb][J] = mfma_f64(a[rb].y, b[J].x, im[rb][J]);
+      }
+  }
+  const int j = l & 15, g = l >> 4;
+#pragma unroll
+  for (int J = 0; J < NF; ++J) {
+    const int cJ = task_col<JB>(16 * J + j, bi, bj, nb, n);
+    if (cJ < 0) continue;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * rb + g + 4 * v;
+        if (row < n) M[(size_t)cJ * d.ldg + row] = cz(re[rb][J][v], im[rb][J][v]);
+      }
+  }
+}
+
 // Column norms, descending order (rank by counting, ties by index), kept rank.
 __global__ __launch_bounds__(256) void jac_sort_kernel(const MatDesc *__restrict__ descs,
                                                        double rel_cutoff) {
@@ -659,7 +641,7 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
         hipLaunchKernelGGL(jac_gram_mfma_kernel, dim3(ntile_max, npair_max, nmat), dim3(64), 0, s, descs,
                            act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
       else
-        hipLaunchKernelGGL(jac_gram_kernel<JB>, dim3(ntile_max, npair_max, nmat), dim3(256), 0, s, descs,
+        hipLaunchKernelGGL(jac_gram_mfma32_kernel, dim3(ntile_max, npair_max, nmat), dim3(128), 0, s, descs,
                            act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
       hipLaunchKernelGGL(jac_inner_kernel<JB>, dim3(npair_max, nmat), dim3(JB * JB), 0, s, descs, act.as<int>(), rnd,
                          tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max);
@@ -667,8 +649,8 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
         hipLaunchKernelGGL(jac_apply_mfma_kernel, dim3(2 * atile_max, npair_max, nmat), dim3(64), 0, s, descs,
                            act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
       else
-        hipLaunchKernelGGL(jac_apply_kernel<JB>, dim3(2 * atile_max, npair_max, nmat), dim3(apply_threads<JB>()), 0, s, descs,
-                         act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
+        hipLaunchKernelGGL(jac_apply_mfma32_kernel, dim3(2 * cdiv(nmax, 16), npair_max, nmat), dim3(64), 0, s,
+                           descs, act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
     }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipEventRecord(e1, s));
