@@ -132,8 +132,9 @@ void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
   // onto (l + P/2, m), source (l, j) onto (l + P/2, j) (both at angles
   // 2 pi l / P, indices l M + m and l N + j) and the shift a e_x + b e_y onto
   // its negative; kernel values and normal derivatives are invariant under
-  // it, so the images (a, b) and (-a, -b) share their stored values.
-  if (b.P % 2 == 0 && ((size_t)(b.P / 2) * b.M) % 64 == 0) {
+  // it, so the images (a, b) and (-a, -b) share their kernel values (the
+  // stored field uses the pairing when (P/2) M fills whole 64-target tiles).
+  if (b.P % 2 == 0) {
     g.mt = (b.P / 2) * b.M;
     g.ms = (b.P / 2) * b.N;
     for (int im = 0; im < g.nimg; ++im)

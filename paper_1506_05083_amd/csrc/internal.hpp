@@ -120,10 +120,12 @@ struct NsumGroup {
   int nimg;
   int ia[9], ib[9];   // image shifts (a, b)
   // Mirror pairing (0: none).  When the half-turn about the body's axis maps
-  // target t to t + mt (t < mt, mt a multiple of 64, nt = 2 mt) and source s
-  // to s + ms (mod S), image (a, b) onto image mir[.] = (-a, -b): the stored
-  // near field keeps the first mt targets only, and their values serve the
-  // other half through K_(-a,-b)[t + mt][s] = K_(a,b)[t][s + ms].
+  // target t to t + mt (t < mt, nt = 2 mt) and source s to s + ms (mod S),
+  // image (a, b) onto image mir[.] = (-a, -b), the values of the first mt
+  // targets serve the other half through K_(-a,-b)[t + mt][s] =
+  // K_(a,b)[t][s + ms]: the on-the-fly sum evaluates half the kernel values,
+  // and when mt is a multiple of 64 the stored near field keeps the first mt
+  // targets only.
   int mt, ms;
   int mir[9];
 };

@@ -24,6 +24,10 @@ constexpr int SC = 128;     // sources per LDS chunk (32 per wave)
 constexpr int MAXR = 16;    // right-hand sides per launch
 constexpr int DU = 16;      // stored values in flight per wave in the dense sum
 
+// the mirror offset of a group if the stored field can use it (whole tiles
+// on both sides of the pairing), else 0
+__host__ __device__ inline int dense_mt(const NsumGroup &g) { return (g.mt > 0 && g.mt % 64 == 0) ? g.mt : 0; }
+
 // G(x - y) = e^{ikR} / (4 pi R) for (dx, dy, dz) = x - y, or its derivative
 // along the target direction (tx, ty, tz) when deriv is set
 __device__ inline double2 near_kernel(double ddx, double ddy, double ddz, double tx, double ty, double tz,
@@ -43,7 +47,14 @@ __device__ inline double2 near_kernel(double ddx, double ddy, double ddz, double
   return cz(cs * tt, sn * tt);
 }
 
-template <int NR>
+// With MIR (every group mirror-paired, NsumGroup::mt) a workgroup takes the
+// targets t < mt of its tile (the first half of its group) and forms the sums
+// of t and of its mirror t + mt from the same kernel values, against the
+// strengths of the sources s and s + ms (mod S) and the weights of the image
+// and of its mirror: half the kernel evaluations.  A lane past mt writes
+// nothing (its sum arrives as a mirror) unless it is a padding target, which
+// gets zero; tiles wholly past mt only write their padding zeros.
+template <int NR, bool MIR>
 __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tgt, int ntp,
                                                    const NsumGroup *__restrict__ groups,
                                                    const int *__restrict__ tile_group, int nrhs,
@@ -54,28 +65,43 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
                                                    double2 *__restrict__ out) {
   extern __shared__ double shm[];
   double *sx = shm, *sy = shm + SC, *szs = shm + 2 * SC;
-  double2 *ssig = reinterpret_cast<double2 *>(shm + 3 * SC);   // [NR][SC]
+  double2 *ssig = reinterpret_cast<double2 *>(shm + 3 * SC);   // [NR][SC], then [NR][SC] mirror
+  double2 *ssig2 = ssig + NR * SC;
   const int tile = blockIdx.x;
   const int split = blockIdx.y;
   const int gi = tile_group[tile];
   const NsumGroup g = groups[gi];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = tile * 64 + lane;
+  const int tl = tile * 64 - g.t0;   // first target of the tile within its group
+  if (MIR && tl >= g.mt) {
+    for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+      const int r = idx / 64, l = idx % 64;
+      if (r < nrhs && tl + l >= g.nt) out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = cz(0.0, 0.0);
+    }
+    return;
+  }
   const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
   const double dxt = tgt[3 * ntp + t], dyt = tgt[4 * ntp + t], dzt = tgt[5 * ntp + t];
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per;
   const int s_end = min(S, s_begin + per);
 
-  double2 tot[NR];
+  double2 tot[NR], tot2[MIR ? NR : 1];
 #pragma unroll
   for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
+  if (MIR)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tot2[r] = cz(0.0, 0.0);
 
   for (int im = 0; im < g.nimg; ++im) {
     const double xs = xt - groups[gi].ia[im] * ex, ys = yt - groups[gi].ib[im] * ey;
-    double2 acc[NR];
+    double2 acc[NR], acc2[MIR ? NR : 1];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
+    if (MIR)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc2[r] = cz(0.0, 0.0);
     for (int c0 = s_begin; c0 < s_end; c0 += SC) {
       const int nc = min(SC, s_end - c0);
       __syncthreads();
@@ -88,7 +114,12 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
       }
       for (int idx = threadIdx.x; idx < NR * SC; idx += 256) {
         const int r = idx / SC, ss = idx % SC;
-        ssig[idx] = (r < nrhs && ss < nc) ? sigma[(size_t)r * S + c0 + ss] : cz(0.0, 0.0);
+        const bool ok = r < nrhs && ss < nc;
+        ssig[idx] = ok ? sigma[(size_t)r * S + c0 + ss] : cz(0.0, 0.0);
+        if (MIR) {
+          const int sm = c0 + ss + g.ms >= S ? c0 + ss + g.ms - S : c0 + ss + g.ms;
+          ssig2[idx] = ok ? sigma[(size_t)r * S + sm] : cz(0.0, 0.0);
+        }
       }
       __syncthreads();
       const int sbeg = wv * (SC / 4);
@@ -96,24 +127,38 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
         const double2 K = near_kernel(xs - sx[ss], ys - sy[ss], zt - szs[ss], dxt, dyt, dzt, k, g.deriv);
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], K, ssig[r * SC + ss]);
+        if (MIR)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc2[r], K, ssig2[r * SC + ss]);
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
       if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
-  }
-  // reduce the four waves
-  __syncthreads();
-  double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
+    if (MIR) {
+      const int jm = groups[gi].mir[im];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot[r];
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
-    const int r = idx / 64, l = idx % 64;
-    if (r >= nrhs) continue;
-    double2 v = red[(0 * NR + r) * 64 + l];
-    for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
-    out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = v;
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs) cfma(tot2[r], wts[((size_t)gi * 9 + jm) * nrhs + r], acc2[r]);
+    }
+  }
+  // reduce the four waves (the target sums, then for MIR the mirror sums)
+  double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
+  for (int half = 0; half < (MIR ? 2 : 1); ++half) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = (MIR && half) ? tot2[r] : tot[r];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+      const int r = idx / 64, l = idx % 64;
+      if (r >= nrhs) continue;
+      double2 v = red[(0 * NR + r) * 64 + l];
+      for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
+      double2 *row = out + ((size_t)split * nrhs + r) * ntp + tile * 64;
+      if (!MIR) row[l] = v;
+      else if (tl + l < g.mt) row[l + (half ? g.mt : 0)] = v;
+      else if (!half && tl + l >= g.nt) row[l] = cz(0.0, 0.0);
+    }
   }
 }
 
@@ -135,7 +180,7 @@ __global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
   const NsumGroup &g = groups[gi];
-  if (g.mt > 0 && tile * 64 - g.t0 >= g.mt) return;   // second half of a mirror pair: not stored
+  if (dense_mt(g) > 0 && tile * 64 - g.t0 >= g.mt) return;   // second half of a mirror pair: not stored
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = tile * 64 + lane;
   const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
@@ -320,13 +365,16 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
   }
 }
 
-// every group mirror-paired (the stored-field sum then runs the MIR form);
-// a plan mixing paired and unpaired groups is refused
-bool plan_mirrored(const NsumPlan &plan) {
+// every group mirror-paired (the on-the-fly sum then runs its MIR form) /
+// every group mirror-paired on whole tiles (the stored field keeps half the
+// tiles and its sum runs the MIR form); a plan mixing paired and unpaired
+// groups is refused
+bool plan_mirrored(const NsumPlan &plan, bool dense) {
   bool any = false, all = true;
   for (const auto &g : plan.groups) {
-    any = any || g.mt > 0;
-    all = all && g.mt > 0;
+    const int mt = dense ? dense_mt(g) : g.mt;
+    any = any || mt > 0;
+    all = all && mt > 0;
   }
   MFS_REQUIRE(any == all, "neighbour sum: mirror pairing must hold for every group or none");
   return all;
@@ -340,7 +388,7 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
                      nrhs, NR, S, sigma, sigT);
   const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
-  if (plan_mirrored(plan))
+  if (plan_mirrored(plan, true))
     hipLaunchKernelGGL((nsum_dense_kernel<NR, true>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
                        plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
                        plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
@@ -355,11 +403,17 @@ template <int NR>
 void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                    const double *src, int S, const double2 *sigma, const double2 *w,
                    int nsplit, double2 *dst, hipStream_t s) {
-  const size_t sh = std::max((size_t)(3 * SC) * sizeof(double) + (size_t)NR * SC * sizeof(double2),
+  const bool mir = plan_mirrored(plan, false);
+  const size_t sh = std::max((size_t)(3 * SC) * sizeof(double) + (size_t)(mir ? 2 : 1) * NR * SC * sizeof(double2),
                              (size_t)4 * NR * 64 * sizeof(double2));
-  hipLaunchKernelGGL(nsum_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
-                     plan.tgt.as<double>(), plan.ntarget_pad, plan.grp.as<NsumGroup>(),
-                     plan.tile_group.as<int>(), nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst);
+  if (mir)
+    hipLaunchKernelGGL((nsum_kernel<NR, true>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                       plan.tgt.as<double>(), plan.ntarget_pad, plan.grp.as<NsumGroup>(),
+                       plan.tile_group.as<int>(), nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst);
+  else
+    hipLaunchKernelGGL((nsum_kernel<NR, false>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+                       plan.tgt.as<double>(), plan.ntarget_pad, plan.grp.as<NsumGroup>(),
+                       plan.tile_group.as<int>(), nrhs, k, ex, ey, src, S, sigma, w, nsplit, dst);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -372,7 +426,7 @@ void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double e
 int nsum_splits(const NsumPlan &plan, int S) {
   // tiles with work in the stored-field sum (a mirror pair's second half has none)
   int tiles = 0;
-  for (const auto &g : plan.groups) tiles += (g.mt > 0 ? g.mt : round_up(std::max(g.nt, 1), 64)) / 64;
+  for (const auto &g : plan.groups) tiles += g.mt > 0 ? cdiv(g.mt, 64) : round_up(std::max(g.nt, 1), 64) / 64;
   tiles = std::max(tiles, 1);
   int ns = std::max(1, 3840 / tiles);
   ns = std::min(ns, std::max(1, S / 256));
@@ -411,7 +465,7 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
     const NsumGroup &g = plan.groups[gi];
     koff[gi] = off;
-    off += (size_t)g.nimg * S * (g.mt > 0 ? g.mt : round_up(std::max(g.nt, 1), 64));
+    off += (size_t)g.nimg * S * (dense_mt(g) > 0 ? g.mt : round_up(std::max(g.nt, 1), 64));
   }
   const size_t bytes = off * sizeof(double2);
   if (bytes > max_bytes) return false;
