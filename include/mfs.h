@@ -194,7 +194,12 @@ mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *st
  * rel_cutoff * s_max dropped; keeps U_n = Q_n W_n (M x r) and V_n S_n^+
  * (N x r) so that A'_n^+ x = V_n S_n^+ (U_n^* x) is applied without forming
  * the pseudoinverse.  Blocking until done.  ranks (host, optional) receives
- * the kept rank of each distinct block, [sum over bodies of P/2+1]. */
+ * the kept rank of each distinct block, [sum over bodies of P/2+1].
+ * The blocked Jacobi (here and for the periodizer's Q^+ in
+ * mfs_solve_incident) uses 32-column blocks once a batch's widest factor
+ * has 2048 columns, 16-column blocks below; the environment variable
+ * MFS_JACOBI_WIDE_MIN_COLS, read at every factorisation, moves that width
+ * (a test of the wide path on small matrices sets it to 0). */
 mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks);
 
 /* Stage times of the operator, milliseconds, measured with HIP events on the

@@ -695,7 +695,9 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
   // round) at the price of an inner problem of twice as many rounds per
   // task; that pays only once the passes over G and V dominate (measured:
   // slower at 600 and 800 columns, faster at several thousand)
-  if (nmax >= kJacWideMinCols) return jac_run_t<32>(descs, h, init_mode, s);
+  int wide = kJacWideMinCols;
+  if (const char *e = getenv("MFS_JACOBI_WIDE_MIN_COLS")) wide = atoi(e);
+  if (nmax >= wide) return jac_run_t<32>(descs, h, init_mode, s);
   return jac_run_t<16>(descs, h, init_mode, s);
 }
 

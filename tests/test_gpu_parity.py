@@ -276,6 +276,42 @@ def test_periodic_solve_parity_small(mfs, ctx, small_oracle, near):
         assert r.eps_flux < 1e-5
 
 
+def test_wide_jacobi_blocks(mfs, ctx, small_oracle, monkeypatch):
+    """The 32-column Jacobi blocks (matrix-core Gram of the ten Hermitian
+    block pairs, 64 x 64 inner sweep, matrix-core apply), which the library
+    takes for factors of 2048 columns and more, forced on the small bodies:
+    singular values against LAPACK on the GPU's own blocks, the same ranks as
+    with 16-column blocks, and the periodic solve (whose Q^+ then uses them
+    as well, on a factor of several hundred columns) against the oracle."""
+    pr, g, out = small_oracle
+    b = pr.body
+    op16 = make_op(mfs, ctx, b)
+    r16 = list(op16.factor_modes(1e-10))
+    monkeypatch.setenv("MFS_JACOBI_WIDE_MIN_COLS", "0")
+    op = make_op(mfs, ctx, b)
+    blocks = op.blocks().cpu().numpy().transpose(0, 2, 1)   # [P/2+1][M][N]
+    r32 = list(op.factor_modes(1e-10))
+    sv = op.singular_values(0)
+    e = 0.0
+    for n in range(blocks.shape[0]):
+        s_own = np.linalg.svd(blocks[n], compute_uv=False)
+        e = max(e, float(np.max(np.abs(sv[n][: s_own.size] - s_own)) / s_own[0]))
+    log(f"[wide jacobi] singular values vs LAPACK {e:.2e} (of s_max); ranks equal {r32 == r16}")
+    assert e < 1e-13
+    assert r32 == r16
+    L = _lat(mfs, pr.lattice)
+    res = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=1e-12, maxit=100,
+                             targets=pr.targets, q_field=pr.q_field)
+    for i, r in enumerate(res):
+        o = out[i]
+        ea = np.max(np.abs(r.a - o["res"]["a"])) / np.max(np.abs(o["res"]["a"]))
+        eb = np.max(np.abs(r.b - o["res"]["b"])) / np.max(np.abs(o["res"]["b"]))
+        eu = np.linalg.norm(r.field - o["u"]) / np.linalg.norm(o["u"])
+        log(f"[wide jacobi] wave {i} iters gpu {r.iters} oracle {o['res']['iters']} a {ea:.2e} b {eb:.2e} "
+            f"u {eu:.2e}")
+        assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+
+
 def test_periodic_k10_full_size_vs_golden(mfs, ctx):
     """Full size of the benchmark workload, in the benchmark's launch
     configuration (all 8 incidences in one batched solve), against the
