@@ -336,6 +336,103 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
   }
 }
 
+// The mirror form for eight right-hand sides on the FP64 matrix cores: per
+// image, out[t][j] += sum_s K[t][s] B[s][j] as 16 x 16 x 4 products with the
+// 64 targets of the tile as four row blocks (A = the stored values, 16
+// targets by 4 sources, read as before), and 16 columns B[s][j] = w_j
+// sigma_j(s) for the eight sums (weights of the image) and
+// w'_(j-8) sigma_(j-8)(s + ms) for the eight mirror sums (weights of the
+// mirror image), each lane forming its one element of B per step.  The
+// weights sit in B, so the accumulators are the totals.
+__global__ __launch_bounds__(256) void nsum_dense_mirror8_kernel(int ntp, const NsumGroup *__restrict__ groups,
+                                                                 const int *__restrict__ tile_group,
+                                                                 const size_t *__restrict__ koff,
+                                                                 const double2 *__restrict__ dense, int nrhs,
+                                                                 int S, const double2 *__restrict__ sigT,
+                                                                 const double2 *__restrict__ wts, int nsplit,
+                                                                 double2 *__restrict__ out) {
+  constexpr int NR = 8, RB = 4, KU = 2;   // KU steps of 4 sources per batch of loads
+  extern __shared__ double shm[];
+  const int tile = blockIdx.x, split = blockIdx.y;
+  const int gi = tile_group[tile];
+  const int l = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
+  const int mt = groups[gi].mt, ms = groups[gi].ms;
+  if (tile * 64 - t0 >= mt) return;   // served by the mirror tile
+  const int per = (S + nsplit - 1) / nsplit;
+  const int s_begin = split * per, s_end = min(S, s_begin + per);
+  const int qw = (s_end - s_begin + 3) / 4;
+  const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
+  const double2 *base = dense + koff[gi] + (size_t)((tile * 64 - t0) >> 6) * nimg * S * 64;
+  const int i = l & 15, k = l >> 4;          // A: target 16 rb + i, source 4 step + k
+  const int j = l & 15;                      // B: column j, source 4 step + k
+  const int jr = j < NR ? j : j - NR;        // right-hand side of column j
+  dx4 tr[RB], ti[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    tr[rb] = dx4{0, 0, 0, 0};
+    ti[rb] = tr[rb];
+  }
+  for (int im = 0; im < nimg; ++im) {
+    const int wim = j < NR ? im : groups[gi].mir[im];
+    const double2 wj = jr < nrhs ? wts[((size_t)gi * 9 + wim) * nrhs + jr] : cz(0.0, 0.0);
+    const double2 *kim = base + (size_t)im * S * 64;
+    for (int c0 = w_begin; c0 < w_end; c0 += 4 * KU) {   // wave-uniform trip count
+      double2 a[KU][RB], b[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int sidx = c0 + 4 * u + k;
+        const bool ok = sidx < w_end;
+        const int sc = ok ? sidx : w_begin;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const double2 *pk = kim + (size_t)sc * 64 + 16 * rb + i;
+          double2 v;
+          v.x = __builtin_nontemporal_load(&pk->x);
+          v.y = __builtin_nontemporal_load(&pk->y);
+          const long long m = ok ? -1LL : 0LL;
+          a[u][rb] = cz(__longlong_as_double(__double_as_longlong(v.x) & m),
+                        __longlong_as_double(__double_as_longlong(v.y) & m));
+        }
+        const int sm = j < NR ? sc : (sc + ms >= S ? sc + ms - S : sc + ms);
+        b[u] = cmul(wj, sigT[(size_t)sm * NR + jr]);   // zero columns past nrhs through wj
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          tr[rb] = mfma_f64(a[u][rb].x, b[u].x, tr[rb]);
+          tr[rb] = mfma_f64(-a[u][rb].y, b[u].y, tr[rb]);
+          ti[rb] = mfma_f64(a[u][rb].x, b[u].y, ti[rb]);
+          ti[rb] = mfma_f64(a[u][rb].y, b[u].x, ti[rb]);
+        }
+    }
+  }
+  // element v of lane j + 16 g: target 16 rb + g + 4 v, column j; the four
+  // waves' sums meet in LDS [4][8 columns][64 targets], the eight sums first,
+  // then the eight mirror sums
+  double2 *red = reinterpret_cast<double2 *>(shm);
+  const int g = l >> 4;
+  for (int half = 0; half < 2; ++half) {
+    if (half) __syncthreads();
+    if ((j >= NR) == (half == 1)) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wv * NR + jr) * 64 + 16 * rb + g + 4 * v] = cz(tr[rb][v], ti[rb][v]);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
+      const int r = idx / 64, tt = idx % 64;
+      if (r >= nrhs) continue;
+      double2 v = red[(0 * NR + r) * 64 + tt];
+      for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + tt]);
+      out[((size_t)split * nrhs + r) * ntp + tile * 64 + (half ? mt : 0) + tt] = v;
+    }
+  }
+}
+
 __global__ void nsum_reduce(int nsplit, int nrhs, int ntp, const double2 *__restrict__ part,
                             double2 *__restrict__ out) {
   const long n = (long)nrhs * ntp;
@@ -388,7 +485,12 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
                      nrhs, NR, S, sigma, sigT);
   const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
-  if (plan_mirrored(plan, true))
+  if (plan_mirrored(plan, true) && NR == 8)
+    hipLaunchKernelGGL(nsum_dense_mirror8_kernel, dim3(plan.ntarget_pad / 64, nsplit), dim3(256),
+                       (size_t)4 * 8 * 64 * sizeof(double2), s, plan.ntarget_pad, plan.grp.as<NsumGroup>(),
+                       plan.tile_group.as<int>(), plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT,
+                       w, nsplit, dst);
+  else if (plan_mirrored(plan, true))
     hipLaunchKernelGGL((nsum_dense_kernel<NR, true>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
                        plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
                        plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
