@@ -224,15 +224,11 @@ __global__ void sig_transpose_kernel(int nrhs, int NRp, int S, const double2 *__
 
 // Stored near field: every wave of a workgroup streams its own contiguous
 // quarter of the split's sources for the workgroup's 64 targets (one lane
-// per target, 16 B per lane and source, coalesced), DUV non-temporal loads
+// per target, 16 B per lane and source, coalesced), eight non-temporal loads
 // in flight, and takes the NR strengths of each source from sigT through a
 // wave-uniform address (scalar loads: no LDS staging, no barrier in the
-// loop).  The four waves' partial sums meet in LDS at the end.  With MIR
-// (every group mirror-paired) the workgroup of a first-half tile also forms
-// the sums of its mirror targets t + mt from the same stored values, against
-// the strengths of the mirror sources s + ms and the weights of the mirror
-// images; second-half workgroups have nothing to do.
-template <int NR, bool MIR>
+// loop).  The four waves' partial sums meet in LDS at the end.
+template <int NR>
 __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                          const int *__restrict__ tile_group,
                                                          const size_t *__restrict__ koff,
@@ -240,9 +236,6 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
                                                          const double2 *__restrict__ sigT,
                                                          const double2 *__restrict__ wts, int nsplit,
                                                          double2 *__restrict__ out) {
-  // loads in flight per wave: the mirror form's second set of sums leaves
-  // registers for 8
-  constexpr int DUV = MIR ? 8 : DU;
   extern __shared__ double shm[];
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
@@ -250,31 +243,23 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = tile * 64 + lane;
   const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
-  const int mt = MIR ? groups[gi].mt : 0, ms = MIR ? groups[gi].ms : 0;
-  if (MIR && tile * 64 - t0 >= mt) return;   // served by the mirror tile
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per, s_end = min(S, s_begin + per);
   const int qw = (s_end - s_begin + 3) / 4;
   const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
   const double2 *base = dense + koff[gi] + (size_t)((t - t0) >> 6) * nimg * S * 64 + lane;
-  double2 tot[NR], tot2[MIR ? NR : 1];
+  double2 tot[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) tot[r] = cz(0.0, 0.0);
-  if (MIR)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) tot2[r] = cz(0.0, 0.0);
   for (int im = 0; im < nimg; ++im) {
-    double2 acc[NR], acc2[MIR ? NR : 1];
+    double2 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = cz(0.0, 0.0);
-    if (MIR)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc2[r] = cz(0.0, 0.0);
     const double2 *kim = base + (size_t)im * S * 64;
-    for (int c0 = w_begin; c0 < w_end; c0 += DUV) {
-      double2 kv[DUV];
+    for (int c0 = w_begin; c0 < w_end; c0 += DU) {
+      double2 kv[DU];
 #pragma unroll
-      for (int e = 0; e < DUV; ++e) {
+      for (int e = 0; e < DU; ++e) {
         // streamed once per launch: non-temporal loads keep them out of the caches
         const bool ok = c0 + e < w_end;
         const double2 *pk = kim + (size_t)(ok ? c0 + e : c0) * 64;
@@ -286,29 +271,16 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
                    __longlong_as_double(__double_as_longlong(v.y) & m));
       }
 #pragma unroll
-      for (int e = 0; e < DUV; ++e) {
+      for (int e = 0; e < DU; ++e) {
         // a source past the wave's range (kv = 0) reads the last valid row
-        const int sidx = min(c0 + e, w_end - 1);
-        const double2 *sv = sigT + (size_t)sidx * NR;
+        const double2 *sv = sigT + (size_t)min(c0 + e, w_end - 1) * NR;
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], kv[e], sv[r]);
-        if (MIR) {
-          const int sm = sidx + ms >= S ? sidx + ms - S : sidx + ms;
-          const double2 *sv2 = sigT + (size_t)sm * NR;
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc2[r], kv[e], sv2[r]);
-        }
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
       if (r < nrhs) cfma(tot[r], wts[((size_t)gi * 9 + im) * nrhs + r], acc[r]);
-    if (MIR) {
-      const int jm = groups[gi].mir[im];
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrhs) cfma(tot2[r], wts[((size_t)gi * 9 + jm) * nrhs + r], acc2[r]);
-    }
   }
   double2 *red = reinterpret_cast<double2 *>(shm);    // [4][NR][64]
 #pragma unroll
@@ -321,37 +293,26 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
     for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
     out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = v;
   }
-  if (MIR) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) red[(wv * NR + r) * 64 + lane] = tot2[r];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
-      const int r = idx / 64, l = idx % 64;
-      if (r >= nrhs) continue;
-      double2 v = red[(0 * NR + r) * 64 + l];
-      for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
-      out[((size_t)split * nrhs + r) * ntp + tile * 64 + mt + l] = v;
-    }
-  }
 }
 
-// The mirror form for eight right-hand sides on the FP64 matrix cores: per
-// image, out[t][j] += sum_s K[t][s] B[s][j] as 16 x 16 x 4 products with the
-// 64 targets of the tile as four row blocks (A = the stored values, 16
-// targets by 4 sources, read as before), and 16 columns B[s][j] = w_j
-// sigma_j(s) for the eight sums (weights of the image) and
-// w'_(j-8) sigma_(j-8)(s + ms) for the eight mirror sums (weights of the
-// mirror image), each lane forming its one element of B per step.  The
-// weights sit in B, so the accumulators are the totals.
-__global__ __launch_bounds__(256) void nsum_dense_mirror8_kernel(int ntp, const NsumGroup *__restrict__ groups,
-                                                                 const int *__restrict__ tile_group,
-                                                                 const size_t *__restrict__ koff,
-                                                                 const double2 *__restrict__ dense, int nrhs,
-                                                                 int S, const double2 *__restrict__ sigT,
-                                                                 const double2 *__restrict__ wts, int nsplit,
-                                                                 double2 *__restrict__ out) {
-  constexpr int NR = 8, RB = 4, KU = 2;   // KU steps of 4 sources per batch of loads
+// The mirror form on the FP64 matrix cores, for NR = 8 or 16 right-hand
+// sides: per image, out[t][c] += sum_s K[t][s] B[s][c] as 16 x 16 x 4
+// products with the 64 targets of the tile as four row blocks (A = the
+// stored values, 16 targets by 4 sources, read as before) and 2 NR columns
+// in blocks of 16: B[s][c] = w_c sigma_c(s) for the NR sums (weights of the
+// image) and w'_(c-NR) sigma_(c-NR)(s + ms) for the NR mirror sums (weights
+// of the mirror image), each lane forming its own element of B per step.
+// The weights sit in B, so the accumulators are the totals.
+template <int NR>
+__global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
+                                                                     const int *__restrict__ tile_group,
+                                                                     const size_t *__restrict__ koff,
+                                                                     const double2 *__restrict__ dense, int nrhs,
+                                                                     int S, const double2 *__restrict__ sigT,
+                                                                     const double2 *__restrict__ wts, int nsplit,
+                                                                     double2 *__restrict__ out) {
+  static_assert(NR == 8 || NR == 16, "two NR columns in blocks of 16");
+  constexpr int RB = 4, CB = 2 * NR / 16, KU = 2;   // KU steps of 4 sources per batch of loads
   extern __shared__ double shm[];
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
@@ -366,20 +327,26 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror8_kernel(int ntp, const 
   const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
   const double2 *base = dense + koff[gi] + (size_t)((tile * 64 - t0) >> 6) * nimg * S * 64;
   const int i = l & 15, k = l >> 4;          // A: target 16 rb + i, source 4 step + k
-  const int j = l & 15;                      // B: column j, source 4 step + k
-  const int jr = j < NR ? j : j - NR;        // right-hand side of column j
-  dx4 tr[RB], ti[RB];
+  const int j = l & 15;                      // B: column 16 cb + j, source 4 step + k
+  dx4 tr[RB][CB], ti[RB][CB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    tr[rb] = dx4{0, 0, 0, 0};
-    ti[rb] = tr[rb];
-  }
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      tr[rb][cb] = dx4{0, 0, 0, 0};
+      ti[rb][cb] = tr[rb][cb];
+    }
   for (int im = 0; im < nimg; ++im) {
-    const int wim = j < NR ? im : groups[gi].mir[im];
-    const double2 wj = jr < nrhs ? wts[((size_t)gi * 9 + wim) * nrhs + jr] : cz(0.0, 0.0);
+    double2 wj[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int c = 16 * cb + j, jr = c < NR ? c : c - NR;
+      const int wim = c < NR ? im : groups[gi].mir[im];
+      wj[cb] = jr < nrhs ? wts[((size_t)gi * 9 + wim) * nrhs + jr] : cz(0.0, 0.0);
+    }
     const double2 *kim = base + (size_t)im * S * 64;
     for (int c0 = w_begin; c0 < w_end; c0 += 4 * KU) {   // wave-uniform trip count
-      double2 a[KU][RB], b[KU];
+      double2 a[KU][RB], bb[KU][CB];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
         const int sidx = c0 + 4 * u + k;
@@ -395,32 +362,44 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror8_kernel(int ntp, const 
           a[u][rb] = cz(__longlong_as_double(__double_as_longlong(v.x) & m),
                         __longlong_as_double(__double_as_longlong(v.y) & m));
         }
-        const int sm = j < NR ? sc : (sc + ms >= S ? sc + ms - S : sc + ms);
-        b[u] = cmul(wj, sigT[(size_t)sm * NR + jr]);   // zero columns past nrhs through wj
+        const int smir = sc + ms >= S ? sc + ms - S : sc + ms;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int c = 16 * cb + j, jr = c < NR ? c : c - NR;
+          bb[u][cb] = cmul(wj[cb], sigT[(size_t)(c < NR ? sc : smir) * NR + jr]);   // zero past nrhs via wj
+        }
       }
 #pragma unroll
       for (int u = 0; u < KU; ++u)
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          tr[rb] = mfma_f64(a[u][rb].x, b[u].x, tr[rb]);
-          tr[rb] = mfma_f64(-a[u][rb].y, b[u].y, tr[rb]);
-          ti[rb] = mfma_f64(a[u][rb].x, b[u].y, ti[rb]);
-          ti[rb] = mfma_f64(a[u][rb].y, b[u].x, ti[rb]);
-        }
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            tr[rb][cb] = mfma_f64(a[u][rb].x, bb[u][cb].x, tr[rb][cb]);
+            tr[rb][cb] = mfma_f64(-a[u][rb].y, bb[u][cb].y, tr[rb][cb]);
+            ti[rb][cb] = mfma_f64(a[u][rb].x, bb[u][cb].y, ti[rb][cb]);
+            ti[rb][cb] = mfma_f64(a[u][rb].y, bb[u][cb].x, ti[rb][cb]);
+          }
     }
   }
-  // element v of lane j + 16 g: target 16 rb + g + 4 v, column j; the four
-  // waves' sums meet in LDS [4][8 columns][64 targets], the eight sums first,
-  // then the eight mirror sums
+  // element v of lane j + 16 g: target 16 rb + g + 4 v, column 16 cb + j; the
+  // four waves' sums meet in LDS [4][NR][64 targets], the NR sums first, then
+  // the NR mirror sums
   double2 *red = reinterpret_cast<double2 *>(shm);
   const int g = l >> 4;
   for (int half = 0; half < 2; ++half) {
     if (half) __syncthreads();
-    if ((j >= NR) == (half == 1)) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+    for (int cb = 0; cb < CB; ++cb) {
+      const int c = 16 * cb + j;
+      if ((c >= NR) == (half == 1)) {
+        const int jr = c < NR ? c : c - NR;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[(wv * NR + jr) * 64 + 16 * rb + g + 4 * v] = cz(tr[rb][v], ti[rb][v]);
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            red[(wv * NR + jr) * 64 + 16 * rb + g + 4 * v] = cz(tr[rb][cb][v], ti[rb][cb][v]);
+      }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
@@ -485,17 +464,15 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
                      nrhs, NR, S, sigma, sigT);
   const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
-  if (plan_mirrored(plan, true) && NR == 8)
-    hipLaunchKernelGGL(nsum_dense_mirror8_kernel, dim3(plan.ntarget_pad / 64, nsplit), dim3(256),
-                       (size_t)4 * 8 * 64 * sizeof(double2), s, plan.ntarget_pad, plan.grp.as<NsumGroup>(),
-                       plan.tile_group.as<int>(), plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT,
-                       w, nsplit, dst);
-  else if (plan_mirrored(plan, true))
-    hipLaunchKernelGGL((nsum_dense_kernel<NR, true>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
-                       plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
-                       plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+  if (plan_mirrored(plan, true)) {
+    MFS_REQUIRE(NR == 8 || NR == 16, "neighbour sum: the mirror form runs with 8 or 16 right-hand sides");
+    hipLaunchKernelGGL((nsum_dense_mirror_mfma_kernel<NR == 16 ? 16 : 8>), dim3(plan.ntarget_pad / 64, nsplit),
+                       dim3(256), (size_t)4 * NR * 64 * sizeof(double2), s, plan.ntarget_pad,
+                       plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
+                       plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+  }
   else
-    hipLaunchKernelGGL((nsum_dense_kernel<NR, false>), dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
+    hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
                        plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(),
                        plan.koff.as<size_t>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
   HIP_CHECK(hipGetLastError());
@@ -542,7 +519,11 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
   const int nsplit = nsum_splits(plan, S);
   double2 *dst = (nsplit == 1) ? out : partial;
   if (plan.dense.p && plan.dense_src == src && plan.dense_S == S && plan.dense_k == k) {
-    if (nrhs <= 1) launch_nsum_dense_t<1>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    if (plan_mirrored(plan, true)) {
+      // the matrix-core mirror form: 8 columns for up to 8 right-hand sides, else 16
+      if (nrhs <= 8) launch_nsum_dense_t<8>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+      else launch_nsum_dense_t<16>(plan, nrhs, S, sigma, w, nsplit, dst, s);
+    } else if (nrhs <= 1) launch_nsum_dense_t<1>(plan, nrhs, S, sigma, w, nsplit, dst, s);
     else if (nrhs <= 2) launch_nsum_dense_t<2>(plan, nrhs, S, sigma, w, nsplit, dst, s);
     else if (nrhs <= 4) launch_nsum_dense_t<4>(plan, nrhs, S, sigma, w, nsplit, dst, s);
     else if (nrhs <= 8) launch_nsum_dense_t<8>(plan, nrhs, S, sigma, w, nsplit, dst, s);
