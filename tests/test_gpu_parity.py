@@ -312,6 +312,34 @@ def test_wide_jacobi_blocks(mfs, ctx, small_oracle, monkeypatch):
         assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
 
 
+def test_sixteen_wave_batch_matches_small_batches(mfs, ctx):
+    """Twelve incidences in one batched solve (the stored-field sums then run
+    with 16 right-hand sides: the matrix-core mirror form with two column
+    blocks) against the same incidences in batches of four (8 right-hand
+    sides, the form the oracle parity tests cover): Bragg amplitudes and
+    fields to 1e-12."""
+    pr = W.small_periodic(nwaves=12)
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    L = _lat(mfs, pr.lattice)
+    waves = [(w.theta, w.phi) for w in pr.waves]
+    kw = dict(tol=1e-12, maxit=100, targets=pr.targets, q_field=pr.q_field)
+    big = mfs.solve_incident(ctx, op, L, waves, **kw)
+    small = []
+    for i in range(0, 12, 4):
+        small += mfs.solve_incident(ctx, op, L, waves[i:i + 4], **kw)
+    worst = 0.0
+    for r1, r2 in zip(big, small):
+        assert np.array_equal(r1.m, r2.m) and np.array_equal(r1.n, r2.n)
+        ea = np.max(np.abs(r1.a - r2.a)) / np.max(np.abs(r2.a))
+        eb = np.max(np.abs(r1.b - r2.b)) / np.max(np.abs(r2.b))
+        eu = np.linalg.norm(r1.field - r2.field) / np.linalg.norm(r2.field)
+        worst = max(worst, ea, eb, eu)
+    log(f"[16 waves] one batch of 12 vs three of 4: worst relative difference {worst:.2e}")
+    assert worst < 1e-12
+
+
 def test_periodic_k10_full_size_vs_golden(mfs, ctx):
     """Full size of the benchmark workload, in the benchmark's launch
     configuration (all 8 incidences in one batched solve), against the
