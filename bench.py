@@ -386,9 +386,9 @@ def main():
         # (plus the strengths and outputs, under 0.1% of them)
         gbs = near_bytes / (nsum_avg * 1e-3) / 1e9
         traffic = measured_traffic("nsum.hip", "nsum_dense_periodic_k10_traffic.txt")
-        roof_nsum = {"bound": "hbm", "kernel": "nsum_dense_mirror_mfma_kernel<8> + nsum_dense_kernel<8> (A_else "
-                                               "surface sums from the mirror-paired stored near field on the matrix "
-                                               "cores, C wall sums; all waves, mean over launches)",
+        roof_nsum = {"bound": "hbm", "kernel": "nsum_dense_mirror_mfma_kernel<8> (A_else surface sums and C wall "
+                                               "sums from the mirror-paired stored near field on the matrix cores; "
+                                               "all waves, mean over launches)",
                      "achieved": gbs, "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs / PEAK_HBM,
                      "traffic": traffic, "traffic_unit": "bytes per launch",
                      "launch_ms": nsum_avg, "bytes_per_launch": near_bytes,

@@ -137,6 +137,9 @@ void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
   if (b.P % 2 == 0) {
     g.mt = (b.P / 2) * b.M;
     g.ms = (b.P / 2) * b.N;
+    g.pkind = 1;
+    g.pg = 0;
+    g.psign = 1;
     for (int im = 0; im < g.nimg; ++im)
       for (int jm = 0; jm < g.nimg; ++jm)
         if (g.ia[jm] == -g.ia[im] && g.ib[jm] == -g.ib[im]) g.mir[im] = jm;
@@ -161,12 +164,19 @@ void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s) {
   } else {
     NsumGroup gv = g;
     gv.deriv = 0;
+    gv.pg = 1;   // its mirror weights are its own
     build_plan(plan, {g, gv}, {t, t}, s);
   }
 }
 
 // The 12 wall target groups R L Rx Lx F B Fy By T Tz D Dz (images and kinds).
-void walls_plan(const mfs_lattice &lat, NsumPlan &plan, hipStream_t s) {
+// With P even (sources at the P angles of ring l N + j, mirror l + P/2) and
+// M1 even, the half-turn about the z axis pairs the groups: R with L, F with
+// B (wall node (a, b) with node (M1-1-a, b) of the other wall; the first of
+// each pair keeps the stored values for both), the x and y derivative groups
+// likewise with the sign reversed (their direction turns over), and T, Tz,
+// D, Dz each with itself (node i with node M1^2-1-i).
+void walls_plan(const mfs_lattice &lat, int P, int N, NsumPlan &plan, hipStream_t s) {
   std::vector<double> wall;
   wall_nodes(lat, wall);
   const int n = lat.M1 * lat.M1;
@@ -196,6 +206,22 @@ void walls_plan(const mfs_lattice &lat, NsumPlan &plan, hipStream_t s) {
     for (int i = 0; i < n; ++i) t[(size_t)(3 + dircomp) * n + i] = 1.0;
     groups.push_back(g);
     tg.push_back(std::move(t));
+  }
+  if (P % 2 == 0 && lat.M1 % 2 == 0) {
+    const int partner[12] = {1, 0, 3, 2, 5, 4, 7, 6, 8, 9, 10, 11};
+    const int sign[12] = {1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1};
+    for (int gi = 0; gi < 12; ++gi) {
+      NsumGroup &g = groups[gi];
+      const NsumGroup &q = groups[partner[gi]];
+      g.ms = (P / 2) * N;
+      g.pg = partner[gi];
+      g.psign = sign[gi];
+      g.m1 = lat.M1;
+      g.pkind = partner[gi] == gi ? 4 : (gi % 2 == 0 ? 2 : 3);
+      for (int im = 0; im < g.nimg; ++im)
+        for (int jm = 0; jm < q.nimg; ++jm)
+          if (q.ia[jm] == -g.ia[im] && q.ib[jm] == -g.ib[im]) g.mir[im] = jm;
+    }
   }
   build_plan(plan, groups, tg, s);
 }
@@ -615,7 +641,7 @@ mfs_status mfs_neighbour_sum(const mfs_op *op, int32_t body, const mfs_lattice *
     nout = b.P * b.M;
   } else if (target_set == MFS_TARGETS_WALLS) {
     MFS_REQUIRE(lat->M1 > 0, "M1 > 0");
-    walls_plan(*lat, plan, s);
+    walls_plan(*lat, b.P, b.N, plan, s);
     walls_weights(al, be, plan, w);
     nout = 8 * lat->M1 * lat->M1;
   } else if (target_set == MFS_TARGETS_USER) {

@@ -41,7 +41,7 @@ void source_points_of(const BodyData &b, const std::vector<double> &srho, const 
 void build_plan(NsumPlan &plan, const std::vector<NsumGroup> &groups,
                 const std::vector<std::vector<double>> &tg, hipStream_t s);
 void surface_plan(const BodyData &b, NsumPlan &plan, hipStream_t s);
-void walls_plan(const mfs_lattice &lat, NsumPlan &plan, hipStream_t s);
+void walls_plan(const mfs_lattice &lat, int P, int N, NsumPlan &plan, hipStream_t s);
 void user_plan(const double *user, int nuser, int want, bool nine, NsumPlan &plan, hipStream_t s);
 void walls_weights(const std::vector<std::complex<double>> &al, const std::vector<std::complex<double>> &be,
                    const NsumPlan &plan, std::vector<double2> &w);

@@ -128,6 +128,13 @@ struct NsumGroup {
   // targets only.
   int mt, ms;
   int mir[9];
+  // General pairing of the stored field (pkind 0: none; 1: the shift above;
+  // 2: this group's target (a, b) pairs target (m1-1-a, b) of group pg, whose
+  // values are not stored; 3: group served by its partner pg (nothing
+  // stored); 4: target i pairs target nt-1-i of the same group).  psign is
+  // the factor of the mirror values (-1 for a normal derivative whose
+  // direction the half-turn reverses); mir[] indexes the partner's images.
+  int pkind, pg, psign, m1;
 };
 struct NsumPlan {
   int ntarget_pad;    // targets padded per group to multiples of 64

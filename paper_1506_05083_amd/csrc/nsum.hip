@@ -24,9 +24,31 @@ constexpr int SC = 128;     // sources per LDS chunk (32 per wave)
 constexpr int MAXR = 16;    // right-hand sides per launch
 constexpr int DU = 16;      // stored values in flight per wave in the dense sum
 
-// the mirror offset of a group if the stored field can use it (whole tiles
-// on both sides of the pairing), else 0
-__host__ __device__ inline int dense_mt(const NsumGroup &g) { return (g.mt > 0 && g.mt % 64 == 0) ? g.mt : 0; }
+// Targets of a group whose values a paired stored field keeps (whole tiles):
+// the first mt for the surface shift (when mt fills whole tiles), all for the
+// first group of a cross pair, none for the group its partner serves, the
+// first half for a self-paired group; -1 if the group cannot be paired.
+__host__ __device__ inline int dense_kept(const NsumGroup &g) {
+  switch (g.pkind) {
+    case 1: return g.mt % 64 == 0 ? g.mt : -1;
+    case 2: return (g.nt + 63) / 64 * 64;
+    case 3: return 0;
+    case 4: return (g.nt / 2 + 63) / 64 * 64;
+    default: return -1;
+  }
+}
+// targets (from the first) whose sums and mirror sums a paired workgroup forms
+__host__ __device__ inline int pair_primaries(const NsumGroup &g) {
+  return g.pkind == 1 ? g.mt : g.pkind == 2 ? g.nt : g.pkind == 4 ? g.nt / 2 : 0;
+}
+// the target paired with group-local target q of a paired group, as an index
+// into the whole plan
+__device__ inline int pair_target(const NsumGroup *groups, const NsumGroup &g, int q) {
+  if (g.pkind == 1) return g.t0 + q + g.mt;
+  if (g.pkind == 4) return g.t0 + g.nt - 1 - q;
+  const int a = q / g.m1, b = q % g.m1;   // pkind 2: node (a, b) -> (m1-1-a, b) of the partner
+  return groups[g.pg].t0 + (g.m1 - 1 - a) * g.m1 + b;
+}
 
 // G(x - y) = e^{ikR} / (4 pi R) for (dx, dy, dz) = x - y, or its derivative
 // along the target direction (tx, ty, tz) when deriv is set
@@ -175,12 +197,12 @@ __global__ __launch_bounds__(256) void nsum_fill_kernel(const double *__restrict
                                                         const int *__restrict__ tile_group,
                                                         const size_t *__restrict__ koff, double k, double ex,
                                                         double ey, const double *__restrict__ src, int S,
-                                                        int nsplit, double2 *__restrict__ dense) {
+                                                        int nsplit, int paired, double2 *__restrict__ dense) {
   __shared__ double sx[SC], sy[SC], szs[SC];
   const int tile = blockIdx.x, split = blockIdx.y;
   const int gi = tile_group[tile];
   const NsumGroup &g = groups[gi];
-  if (dense_mt(g) > 0 && tile * 64 - g.t0 >= g.mt) return;   // second half of a mirror pair: not stored
+  if (paired && tile * 64 - g.t0 >= dense_kept(g)) return;   // values served by the mirror: not stored
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = tile * 64 + lane;
   const double xt = tgt[t], yt = tgt[ntp + t], zt = tgt[2 * ntp + t];
@@ -302,7 +324,11 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
 // in blocks of 16: B[s][c] = w_c sigma_c(s) for the NR sums (weights of the
 // image) and w'_(c-NR) sigma_(c-NR)(s + ms) for the NR mirror sums (weights
 // of the mirror image), each lane forming its own element of B per step.
-// The weights sit in B, so the accumulators are the totals.
+// The weights sit in B, so the accumulators are the totals.  The pairing is
+// that of the group (NsumGroup::pkind): the surface shift t -> t + mt, a wall
+// node and its mirror on the opposite wall (the partner group's weights, and
+// a sign for the normal derivatives the half-turn reverses), or a node and
+// its mirror on the same wall.
 template <int NR>
 __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                                      const int *__restrict__ tile_group,
@@ -318,14 +344,17 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, co
   const int gi = tile_group[tile];
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int t0 = groups[gi].t0, nimg = groups[gi].nimg;
-  const int mt = groups[gi].mt, ms = groups[gi].ms;
-  if (tile * 64 - t0 >= mt) return;   // served by the mirror tile
+  const NsumGroup &G = groups[gi];
+  const int t0 = G.t0, nimg = G.nimg, ms = G.ms;
+  const int tl = tile * 64 - t0;
+  if (tl >= dense_kept(G)) return;   // values served by the mirror (or by the partner group)
+  const int nprim = pair_primaries(G);
+  const double psign = G.psign;
   const int per = (S + nsplit - 1) / nsplit;
   const int s_begin = split * per, s_end = min(S, s_begin + per);
   const int qw = (s_end - s_begin + 3) / 4;
   const int w_begin = min(s_end, s_begin + wv * qw), w_end = min(s_end, w_begin + qw);
-  const double2 *base = dense + koff[gi] + (size_t)((tile * 64 - t0) >> 6) * nimg * S * 64;
+  const double2 *base = dense + koff[gi] + (size_t)(tl >> 6) * nimg * S * 64;
   const int i = l & 15, k = l >> 4;          // A: target 16 rb + i, source 4 step + k
   const int j = l & 15;                      // B: column 16 cb + j, source 4 step + k
   dx4 tr[RB][CB], ti[RB][CB];
@@ -341,8 +370,11 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, co
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
       const int c = 16 * cb + j, jr = c < NR ? c : c - NR;
-      const int wim = c < NR ? im : groups[gi].mir[im];
-      wj[cb] = jr < nrhs ? wts[((size_t)gi * 9 + wim) * nrhs + jr] : cz(0.0, 0.0);
+      // the mirror columns take the partner group's weight of the mirror image
+      const double2 wv2 = jr < nrhs ? (c < NR ? wts[((size_t)gi * 9 + im) * nrhs + jr]
+                                              : wts[((size_t)G.pg * 9 + G.mir[im]) * nrhs + jr])
+                                    : cz(0.0, 0.0);
+      wj[cb] = c < NR ? wv2 : cscale(wv2, psign);
     }
     const double2 *kim = base + (size_t)im * S * 64;
     for (int c0 = w_begin; c0 < w_end; c0 += 4 * KU) {   // wave-uniform trip count
@@ -407,7 +439,14 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, co
       if (r >= nrhs) continue;
       double2 v = red[(0 * NR + r) * 64 + tt];
       for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + tt]);
-      out[((size_t)split * nrhs + r) * ntp + tile * 64 + (half ? mt : 0) + tt] = v;
+      const int q = tl + tt;   // group-local target
+      double2 *row = out + ((size_t)split * nrhs + r) * ntp;
+      if (!half) {
+        // a target past the primaries of a self pair or a shift is a mirror, written by its partner
+        if (q < nprim || G.pkind == 2) row[tile * 64 + tt] = v;
+      } else if (q < nprim) {
+        row[pair_target(groups, G, q)] = v;
+      }
     }
   }
 }
@@ -448,9 +487,9 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
 bool plan_mirrored(const NsumPlan &plan, bool dense) {
   bool any = false, all = true;
   for (const auto &g : plan.groups) {
-    const int mt = dense ? dense_mt(g) : g.mt;
-    any = any || mt > 0;
-    all = all && mt > 0;
+    const bool p = dense ? dense_kept(g) >= 0 : (g.pkind == 1 && g.mt > 0);
+    any = any || p;
+    all = all && p;
   }
   MFS_REQUIRE(any == all, "neighbour sum: mirror pairing must hold for every group or none");
   return all;
@@ -505,7 +544,10 @@ void launch_nsum_t(const NsumPlan &plan, int nrhs, double k, double ex, double e
 int nsum_splits(const NsumPlan &plan, int S) {
   // tiles with work in the stored-field sum (a mirror pair's second half has none)
   int tiles = 0;
-  for (const auto &g : plan.groups) tiles += g.mt > 0 ? cdiv(g.mt, 64) : round_up(std::max(g.nt, 1), 64) / 64;
+  for (const auto &g : plan.groups)
+    tiles += g.pkind == 1 && g.mt > 0 ? cdiv(g.mt, 64)
+             : dense_kept(g) >= 0     ? dense_kept(g) / 64
+                                      : round_up(std::max(g.nt, 1), 64) / 64;
   tiles = std::max(tiles, 1);
   int ns = std::max(1, 3840 / tiles);
   ns = std::min(ns, std::max(1, S / 256));
@@ -543,12 +585,13 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
 
 bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,
                       size_t max_bytes, hipStream_t s) {
+  const bool paired = plan_mirrored(plan, true);
   size_t off = 0;
   std::vector<size_t> koff(plan.groups.size());
   for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
     const NsumGroup &g = plan.groups[gi];
     koff[gi] = off;
-    off += (size_t)g.nimg * S * (dense_mt(g) > 0 ? g.mt : round_up(std::max(g.nt, 1), 64));
+    off += (size_t)g.nimg * S * (paired ? dense_kept(g) : round_up(std::max(g.nt, 1), 64));
   }
   const size_t bytes = off * sizeof(double2);
   if (bytes > max_bytes) return false;
@@ -562,7 +605,7 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   const int nsplit = nsum_splits(plan, S);
   hipLaunchKernelGGL(nsum_fill_kernel, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), 0, s, plan.tgt.as<double>(),
                      plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
-                     k, ex, ey, src, S, nsplit, plan.dense.as<double2>());
+                     k, ex, ey, src, S, nsplit, paired ? 1 : 0, plan.dense.as<double2>());
   HIP_CHECK(hipGetLastError());
   plan.dense_src = src;
   plan.dense_S = S;

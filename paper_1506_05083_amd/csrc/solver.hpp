@@ -136,7 +136,7 @@ struct Solver {
 
   void setup_sums() {
     surface_plan(b, psurf, s);
-    walls_plan(lat, pwalls, s);
+    walls_plan(lat, b.P, b.N, pwalls, s);
     std::vector<double2> w1, w2;
     image_weights(al, be, psurf, w1);
     walls_weights(al, be, pwalls, w2);

@@ -66,3 +66,47 @@ def test_other_rotations_do_not_pair_the_images():
     sv = np.max(np.abs(ref))
     assert np.max(np.abs(vq[(1, 0)] - ref)) > 1e-3 * sv
     assert np.max(np.abs(vt[(1, 0)] - ref)) > 1e-3 * sv
+
+
+def test_half_turn_pairs_the_wall_nodes():
+    """The walls of the unit cell (Sec. 4.1): the half-turn takes the right
+    wall's Gauss node (a, b) to the left wall's node (M1-1-a, b), the front
+    wall's to the back wall's likewise, and the top (bottom) wall's node i to
+    its own node M1^2-1-i, the Gauss rule being symmetric.  Values at the
+    paired node against the rotated sources and the negated shift agree; an
+    x or y derivative changes sign (its direction turns over), a z derivative
+    does not."""
+    from oracle import periodic
+    pr = W.small_periodic()
+    b, lat = pr.body, pr.lattice
+    P, M1 = b.P, lat.M1
+    assert P % 2 == 0 and M1 % 2 == 0
+    g = geometry.build_geometry(b)
+    Y = geometry.source_ring_points(g, b.P)          # [P, N, 3]
+    w = periodic.wall_nodes(lat)
+    idx = np.arange(M1 * M1)
+    a_, b_ = idx // M1, idx % M1
+    cross = (M1 - 1 - a_) * M1 + b_
+    own = M1 * M1 - 1 - idx
+    ex, ey, ez = np.eye(3)
+    cases = [(w.R, w.L, cross, ex), (w.F, w.B, cross, ey), (w.T, w.T, own, ez), (w.D, w.D, own, ez)]
+    ls = np.array([0, 2, P // 2 + 3, P - 1])
+    ys, ym = Y[ls], Y[(ls + P // 2) % P]
+    sel = np.array([0, 7, M1 * M1 // 2 + 1, M1 * M1 - 1])
+    for (X0, X1, pair, d) in cases:
+        assert np.allclose(X1[pair[sel]], X0[sel] * np.array([-1.0, -1.0, 1.0]), atol=1e-15)
+        x0 = X0[sel][:, None, None, :]
+        x1 = X1[pair[sel]][:, None, None, :]
+        nd = np.broadcast_to(d, x0.shape)
+        sgn = -1.0 if d[2] == 0 else 1.0
+        for (a, c) in _images():
+            s0 = np.array([a * lat.ex, c * lat.ey, 0.0])
+            v0 = kernel.G(b.k, x0, ys[None] + s0)
+            v1 = kernel.G(b.k, x1, ym[None] - s0)
+            d0 = kernel.dG_dnx(b.k, x0, nd, ys[None] + s0)
+            d1 = kernel.dG_dnx(b.k, x1, nd, ym[None] - s0)
+            assert np.max(np.abs(v1 - v0)) < 1e-13 * np.max(np.abs(v0)), (a, c)
+            assert np.max(np.abs(d1 - sgn * d0)) < 1e-13 * np.max(np.abs(d0)), (a, c)
+            # without the rotation of the sources the pairing fails
+            bad = kernel.G(b.k, x1, ys[None] - s0)
+            assert np.max(np.abs(bad - v0)) > 1e-3 * np.max(np.abs(v0)), (a, c)
