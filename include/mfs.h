@@ -282,7 +282,12 @@ mfs_status mfs_field_interior(const mfs_op *op, int32_t body, int32_t nrhs, int3
  * dense in RAM and applies A_else by the FMM; on one GPU all three fit).
  * max_bytes bounds that storage: 0 evaluates the sums on the fly every
  * iteration; the default (UINT64_MAX) stores them whenever they fit with
- * 2 GiB of device memory to spare.  Results agree to rounding either way. */
+ * 2 GiB of device memory to spare.  Results agree to rounding either way.
+ * Both forms split the sources of every 64-target tile into slices (one
+ * workgroup each, at least 256 sources a slice) aiming at 6144 workgroups
+ * per sum; the environment variable MFS_NSUM_WORKGROUPS, read once per
+ * process, sets another aim (slice count changes only the order in which
+ * partial sums are added). */
 mfs_status mfs_set_near_field_budget(mfs_op *op, uint64_t max_bytes);
 
 /* (c) Periodic solve for nwaves incident waves (Sec. 4.2): per wave, fill and

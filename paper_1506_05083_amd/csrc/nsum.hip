@@ -13,6 +13,7 @@
 // sincos) is shared by every right-hand side.  Slices are summed by a second
 // kernel.  FP64 VALU bound; the only HBM traffic is the strengths and the
 // output.
+#include <cstdlib>
 #include <algorithm>
 
 #include "internal.hpp"
@@ -549,7 +550,14 @@ int nsum_splits(const NsumPlan &plan, int S) {
              : dense_kept(g) >= 0     ? dense_kept(g) / 64
                                       : round_up(std::max(g.nt, 1), 64) / 64;
   tiles = std::max(tiles, 1);
-  int ns = std::max(1, 3840 / tiles);
+  // eight rounds of workgroups at three 256-thread workgroups per CU on 256 CUs;
+  // MFS_NSUM_WORKGROUPS (read once) sets another target
+  static const int target = []() -> int {
+    const char *e = std::getenv("MFS_NSUM_WORKGROUPS");
+    const int t = e ? std::atoi(e) : 0;
+    return t > 0 ? t : 6144;
+  }();
+  int ns = std::max(1, target / tiles);
   ns = std::min(ns, std::max(1, S / 256));
   return ns;
 }
