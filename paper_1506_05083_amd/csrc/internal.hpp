@@ -145,6 +145,8 @@ struct NsumPlan {
   // optional dense near field (nsum_build_dense): kernel values of every
   // group, image, source and target, for the sources `dense_src` (S of them)
   DevBuf dense, koff;
+  DevBuf dense_tiles; // int [ndense_tiles]: the tiles whose values are stored (paired form), most images first
+  int ndense_tiles = 0;
   DevBuf sigT;        // [S][MAXR] strengths of one launch, source-major (scratch of the dense sum)
   const double *dense_src = nullptr;
   int dense_S = 0;

@@ -329,11 +329,14 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
 // that of the group (NsumGroup::pkind): the surface shift t -> t + mt, a wall
 // node and its mirror on the opposite wall (the partner group's weights, and
 // a sign for the normal derivatives the half-turn reverses), or a node and
-// its mirror on the same wall.
+// its mirror on the same wall.  The grid runs over the stored tiles only
+// (tiles[], those with the most images first, so that a launch ends on short
+// workgroups).
 template <int NR>
 __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                                      const int *__restrict__ tile_group,
                                                                      const size_t *__restrict__ koff,
+                                                                     const int *__restrict__ tiles,
                                                                      const double2 *__restrict__ dense, int nrhs,
                                                                      int S, const double2 *__restrict__ sigT,
                                                                      const double2 *__restrict__ wts, int nsplit,
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, co
   static_assert(NR == 8 || NR == 16, "two NR columns in blocks of 16");
   constexpr int RB = 4, CB = 2 * NR / 16, KU = 2;   // KU steps of 4 sources per batch of loads
   extern __shared__ double shm[];
-  const int tile = blockIdx.x, split = blockIdx.y;
+  const int tile = tiles[blockIdx.x], split = blockIdx.y;   // stored tiles only
   const int gi = tile_group[tile];
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -506,10 +509,11 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
   if (plan_mirrored(plan, true)) {
     MFS_REQUIRE(NR == 8 || NR == 16, "neighbour sum: the mirror form runs with 8 or 16 right-hand sides");
-    hipLaunchKernelGGL((nsum_dense_mirror_mfma_kernel<NR == 16 ? 16 : 8>), dim3(plan.ntarget_pad / 64, nsplit),
+    MFS_REQUIRE(plan.ndense_tiles > 0, "neighbour sum: stored tiles of the paired field missing");
+    hipLaunchKernelGGL((nsum_dense_mirror_mfma_kernel<NR == 16 ? 16 : 8>), dim3(plan.ndense_tiles, nsplit),
                        dim3(256), (size_t)4 * NR * 64 * sizeof(double2), s, plan.ntarget_pad,
                        plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
-                       plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+                       plan.dense_tiles.as<int>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
   }
   else
     hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
@@ -610,6 +614,23 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   plan.sigT.alloc((size_t)S * MAXR * sizeof(double2));
   plan.koff.alloc(koff.size() * sizeof(size_t));
   HIP_CHECK(hipMemcpyAsync(plan.koff.p, koff.data(), koff.size() * sizeof(size_t), hipMemcpyHostToDevice, s));
+  std::vector<int> tiles;
+  if (paired) {
+    // the sum's workgroups run over the stored tiles only, those with the
+    // most images (the longest workgroups) first
+    std::vector<std::pair<int, int>> kt;   // (images, tile)
+    for (const NsumGroup &g : plan.groups)
+      for (int t = 0; t < dense_kept(g) / 64; ++t) kt.emplace_back(g.nimg, g.t0 / 64 + t);
+    std::stable_sort(kt.begin(), kt.end(), [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+      return a.first > b.first;
+    });
+    for (const auto &e : kt) tiles.push_back(e.second);
+    MFS_REQUIRE(!tiles.empty(), "neighbour sum: a paired field with no stored tile");
+    plan.dense_tiles.alloc(tiles.size() * sizeof(int));
+    HIP_CHECK(hipMemcpyAsync(plan.dense_tiles.p, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  plan.ndense_tiles = (int)tiles.size();
+  HIP_CHECK(hipStreamSynchronize(s));   // the host vectors above are copied before they go
   const int nsplit = nsum_splits(plan, S);
   hipLaunchKernelGGL(nsum_fill_kernel, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), 0, s, plan.tgt.as<double>(),
                      plan.ntarget_pad, plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
