@@ -101,6 +101,32 @@ __device__ inline int task_col(int a, int bi, int bj, int nb, int n) {
   return (blk < nb && c < n) ? c : -1;
 }
 
+// Converged pairs.  A block pair found converged (no rotation) needs no new
+// check until one of its blocks turns: bmod[mat][blk] is the round (counted
+// over sweeps) in which block blk last turned, pchk[mat][a][b] (a < b) the
+// round in which the pair was last found converged, -1 for never.  The Gram
+// matrix and inner sweep of such a pair would reproduce the same verdict from
+// the same columns, so skipping them changes no result.
+struct JacClean {
+  int *bmod, *pchk;
+  int *nchk;   // [mat] pairs checked (not skipped) in the current sweep
+  int nbp;
+};
+__device__ inline bool jac_clean(const JacClean &cs, int mat, int bi, int bj) {
+  const int a = min(bi, bj), b = max(bi, bj);
+  const int c = cs.pchk[((size_t)mat * cs.nbp + a) * cs.nbp + b];
+  return c >= 0 && c > cs.bmod[mat * cs.nbp + bi] && c > cs.bmod[mat * cs.nbp + bj];
+}
+__global__ void jac_clean_init(JacClean cs, int nmat) {
+  const long n = (long)nmat * cs.nbp * (cs.nbp + 1);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    cs.bmod[i] = -1;   // bmod and pchk are one allocation
+}
+__global__ void jac_clear_checks(JacClean cs, int nmat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nmat) cs.nchk[i] = 0;
+}
+
 // 2. one workgroup per task: H = sum of the partials, one Jacobi sweep over
 //    its JC columns on H, J = product of the rotations -> jbuf, rot = any rotation
 template <int JB>
@@ -108,15 +134,20 @@ __global__ __launch_bounds__(JB * JB) void jac_inner_kernel(const MatDesc *__res
                                                         const int *__restrict__ act, int round, double tol_eps,
                                                         const double2 *__restrict__ hpart,
                                                         double2 *__restrict__ jbuf, int *__restrict__ rot,
-                                                        int npair_max, int ntile_max) {
+                                                        int npair_max, int ntile_max, JacClean cs, int gr) {
   constexpr int JC = 2 * JB, IT = JB * JB;   // one 2 x 2 block of H per thread
   const int mat = blockIdx.y;
   if (!act[mat]) return;
   const MatDesc d = descs[mat];
   const int pair = blockIdx.x;
+  int tbi, tbj;
   {
-    int bi, bj, nb;
-    if (!task_blocks<JB>(d, round, pair, bi, bj, nb)) return;
+    int nb;
+    if (!task_blocks<JB>(d, round, pair, tbi, tbj, nb)) return;
+  }
+  if (jac_clean(cs, mat, tbi, tbj)) {   // uniform; nothing of this pair changes this round
+    if (threadIdx.x == 0) rot[(size_t)mat * npair_max + pair] = 0;
+    return;
   }
   __shared__ double2 Hs[JC][JC + 1];
   __shared__ double2 Js[JC][JC + 1];
@@ -241,7 +272,14 @@ __global__ __launch_bounds__(JB * JB) void jac_inner_kernel(const MatDesc *__res
   for (int idx = tid; idx < JC * JC; idx += IT) jo[idx] = Js[idx / JC][idx % JC];
   if (tid == 0) {
     rot[(size_t)mat * npair_max + pair] = s_nrot > 0;
-    if (s_nrot > 0) atomicAdd(d.flag, 1);
+    atomicAdd(cs.nchk + mat, 1);
+    if (s_nrot > 0) {
+      atomicAdd(d.flag, 1);
+      cs.bmod[mat * cs.nbp + tbi] = gr;
+      cs.bmod[mat * cs.nbp + tbj] = gr;
+    } else {
+      cs.pchk[((size_t)mat * cs.nbp + min(tbi, tbj)) * cs.nbp + max(tbi, tbj)] = gr;
+    }
   }
 }
 
@@ -258,7 +296,7 @@ __global__ __launch_bounds__(JB * JB) void jac_inner_kernel(const MatDesc *__res
 __global__ __launch_bounds__(64) void jac_gram_mfma_kernel(const MatDesc *__restrict__ descs,
                                                            const int *__restrict__ act, int round,
                                                            double2 *__restrict__ hpart, int npair_max,
-                                                           int ntile_max) {
+                                                           int ntile_max, JacClean cs) {
   constexpr int JB = 16, JC = 32, KB = 8;
   const int mat = blockIdx.z;
   if (!act[mat]) return;
@@ -268,6 +306,7 @@ __global__ __launch_bounds__(64) void jac_gram_mfma_kernel(const MatDesc *__rest
   if (rbeg >= n) return;
   int bi, bj, nb;
   if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
+  if (jac_clean(cs, mat, bi, bj)) return;   // converged and unchanged since
   const int l = threadIdx.x, c = l & 15, k = l >> 4;
   const int c0 = task_col<JB>(c, bi, bj, nb, n), c1 = task_col<JB>(JB + c, bi, bj, nb, n);
   const double2 *g0 = d.g + (size_t)max(c0, 0) * d.ldg, *g1 = d.g + (size_t)max(c1, 0) * d.ldg;
@@ -403,7 +442,7 @@ __device__ inline void gram32_pair(int w, int p, int &I, int &J) {
 __global__ __launch_bounds__(128) void jac_gram_mfma32_kernel(const MatDesc *__restrict__ descs,
                                                               const int *__restrict__ act, int round,
                                                               double2 *__restrict__ hpart, int npair_max,
-                                                              int ntile_max) {
+                                                              int ntile_max, JacClean cs) {
   constexpr int JB = 32, JC = 64, NF = 4, NP = 5;
   const int mat = blockIdx.z;
   if (!act[mat]) return;
@@ -413,6 +452,7 @@ __global__ __launch_bounds__(128) void jac_gram_mfma32_kernel(const MatDesc *__r
   if (rbeg >= n) return;
   int bi, bj, nb;
   if (!task_blocks<JB>(d, round, blockIdx.y, bi, bj, nb)) return;
+  if (jac_clean(cs, mat, bi, bj)) return;   // converged and unchanged since
   const int l = threadIdx.x & 63, c = l & 15, k = l >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int cf[NF];
@@ -620,13 +660,19 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
       }
     width[i] = tasks[i] > 0.0 ? cols / tasks[i] : 0.0;
   }
-  std::vector<int> flags(nmat), active(nmat, 1);
+  std::vector<int> flags(nmat), checked(nmat), active(nmat, 1);
   DevBuf act((size_t)nmat * sizeof(int));
   const int npair_max = std::max(1, nbpmax / 2);
   const int ntile_max = cdiv(nmax, GT), atile_max = cdiv(nmax, AT);
   DevBuf hpart((size_t)nmat * npair_max * ntile_max * JC * JC * sizeof(double2));
   DevBuf jbuf((size_t)nmat * npair_max * JC * JC * sizeof(double2));
   DevBuf rotf((size_t)nmat * npair_max * sizeof(int));
+  const size_t ncl = (size_t)nmat * nbpmax * (nbpmax + 1);
+  DevBuf cleanbuf((ncl + nmat) * sizeof(int));
+  JacClean cs{cleanbuf.as<int>(), cleanbuf.as<int>() + (size_t)nmat * nbpmax, cleanbuf.as<int>() + ncl, nbpmax};
+  hipLaunchKernelGGL(jac_clean_init, dim3(std::min(1024, cdiv(nmat * nbpmax * (nbpmax + 1), 256))), dim3(256), 0,
+                     s, cs, nmat);
+  HIP_CHECK(hipGetLastError());
   // rotation threshold 4 sqrt(n) eps, n of each matrix (set in the kernel)
   const double tol = 4.0 * 2.220446049250313e-16;
   const int max_sweeps = 40;
@@ -635,16 +681,18 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
   for (; sweep < max_sweeps; ++sweep) {
     HIP_CHECK(hipMemcpyAsync(act.p, active.data(), nmat * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(jac_clear_flags, dim3(cdiv(nmat, 256)), dim3(256), 0, s, descs, nmat);
+    hipLaunchKernelGGL(jac_clear_checks, dim3(cdiv(nmat, 256)), dim3(256), 0, s, cs, nmat);
     HIP_CHECK(hipEventRecord(e0, s));
     for (int rnd = 0; rnd < rounds; ++rnd) {
       if (JB == 16)
         hipLaunchKernelGGL(jac_gram_mfma_kernel, dim3(ntile_max, npair_max, nmat), dim3(64), 0, s, descs,
-                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
+                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max, cs);
       else
         hipLaunchKernelGGL(jac_gram_mfma32_kernel, dim3(ntile_max, npair_max, nmat), dim3(128), 0, s, descs,
-                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max);
+                           act.as<int>(), rnd, hpart.as<double2>(), npair_max, ntile_max, cs);
       hipLaunchKernelGGL(jac_inner_kernel<JB>, dim3(npair_max, nmat), dim3(JB * JB), 0, s, descs, act.as<int>(), rnd,
-                         tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max);
+                         tol, hpart.as<double2>(), jbuf.as<double2>(), rotf.as<int>(), npair_max, ntile_max, cs,
+                         sweep * rounds + rnd);
       if (JB == 16)
         hipLaunchKernelGGL(jac_apply_mfma_kernel, dim3(2 * atile_max, npair_max, nmat), dim3(64), 0, s, descs,
                            act.as<int>(), rnd, jbuf.as<double2>(), rotf.as<int>(), npair_max);
@@ -655,28 +703,31 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipMemcpyAsync(flags.data(), h[0].flag, nmat * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(checked.data(), cs.nchk, nmat * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
     st.ms += ms;
     st.launches += 3 * rounds;
-    // algorithmic work: every task reads its columns of G and forms the
-    // Hermitian Gram matrix; a task that rotated writes them back and reads
-    // and writes its columns of V, applying the c x c rotation product to both
+    // algorithmic work: every checked task (a pair not known converged) reads
+    // its columns of G and forms the Hermitian Gram matrix; a task that
+    // rotated writes them back and reads and writes its columns of V, applying
+    // the c x c rotation product to both
     bool any = false;
     int nact = 0;
-    long nrot = 0;
+    long nrot = 0, nchecked = 0;
     for (int i = 0; i < nmat; ++i) {
       if (!active[i]) continue;
+      nchecked += checked[i];
       const double n = h[i].n, c = width[i], col = n * sizeof(double2);
-      st.bytes += tasks[i] * c * col + (double)flags[i] * 3.0 * c * col;
-      st.flops += tasks[i] * 4.0 * c * (c + 1.0) * n + (double)flags[i] * 16.0 * c * c * n;
+      st.bytes += (double)checked[i] * c * col + (double)flags[i] * 3.0 * c * col;
+      st.flops += (double)checked[i] * 4.0 * c * (c + 1.0) * n + (double)flags[i] * 16.0 * c * c * n;
       if (flags[i] != 0) { any = true; ++nact; nrot += flags[i]; }
       else active[i] = 0;
     }
     if (dbg)
-      fprintf(stderr, "[jacobi] nmat %d n %d sweep %d active %d rotating tasks %ld\n", nmat, nmax, sweep,
-              nact, nrot);
+      fprintf(stderr, "[jacobi] nmat %d n %d sweep %d active %d rotating tasks %ld checked %ld\n", nmat, nmax,
+              sweep, nact, nrot, nchecked);
     if (!any) break;
   }
   (void)hipEventDestroy(e0);
