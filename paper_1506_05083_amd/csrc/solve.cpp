@@ -145,8 +145,7 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
     for (int j = 0; j < maxit && any_active; ++j) {
       const double2 *vj = V + (size_t)j * MP;
       // z = Op(v_j): v_j of wave w is at V + w*ldw + j*MP; Op works on [W][MP] so gather
-      for (int w = 0; w < W; ++w)
-        HIP_CHECK(hipMemcpyAsync(Zb + (size_t)w * MP, vj + w * ldw, MP * sizeof(double2),
+      HIP_CHECK(hipMemcpy2DAsync(Zb, MP * sizeof(double2), vj, ldw * sizeof(double2), MP * sizeof(double2), W,
                                  hipMemcpyDeviceToDevice, s));
       HIP_CHECK(hipMemcpyAsync(S.XIN.p, Zb, (size_t)W * MP * sizeof(double2), hipMemcpyDeviceToDevice, s));
       S.apply_op(S.XIN.as<double2>(), Zb);
