@@ -70,13 +70,15 @@ __device__ inline double2 near_kernel(double ddx, double ddy, double ddz, double
   return cz(cs * tt, sn * tt);
 }
 
-// With MIR (every group mirror-paired, NsumGroup::mt) a workgroup takes the
-// targets t < mt of its tile (the first half of its group) and forms the sums
-// of t and of its mirror t + mt from the same kernel values, against the
-// strengths of the sources s and s + ms (mod S) and the weights of the image
-// and of its mirror: half the kernel evaluations.  A lane past mt writes
+// With MIR (every group mirror-paired, NsumGroup::pkind) a workgroup takes
+// the primary targets of its tile (the first mt of the surface, all of the
+// first wall of a cross pair, the first half of a self-paired wall, none of a
+// wall its partner serves) and forms the sums of each and of its mirror from
+// the same kernel values, against the strengths of the sources s and s + ms
+// (mod S) and the weights of the mirror images (the partner group's, times
+// psign): half the kernel evaluations.  A lane past the primaries writes
 // nothing (its sum arrives as a mirror) unless it is a padding target, which
-// gets zero; tiles wholly past mt only write their padding zeros.
+// gets zero; tiles wholly past them only write their padding zeros.
 template <int NR, bool MIR>
 __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tgt, int ntp,
                                                    const NsumGroup *__restrict__ groups,
@@ -97,7 +99,8 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = tile * 64 + lane;
   const int tl = tile * 64 - g.t0;   // first target of the tile within its group
-  if (MIR && tl >= g.mt) {
+  const int nprim = MIR ? pair_primaries(g) : 0;
+  if (MIR && tl >= nprim) {
     for (int idx = threadIdx.x; idx < NR * 64; idx += 256) {
       const int r = idx / 64, l = idx % 64;
       if (r < nrhs && tl + l >= g.nt) out[((size_t)split * nrhs + r) * ntp + tile * 64 + l] = cz(0.0, 0.0);
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
       const int jm = groups[gi].mir[im];
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nrhs) cfma(tot2[r], wts[((size_t)gi * 9 + jm) * nrhs + r], acc2[r]);
+        if (r < nrhs) cfma(tot2[r], cscale(wts[((size_t)g.pg * 9 + jm) * nrhs + r], (double)g.psign), acc2[r]);
     }
   }
   // reduce the four waves (the target sums, then for MIR the mirror sums)
@@ -177,10 +180,16 @@ __global__ __launch_bounds__(256) void nsum_kernel(const double *__restrict__ tg
       if (r >= nrhs) continue;
       double2 v = red[(0 * NR + r) * 64 + l];
       for (int w2 = 1; w2 < 4; ++w2) v = cadd(v, red[(w2 * NR + r) * 64 + l]);
-      double2 *row = out + ((size_t)split * nrhs + r) * ntp + tile * 64;
-      if (!MIR) row[l] = v;
-      else if (tl + l < g.mt) row[l + (half ? g.mt : 0)] = v;
-      else if (!half && tl + l >= g.nt) row[l] = cz(0.0, 0.0);
+      double2 *row = out + ((size_t)split * nrhs + r) * ntp;
+      const int q = tl + l;   // group-local target
+      if (!MIR) row[tile * 64 + l] = v;
+      else if (half) {
+        if (q < nprim) row[pair_target(groups, g, q)] = v;
+      } else if (q < nprim) {
+        row[tile * 64 + l] = v;
+      } else if (q >= g.nt) {
+        row[tile * 64 + l] = cz(0.0, 0.0);
+      }
     }
   }
 }
@@ -491,7 +500,7 @@ __global__ void combine_walls_kernel(int nw, int M1sq, const double2 *__restrict
 bool plan_mirrored(const NsumPlan &plan, bool dense) {
   bool any = false, all = true;
   for (const auto &g : plan.groups) {
-    const bool p = dense ? dense_kept(g) >= 0 : (g.pkind == 1 && g.mt > 0);
+    const bool p = dense ? dense_kept(g) >= 0 : (g.pkind == 1 ? g.mt > 0 : g.pkind >= 2);
     any = any || p;
     all = all && p;
   }
