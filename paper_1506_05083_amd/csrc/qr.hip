@@ -34,6 +34,8 @@ constexpr int YT = 128;     // columns of Y per workgroup in V^H Y
 constexpr int WT = 64;      // columns per workgroup in W2 and in the update
 constexpr int UR = 64;      // rows per workgroup in the update
 constexpr int NPART = NB + 1;
+constexpr int SUB = CH / NPART;   // threads per slot summing the chunk partials
+static_assert(SUB >= 1, "a column-step workgroup sums every partial slot");
 
 // element r of Householder vector i of the panel starting at column k0
 __device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__
   double2 *pb = part + (size_t)blockIdx.y * 2 * nchmax * NPART;
   double2 *sb = side + (size_t)blockIdx.y * 2 * NB;
   __shared__ double2 fin[NPART];
-  __shared__ double2 fsum[NPART][7];
+  __shared__ double2 fsum[NPART][SUB];
   __shared__ double2 sf[NB];
   __shared__ double2 red[CH / 64][NPART];
   __shared__ double2 s_scale, s_tau, s_alpha;
@@ -80,18 +82,18 @@ __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__
     const double2 *pin = pb + (size_t)(s & 1) * nchmax * NPART;
     const double2 *srow = sb + (s & 1) * NB;
     const int nch = (mrows + CH - 1) / CH;
-    // chunk partials summed by 7 threads per slot, then across them
-    if (tid < NPART * 7) {
-      const int slot = tid / 7, sub = tid % 7;
+    // chunk partials summed by SUB threads per slot, then across them
+    if (tid < NPART * SUB) {
+      const int slot = tid / SUB, sub = tid % SUB;
       double2 t = cz(0.0, 0.0);
-      for (int ch = sub; ch < nch; ch += 7) t = cadd(t, pin[(size_t)ch * NPART + slot]);
+      for (int ch = sub; ch < nch; ch += SUB) t = cadd(t, pin[(size_t)ch * NPART + slot]);
       fsum[slot][sub] = t;
     }
     __syncthreads();
     if (tid < NPART) {
       double2 t = fsum[tid][0];
 #pragma unroll
-      for (int u = 1; u < 7; ++u) t = cadd(t, fsum[tid][u]);
+      for (int u = 1; u < SUB; ++u) t = cadd(t, fsum[tid][u]);
       fin[tid] = t;
     }
     __syncthreads();
