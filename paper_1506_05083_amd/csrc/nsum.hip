@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
 // (tiles[], those with the most images first, so that a launch ends on short
 // workgroups).
 template <int NR>
-__global__ __launch_bounds__(256) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
+__global__ __launch_bounds__(256, NR == 8 ? 4 : 2) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
                                                                      const int *__restrict__ tile_group,
                                                                      const size_t *__restrict__ koff,
                                                                      const int *__restrict__ tiles,
