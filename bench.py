@@ -72,13 +72,14 @@ def run_gpu(pr: W.Problem, steps: int, warmup: int):
     waves = [(w.theta, w.phi) for w in pr.waves]
 
     def step():
+        ts = time.perf_counter()
         op = mfs.build_operator(ctx, [mfs.BodySpec(b.M, b.N, b.P, b.q, b.k, geom)])
         op.factor_modes(1e-10)
         t0 = time.perf_counter()
         res, tm = mfs.solve_incident(ctx, op, L, waves, tol=pr.gmres_tol, maxit=pr.maxit,
                                      targets=pr.targets, q_field=pr.q_field, timing=True)
-        t_solve = time.perf_counter() - t0
-        return op.timing(), res, tm, t_solve
+        t1 = time.perf_counter()
+        return op.timing(), res, tm, t1 - t0, t1 - ts
 
     for _ in range(warmup):
         step()
@@ -240,18 +241,19 @@ def run_serving(pr: W.Problem, nreq: int, nplain: int, slots: int):
     }
 
 
-def cpu_baseline(pr: W.Problem):
+def cpu_baseline(pr: W.Problem, iters: int):
     """The oracle, as it stands, on a bounded sample of the same workload
     (10-30 s of CPU work), scaled to incident-wave solves per second with
     the operator build amortised over the batch of waves, like `value`:
       - one-body fill and per-mode SVDs of the body, in full;
-      - for one wave: the oracle's A_else point matrix on 4 of its P target
-        rings, the C point matrix on 1/8 of the T-wall rows (scaled to all
-        42 image-evaluations of the 12 wall groups), the Q fill on 1/4 of
-        its rows, the dense SVD of Q on 1/2 of its rows (scaled by the row
-        ratio: LAPACK's cost is linear in rows at fixed columns), and two
-        matrix-vector products of the oracle's dense A_else (1/8 of its
-        rows, scaled), times the GPU's GMRES iteration count."""
+      - for one wave, in full: the Q fill (q_matrix) and its equilibrated
+        truncated SVD (equilibrated_pinv_factors);
+      - for one wave, extrapolated: the oracle's A_else point matrix on 4 of
+        its P target rings (linear in rings), the C point matrix on 1/8 of
+        the T-wall rows (scaled to all 42 image-evaluations of the 12 wall
+        groups), and two matrix-vector products with a matrix of A_else's
+        size (1/8 of its rows, scaled) times the GPU's GMRES iteration
+        count `iters`."""
     import oracle.geometry as og
     import oracle.onebody as ob
     import oracle.periodic as op_
@@ -291,25 +293,19 @@ def cpu_baseline(pr: W.Problem):
     t1 = time.perf_counter()
     op_.near_matrices(b.k, Y, sub, op_.image_list(lat, ps.alpha, ps.beta, op_.NEAR9))
     t_c = (time.perf_counter() - t1) * 8 * (42.0 / 9.0)
-    # Q fill: harmonics on 1/4 of the wall nodes (S block dominates)
-    X4 = ps.walls.T[: max(1, nT // 4)]
+    # Q: the whole fill and the whole equilibrated truncated SVD
     t1 = time.perf_counter()
-    op_.harmonics(b.k, lat.p, X4)
-    t_qfill = (time.perf_counter() - t1) * 4 * 6       # 6 walls
-    nq = (lat.p + 1) ** 2 + 2 * ps.orders.m.size
-    rows = 8 * lat.M1 ** 2
-    rng = np.random.default_rng(0)
-    Qs = rng.standard_normal((rows // 2, nq)) + 1j * rng.standard_normal((rows // 2, nq))
+    Q = ps.q_matrix()
+    t_qfill = time.perf_counter() - t1
     t1 = time.perf_counter()
-    np.linalg.svd(Qs, full_matrices=False)
-    t_qsvd = (time.perf_counter() - t1) * 2
+    op_.equilibrated_pinv_factors(Q, 1e-10)
+    t_qsvd = time.perf_counter() - t1
     K = np.ones((b.P * b.M // 8, b.P * b.N), dtype=np.complex128)
     v = np.ones(b.P * b.N, dtype=np.complex128)
     t1 = time.perf_counter()
     for _ in range(2):
         K @ v
     t_mv = (time.perf_counter() - t1) / 2 * 8
-    iters = 15
     t_wave = t_aelse + t_c + t_qfill + t_qsvd + iters * t_mv
     nw = len(pr.waves)
     t_step = t_build + nw * t_wave
@@ -318,17 +314,17 @@ def cpu_baseline(pr: W.Problem):
         "value": nw / t_step, "unit": "solves/s", "cores": cores, "kind": "oracle",
         "sample": (f"oracle (numpy/scipy, {cores} threads) on the same workload: one-body fill + per-mode "
                    f"SVDs in full ({t_build:.1f} s); per wave, extrapolated from fractions: A_else "
-                   f"assembly {t_aelse:.0f} s ({RINGS}/{b.P} of rows), C {t_c:.0f} s (1/8 of a wall), Q fill "
-                   f"{t_qfill:.0f} s (1/4), Q SVD {t_qsvd:.1f} s (1/2 of rows), {iters} GMRES products "
-                   f"{iters * t_mv:.1f} s; {sample_s:.0f} s of CPU work measured"),
+                   f"assembly {t_aelse:.0f} s ({RINGS}/{b.P} of rows), C {t_c:.0f} s (1/8 of a wall); in full: "
+                   f"Q fill {t_qfill:.1f} s, Q SVD {t_qsvd:.1f} s ({Q.shape[0]} x {Q.shape[1]}); {iters} GMRES "
+                   f"products {iters * t_mv:.1f} s; {sample_s:.0f} s of CPU work measured"),
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-obstacles", type=int, default=256,
                     help="obstacles of the batched-build measurement (0 skips it)")
@@ -337,12 +333,17 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device to device (the reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["batch", "large", "large-transmission"],
+    ap.add_argument("--only", choices=["batch", "large", "large-transmission", "serve"],
                     help="run one other configuration's measurement alone and print its JSON line")
-    ap.add_argument("--large-waves", type=int, default=8)
+    ap.add_argument("--large-waves", type=int, default=8,
+                    help="incidences of the large-cup measurement (0 skips it)")
     args = ap.parse_args()
     if args.only == "batch":
         print(json.dumps(run_batch_build(args.batch_obstacles)))
+        return
+    if args.only == "serve":
+        print(json.dumps(run_serving(W.periodic_k10(1), args.serve_requests, min(8, args.serve_requests),
+                                     args.serve_slots)))
         return
     if args.only in ("large", "large-transmission"):
         print(json.dumps(run_large(args.large_waves, args.only == "large-transmission")))
@@ -380,18 +381,22 @@ def main():
     pairs = nsum_pairs(pr)                # one batched launch serves all waves
     pairs_per_s = pairs / (nsum_avg * 1e-3)
     near_bytes = float(np.median([t["near_bytes"] for t in tms]))
+    near_alg = float(np.median([t["near_alg_bytes"] for t in tms]))
+    near_modes = sorted({int(t["near_mode"]) for t in tms})
     nsum_share = float(np.median([t["nsum_avg"] * t["nsum_launches"] for t in tms])) / ms_step
     if near_bytes > 0:
-        # stored near field: every launch streams the kernel values once
-        # (plus the strengths and outputs, under 0.1% of them)
-        gbs = near_bytes / (nsum_avg * 1e-3) / 1e9
+        # stored near field: every launch streams the kernel values the
+        # method needs once (the padding of the last 64-target tile of each
+        # group is not counted; strengths and outputs are under 0.1%)
+        gbs = near_alg / (nsum_avg * 1e-3) / 1e9
         traffic = measured_traffic("nsum.hip", "nsum_dense_periodic_k10_traffic.txt")
         roof_nsum = {"bound": "hbm", "kernel": "nsum_dense_mirror_mfma_kernel<8> (A_else surface sums and C wall "
                                                "sums from the mirror-paired stored near field on the matrix cores; "
                                                "all waves, mean over launches)",
                      "achieved": gbs, "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs / PEAK_HBM,
                      "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "launch_ms": nsum_avg, "bytes_per_launch": near_bytes,
+                     "launch_ms": nsum_avg, "bytes_per_launch": near_alg,
+                     "stored_bytes_per_launch": near_bytes,
                      "fill_ms": float(np.median([t["near_fill_ms"] for t in tms])), "share_of_step": nsum_share}
     else:
         # algorithmic FP64 work of one (target, source, image) pair: distance and
@@ -437,15 +442,19 @@ def main():
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "periodic_k10: unit lattice, k=10, r=0.3(1+0.1cos3t), N=200, M=240, "
-                               "P=64, q=400, p=36, N0=14, M1=30, 8 seeded incidences, GMRES 1e-10"},
+        "config": {"workload": f"periodic_k10: unit lattice, k=10, r=0.3(1+0.1cos3t), N={b.N}, M={b.M}, "
+                               f"P={b.P}, q={b.q}, tau={b.tau}, z0={pr.lattice.z0}, p={pr.lattice.p}, "
+                               f"N0={pr.lattice.N0:g}, M1={pr.lattice.M1}, {nw} seeded incidences, "
+                               f"GMRES {pr.gmres_tol:g}"},
         "fill_qr_tflops": flops / ((np.median(fill_ms) + np.median(qr_ms)) * 1e-3) / 1e12,
         "fill_ms": float(np.median(fill_ms)), "qr_ms": float(np.median(qr_ms)),
         "trunc_ms": float(np.median(svd_ms)),
         "solve_ms": float(np.median(solve_ms)),
         "solve_only_solves_per_s": nw / (np.median(solve_ms) * 1e-3),
-        "latency_p50_ms": float(np.percentile(solve_ms, 50)),
-        "latency_p99_ms": float(np.percentile(solve_ms, 99)),
+        "batch_solve_ms_p50": float(np.percentile(solve_ms, 50)),
+        "batch_solve_ms_p99": float(np.percentile(solve_ms, 99)),
+        "step_ms_max": float(max(1e3 * r[4] for r in recs)),
+        "near_field": {0: "on the fly (budget 0)", 1: "stored", 2: "on the fly (did not fit)"}[near_modes[-1]],
         "stage_ms": {k: float(np.median([t[k] for t in tms])) for k in ("rhs", "periodizer", "gmres", "recover")},
         "gmres_iters": [r.iters for r in res],
         "eps_flux_max": float(max(r.eps_flux for r in res)),
@@ -455,10 +464,18 @@ def main():
     if args.batch_obstacles > 0:
         line["batch_build"] = run_batch_build(args.batch_obstacles)
     if args.serve_requests > 0:
-        line["serving"] = run_serving(W.periodic_k10(1), args.serve_requests, min(8, args.serve_requests),
-                                      args.serve_slots)
+        sv = run_serving(W.periodic_k10(1), args.serve_requests, min(8, args.serve_requests), args.serve_slots)
+        line["serving"] = sv
+        # the metric's p50/p99: request latency (completion - arrival) of the
+        # Poisson stream at 0.8 of the saturated served rate
+        line["latency_p50_ms"] = sv["poisson_latency_p50_ms"]
+        line["latency_p99_ms"] = sv["poisson_latency_p99_ms"]
+        line["latency_source"] = (f"serving: {sv['requests']} requests of the seeded stream, Poisson arrivals at "
+                                  f"{sv['poisson_rate_per_s']:.1f}/s (0.8 of the saturated served rate)")
+    if args.large_waves > 0:
+        line["large"] = run_large(args.large_waves, False)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pr)
+        line["cpu_baseline"] = cpu_baseline(pr, int(round(np.mean([r.iters for r in res]))))
     print(json.dumps(line))
 
 

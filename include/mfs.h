@@ -38,7 +38,8 @@ typedef enum {
   MFS_EINVAL = 1,   /* bad argument; nothing was written                     */
   MFS_ENOMEM = 2,   /* device or host allocation failed                       */
   MFS_EDEVICE = 3,  /* a HIP call failed                                      */
-  MFS_ENOTCONV = 4, /* GMRES hit maxit; results hold the last iterate         */
+  MFS_ENOTCONV = 4, /* GMRES hit maxit, or a Jacobi SVD its sweep cap;
+                       results hold the last iterate                         */
   MFS_ESTATE = 5,   /* call out of order (e.g. apply before factor)          */
   MFS_EBUSY = 6
 } mfs_status;
@@ -150,6 +151,11 @@ typedef struct {
   double near_fill_ms;    /* filling the dense near field (0 if on the fly)  */
   double near_bytes;      /* mean dense near-field bytes streamed by one of
                              those launches (0 if evaluated on the fly)       */
+  double near_alg_bytes;  /* the same without the padding of the last 64-target
+                             tile of each group: the values the method needs */
+  int32_t near_mode;      /* 0: sums evaluated on the fly (budget 0); 1: stored
+                             near field; 2: on the fly because the stored field
+                             did not fit the budget or the free device memory */
 } mfs_solve_timing;
 
 const char *mfs_last_error(void);
@@ -158,6 +164,23 @@ const char *mfs_version(void);
 /* Create a context on HIP device `device`.  Allocates nothing large. */
 mfs_status mfs_create(int device, mfs_ctx **out);
 void mfs_destroy(mfs_ctx *ctx);
+
+/* Device memory of the library.  Every device buffer of 1 MiB or more that
+ * the library allocates comes from a per-device cache: a released buffer is
+ * kept (after the device has finished the work queued before its release)
+ * and handed to the next request of about its size, so repeated solves do
+ * not return tens of GB to the driver and ask for them again.  At most half
+ * of the device's memory is kept idle; a failed allocation first frees the
+ * idle blocks and retries.
+ *   mfs_memory_stats: bytes held by live library buffers (in_use), their
+ *     largest value since the last mfs_memory_reset_peak (peak), and idle
+ *     cached bytes (cached); any pointer may be NULL.
+ *   mfs_release_cached_memory: return the idle cached blocks to the driver
+ *     (for a caller that needs the memory for something else).
+ * EINVAL for a device that does not exist. */
+mfs_status mfs_memory_stats(int device, uint64_t *in_use, uint64_t *peak, uint64_t *cached);
+mfs_status mfs_memory_reset_peak(int device);
+mfs_status mfs_release_cached_memory(int device);
 
 /* Host helper: geometry of a polar body, written into caller arrays
  * rho, z, nrho, nz [spec->M] and srho, sz [spec->N] (Sec. 3, Sec. 3.2). */
@@ -199,7 +222,11 @@ mfs_status mfs_op_blocks(const mfs_op *op, int32_t body, mfs_c128 *out, void *st
  * mfs_solve_incident) uses 32-column blocks once a batch's widest factor
  * has 2048 columns, 16-column blocks below; the environment variable
  * MFS_JACOBI_WIDE_MIN_COLS, read at every factorisation, moves that width
- * (a test of the wide path on small matrices sets it to 0). */
+ * (a test of the wide path on small matrices sets it to 0).  The Jacobi
+ * stops after 40 sweeps (MFS_JACOBI_MAX_SWEEPS, read at every
+ * factorisation, lowers the cap); if some block still rotates then, the
+ * factors of the last sweep are kept and ENOTCONV is returned.  ESTATE if
+ * the operator is already factored. */
 mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks);
 
 /* Stage times of the operator, milliseconds, measured with HIP events on the
@@ -212,11 +239,35 @@ mfs_status mfs_op_timing(const mfs_op *op, double *ms);
  * mfs_factor_modes. */
 mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out);
 
-/* (c) Solution-operator apply: c_n = A'_n^+ x_n for every mode of nrhs
- * right-hand sides.  in: dev [nrhs][P][M] mode coefficients (FFT bin order);
- * out: dev [nrhs][P][N].  ESTATE before mfs_factor_modes. */
+/* Layouts of mfs_apply_solution_op. */
+enum {
+  MFS_LAYOUT_MODES = 0,  /* in: [nrhs][P][M] mode coefficients (FFT bin order);
+                            out: [nrhs][P][N] mode coefficients c_n           */
+  MFS_LAYOUT_ANGLE = 1,  /* in only: [nrhs][M][P] samples f(rho_m, phi_l, z_m)
+                            at the P angles phi_l = 2 pi l / P (l contiguous) */
+  MFS_LAYOUT_POINTS = 2  /* out only: [nrhs][P][N] point strengths
+                            sigma_jl = (1/P) sum_n c_nj e^{+i n phi_l} of the
+                            sources at the P angles (the sigma input of
+                            mfs_neighbour_sum with qs = P)                  */
+};
+
+/* (c) Solution-operator apply (Sec. 3 eq. (linsys) and Sec. 4.2): for every
+ * mode, c_n = A'_n^+ f_n with the truncated factors of mfs_factor_modes.
+ * With in_layout ANGLE the library first takes the angle DFT
+ * f_n = (1/P) sum_l f(phi_l) e^{-i n phi_l} (eq. (fhatquad), q = P); with
+ * out_layout POINTS it returns the point strengths of the P-angle source
+ * rings (the point-source form of Sec. 4.1) instead of the modes.  For a
+ * transmission body M and N read 2M and 2N in the MODES and ANGLE layouts
+ * (rows [values; normal derivatives], columns [exterior; interior]), while
+ * POINTS holds the exterior sources' strengths, [nrhs][P][N].
+ * in, out: dev, caller-owned, on the context's device.  An ANGLE input or a
+ * POINTS output needs an intermediate [nrhs][P][M] or [nrhs][P][N] buffer,
+ * taken from the library's device cache; the per-mode work buffer belongs to
+ * the operator.  Asynchronous on `stream`.  ESTATE before mfs_factor_modes;
+ * EINVAL for an unknown layout (nothing written). */
 mfs_status mfs_apply_solution_op(const mfs_op *op, int32_t body, int32_t nrhs,
-                                 const mfs_c128 *in, mfs_c128 *out, void *stream);
+                                 const mfs_c128 *in, int32_t in_layout,
+                                 mfs_c128 *out, int32_t out_layout, void *stream);
 
 /* Right-hand side of eq. (linsys): f = -du^i/dn at the P x M surface points
  * then f_hat_n = (1/P) sum_l f(phi_l) e^{-i n phi_l} (eq. (fhatquad), q = P).
@@ -291,14 +342,21 @@ mfs_status mfs_field_interior(const mfs_op *op, int32_t body, int32_t nrhs, int3
 mfs_status mfs_set_near_field_budget(mfs_op *op, uint64_t max_bytes);
 
 /* (c) Periodic solve for nwaves incident waves (Sec. 4.2): per wave, fill and
- * factor Q = [S, -W] (SVD truncated at rel_cutoff relative), then GMRES on
+ * factor Q = [S, -W], then GMRES on
  * eq. (iter) (I + A_else A_0^+ - B Q^+ C A_0^+) eta~ = f_hat, unrestarted from
  * zero, CGS2 orthogonalisation, stopping at ||r|| <= tol ||f_hat||;
  * eta = A_0^+ eta~, xi = -Q^+ C eta; the Bragg amplitudes a, b; the field
  * u at the host targets [ntargets][3] from eq. (urep) with q_field-node
- * point sources; eps_flux.  Blocking.  Returns ENOTCONV if some wave hit
- * maxit (its result holds the last iterate), EINVAL if a result's
- * cap_orders is too small (norders is set so the caller can retry).
+ * point sources; eps_flux.  Blocking.
+ * Q^+: the truncated SVD pseudoinverse (singular values below rel_cutoff
+ * times the largest dropped) of Q with its columns scaled to unit norm, the
+ * scaling folded back into the factors (Q^+ = D (Q D)^+).  When
+ * ||R||_F ||R^{-1}||_F < 1/rel_cutoff for the triangle R of the QR of Q D,
+ * no singular value can fall below the cutoff and Q^+ = D R^{-1} Q_1^*
+ * is formed without the SVD.
+ * Returns ENOTCONV if some wave hit maxit or its Q's Jacobi SVD its sweep
+ * cap (the results hold the last iterate), EINVAL if a result's cap_orders
+ * is too small (norders is set so the caller can retry).
  * timing (optional) receives stage times.  With the environment variable
  * MFS_PROGRESS set, the stages and every fifth GMRES iteration are reported
  * on stderr. */

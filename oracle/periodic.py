@@ -157,6 +157,21 @@ def image_list(lat: Lattice, alpha: complex, beta: complex, which):
     return [((a, b), alpha ** a * beta ** b, a * lat.ex * E1 + b * lat.ey * E2) for a, b in which]
 
 
+def equilibrated_pinv_factors(Q: np.ndarray, cut: float):
+    """Factors of Q's truncated pseudoinverse (Sec. 4.2: SVD, singular values
+    below `cut` times the largest dropped), taken of Q with every column
+    scaled to unit 2-norm.  The paper leaves the normalisation of the
+    auxiliary basis open; with orthonormal Y_lm the columns of the high
+    degrees are smaller than the low ones by more than the cutoff, so an
+    unscaled relative cutoff would discard them whatever their use.  With
+    Q D = U S V^* (D = diag(1/||q_j||)) the pseudoinverse is D V S^+ U^*;
+    returned as (U_k, s_k, V_k^* D) for apply_qpinv."""
+    dinv = 1.0 / np.linalg.norm(Q, axis=0)
+    U, s, Vh = np.linalg.svd(Q * dinv[None, :], full_matrices=False)
+    keep = s > cut * s[0]
+    return U[:, keep], s[keep], Vh[keep] * dinv[None, :]
+
+
 NEAR9 = [(a, b) for a in (-1, 0, 1) for b in (-1, 0, 1)]
 ELSE8 = [ab for ab in NEAR9 if ab != (0, 0)]
 
@@ -200,9 +215,7 @@ class PeriodicSolver:
         self.Kelse = self.aelse_point_matrix()
         self.Cpt = self.c_point_matrix(cancel=True)
         self.Q = self.q_matrix()
-        U, s, Vh = np.linalg.svd(self.Q, full_matrices=False)
-        keep = s > self.cut * s[0]
-        self.Qf = (U[:, keep], s[keep], Vh[keep])
+        self.Qf = equilibrated_pinv_factors(self.Q, self.cut)
 
     def aelse_point_matrix(self) -> np.ndarray:
         """K_else[(l', m), (l, j)] = sum over the 8 non-central images of

@@ -21,6 +21,7 @@ _lib = None
 
 MFS_OK, MFS_EINVAL, MFS_ENOMEM, MFS_EDEVICE, MFS_ENOTCONV, MFS_ESTATE, MFS_EBUSY = range(7)
 TARGETS_SURFACE, TARGETS_WALLS, TARGETS_USER = 0, 1, 2
+LAYOUT_MODES, LAYOUT_ANGLE, LAYOUT_POINTS = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -78,7 +79,7 @@ class SolveTiming(C.Structure):
                 ("nsum_launches", C.c_int32), ("jacobi_ms", C.c_double),
                 ("jacobi_launches", C.c_int32), ("jacobi_bytes", C.c_double),
                 ("jacobi_flops", C.c_double), ("near_fill_ms", C.c_double),
-                ("near_bytes", C.c_double)]
+                ("near_bytes", C.c_double), ("near_alg_bytes", C.c_double), ("near_mode", C.c_int32)]
 
 
 _SIGS = {
@@ -86,6 +87,10 @@ _SIGS = {
     "mfs_version": (C.c_char_p, []),
     "mfs_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "mfs_destroy": (None, [C.c_void_p]),
+    "mfs_memory_stats": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                   C.POINTER(C.c_uint64)]),
+    "mfs_memory_reset_peak": (C.c_int, [C.c_int]),
+    "mfs_release_cached_memory": (C.c_int, [C.c_int]),
     "mfs_polar_geometry": (C.c_int, [C.POINTER(PolarSpec), _dp, _dp, _dp, _dp, _dp, _dp]),
     "mfs_cup_geometry": (C.c_int, [C.POINTER(CupSpec), _dp, _dp, _dp, _dp, _dp, _dp]),
     "mfs_build_operator": (C.c_int, [C.c_void_p, C.POINTER(Body), C.c_int32, C.c_void_p,
@@ -96,8 +101,8 @@ _SIGS = {
     "mfs_op_singular_values": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "mfs_op_timing": (C.c_int, [C.c_void_p, _dp]),
     "mfs_set_near_field_budget": (C.c_int, [C.c_void_p, C.c_uint64]),
-    "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
-                                        C.c_void_p]),
+    "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                        C.c_void_p, C.c_int32, C.c_void_p]),
     "mfs_rhs_modes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_void_p, C.c_void_p]),
     "mfs_point_strengths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
@@ -217,6 +222,23 @@ def create(device: int = 0) -> Context:
     return Context(device)
 
 
+def memory_stats(device: int = 0) -> dict:
+    """Bytes held by the library's live device buffers, their peak since
+    reset_memory_peak(), and idle bytes in the library's device cache."""
+    a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(lib().mfs_memory_stats(device, C.byref(a), C.byref(b), C.byref(c)))
+    return {"in_use": a.value, "peak": b.value, "cached": c.value}
+
+
+def reset_memory_peak(device: int = 0) -> None:
+    _check(lib().mfs_memory_reset_peak(device))
+
+
+def release_cached_memory(device: int = 0) -> None:
+    """Return the idle blocks of the library's device cache to the driver."""
+    _check(lib().mfs_release_cached_memory(device))
+
+
 @dataclass
 class BodySpec:
     """km = 0: sound-hard; km > 0: transmission, geom then also holds the
@@ -307,13 +329,17 @@ def factor_modes(op: Operator, rel_cutoff: float = 1e-10):
     return op.factor_modes(rel_cutoff)
 
 
-def apply_solution_op(op: Operator, x, body: int = 0):
-    """c = A'^+ x per mode; x: cuda complex128 [nrhs][P][M] -> [nrhs][P][N]."""
+def apply_solution_op(op: Operator, x, body: int = 0, in_layout: int = 0, out_layout: int = 0):
+    """c = A'^+ x per mode.  x: cuda complex128 [nrhs][P][M] modes (in_layout
+    LAYOUT_MODES) or [nrhs][M][P] angle samples (LAYOUT_ANGLE); returns
+    [nrhs][P][N] modes (LAYOUT_MODES) or point strengths (LAYOUT_POINTS)."""
     import torch
     b = op.bodies[body]
     x = x.contiguous()
-    out = torch.empty((x.shape[0], b.P, b.cols), dtype=torch.complex128, device=x.device)
-    _check(lib().mfs_apply_solution_op(op.h, body, x.shape[0], _dev(x), _dev(out), _stream()))
+    ncol = b.cols if out_layout == LAYOUT_MODES else b.N
+    out = torch.empty((x.shape[0], b.P, ncol), dtype=torch.complex128, device=x.device)
+    _check(lib().mfs_apply_solution_op(op.h, body, x.shape[0], _dev(x), in_layout, _dev(out), out_layout,
+                                       _stream()))
     return out
 
 

@@ -31,21 +31,6 @@ void progress(const char *fmt, ...) {
   std::fflush(stderr);
 }
 
-void DevBuf::alloc(size_t n) {
-  release();
-  if (n == 0) return;
-  if (hipMalloc(&p, n) != hipSuccess) {
-    p = nullptr;
-    throw Error{MFS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
-  }
-  bytes = n;
-}
-void DevBuf::release() {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-  bytes = 0;
-}
-
 static bool finite_all(const double *p, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -346,6 +331,37 @@ mfs_status mfs_create(int device, mfs_ctx **out) {
 
 void mfs_destroy(mfs_ctx *ctx) { delete ctx; }
 
+mfs_status mfs_memory_stats(int device, uint64_t *in_use, uint64_t *peak, uint64_t *cached) {
+  MFS_API_BEGIN
+  int n = 0;
+  HIP_CHECK(hipGetDeviceCount(&n));
+  MFS_REQUIRE(device >= 0 && device < n, "no such HIP device");
+  size_t a = 0, b = 0, c = 0;
+  pool_stats(device, &a, &b, &c);
+  if (in_use) *in_use = a;
+  if (peak) *peak = b;
+  if (cached) *cached = c;
+  MFS_API_END
+}
+
+mfs_status mfs_memory_reset_peak(int device) {
+  MFS_API_BEGIN
+  int n = 0;
+  HIP_CHECK(hipGetDeviceCount(&n));
+  MFS_REQUIRE(device >= 0 && device < n, "no such HIP device");
+  pool_reset_peak(device);
+  MFS_API_END
+}
+
+mfs_status mfs_release_cached_memory(int device) {
+  MFS_API_BEGIN
+  int n = 0;
+  HIP_CHECK(hipGetDeviceCount(&n));
+  MFS_REQUIRE(device >= 0 && device < n, "no such HIP device");
+  pool_trim(device);
+  MFS_API_END
+}
+
 mfs_status mfs_polar_geometry(const mfs_polar_spec *spec, double *rho, double *z, double *nrho,
                               double *nz, double *srho, double *sz) {
   MFS_API_BEGIN
@@ -478,8 +494,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
     }
   }
   std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.m.n > y.m.n; });
-  size_t fr = 0, tot = 0;
-  HIP_CHECK(hipMemGetInfo(&fr, &tot));
+  const size_t fr = device_free_bytes();
   const double budget = std::max(0.45 * (double)fr, (double)(1ull << 30));
   for (int i = 0; i < 3; ++i)
     if (!op->ev[i]) HIP_CHECK(hipEventCreate(&op->ev[i]));
@@ -490,6 +505,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   }
   op->gps.clear();
   op->ms_qr = op->ms_svd = 0.0;
+  int unconverged = 0;
   size_t c0 = 0;
   while (c0 < items.size()) {
     size_t c1 = c0 + 1;
@@ -522,6 +538,7 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
       std::copy(sv.begin() + (i - c0) * ldo, sv.begin() + (i - c0) * ldo + std::min(ldo, b.cols),
                 b.h_sv.begin() + (size_t)it.d * b.cols);
     }
+    unconverged += g->jacobi_unconverged;
     g->release_work();
     op->gps.push_back(std::move(g));
     c0 = c1;
@@ -539,6 +556,11 @@ mfs_status mfs_factor_modes(mfs_op *op, double rel_cutoff, int32_t *ranks) {
   for (auto &bp : op->bodies) bp->blocks.release();
   op->factored = true;
   op->cutoff = rel_cutoff;
+  if (unconverged > 0) {
+    set_error("mfs_factor_modes: the Jacobi SVD of " + std::to_string(unconverged) +
+              " block(s) reached its sweep cap; their factors are those of the last sweep");
+    return MFS_ENOTCONV;
+  }
   MFS_API_END
 }
 
@@ -568,13 +590,19 @@ mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out) {
 }
 
 mfs_status mfs_apply_solution_op(const mfs_op *op, int32_t body, int32_t nrhs, const mfs_c128 *in,
-                                 mfs_c128 *out, void *stream) {
+                                 int32_t in_layout, mfs_c128 *out, int32_t out_layout, void *stream) {
   MFS_API_BEGIN
   BodyData &b = body_of(op, body);
-  if (!op->factored) MFS_THROW(MFS_ESTATE, "mfs_factor_modes has not run");
-  MFS_REQUIRE(nrhs >= 0 && (nrhs == 0 || (in && out)), "bad arguments");
+  check_apply_args(op, nrhs, in, in_layout, out, out_layout);
+  if (nrhs == 0) return MFS_OK;
+  HIP_CHECK(hipSetDevice(op->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  apply_pinv_body(op, b, nrhs, reinterpret_cast<const double2 *>(in), reinterpret_cast<double2 *>(out), s);
+  DevBuf im, om;
+  if (in_layout == MFS_LAYOUT_ANGLE) im.alloc((size_t)nrhs * b.P * b.rows * sizeof(double2));
+  if (out_layout == MFS_LAYOUT_POINTS) om.alloc((size_t)nrhs * b.P * b.cols * sizeof(double2));
+  apply_solution_layouts(op, b, nrhs, reinterpret_cast<const double2 *>(in), in_layout,
+                         reinterpret_cast<double2 *>(out), out_layout, im.as<double2>(), om.as<double2>(), nullptr,
+                         s);
   MFS_API_END
 }
 

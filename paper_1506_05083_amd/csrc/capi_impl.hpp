@@ -49,9 +49,21 @@ void image_weights(const std::vector<std::complex<double>> &al, const std::vecto
                    const NsumPlan &plan, std::vector<double2> &w);
 BodyData &body_of(const mfs_op *op, int body);
 double2 *op_workspace(const mfs_op *op, size_t bytes);
-// c = A0^+ x for nrhs right-hand sides in mode layout (chunks of 16)
+// c = A0^+ x for nrhs right-hand sides in mode layout (chunks of 16); yw is
+// a work buffer of apply_pinv_work_bytes(b) bytes (null: the operator's own)
 void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double2 *x, double2 *out,
-                     hipStream_t s);
+                     hipStream_t s, double2 *yw = nullptr);
+size_t apply_pinv_work_bytes(const BodyData &b);
+// The solution-operator apply with its input and output layouts (MFS_LAYOUT_*):
+// an ANGLE input goes through the forward angle DFT into in_modes
+// ([nrhs][P][rows]), a POINTS output is formed from out_modes
+// ([nrhs][P][cols]) by the inverse DFT; yw as for apply_pinv_body.  The
+// buffers are the caller's (the library's cache, or the no-allocation entry
+// point's static scratch).
+void apply_solution_layouts(const mfs_op *op, const BodyData &b, int nrhs, const double2 *in, int in_layout,
+                            double2 *out, int out_layout, double2 *in_modes, double2 *out_modes, double2 *yw,
+                            hipStream_t s);
+void check_apply_args(const mfs_op *op, int nrhs, const void *in, int in_layout, const void *out, int out_layout);
 void launch_zero(double2 *p, long n, hipStream_t s);
 void launch_scale(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd,
                   const double *sdev, hipStream_t s);

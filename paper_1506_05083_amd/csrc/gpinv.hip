@@ -40,6 +40,7 @@
 namespace mfs {
 
 void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s);
+void launch_zero(double2 *p, long n, hipStream_t s);
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,
               std::vector<int> &ranks);
 
@@ -57,14 +58,15 @@ __global__ __launch_bounds__(256) void colnorm_kernel(const MatDesc *__restrict_
   if (lane == 0) out[(size_t)blockIdx.y * ld + c] = sqrt(s);
 }
 
-// dst column i = src column perm[i]
+// dst column i = src column perm[i], times scale[perm[i]] when scale is given
 __global__ void gather_kernel(const MatDesc *__restrict__ src, const MatDesc *__restrict__ dst,
-                              const int *__restrict__ perm, int ldp) {
+                              const int *__restrict__ perm, int ldp, const double *__restrict__ scale) {
   const MatDesc s = src[blockIdx.y], d = dst[blockIdx.y];
   const int i = blockIdx.x;
   if (i >= d.n) return;
   const int c = perm[(size_t)blockIdx.y * ldp + i];
-  for (int r = threadIdx.x; r < d.m; r += blockDim.x) d.a[(size_t)i * d.lda + r] = s.a[(size_t)c * s.lda + r];
+  const double f = scale ? scale[(size_t)blockIdx.y * ldp + c] : 1.0;
+  for (int r = threadIdx.x; r < d.m; r += blockDim.x) d.a[(size_t)i * d.lda + r] = cscale(s.a[(size_t)c * s.lda + r], f);
 }
 
 // squared norms of the rows of R = triu(a[0:n, 0:n])
@@ -125,7 +127,8 @@ __global__ void prep_uv_kernel(const MatDesc *__restrict__ qd, const MatDesc *__
 
 // W[perm[i], k] = l.u[i, k] (rows of dropped columns stay zero)
 __global__ void scatter_w_kernel(const MatDesc *__restrict__ ld, const MatDesc *__restrict__ fd,
-                                 const int *__restrict__ perm, const int *__restrict__ piv, int ldp) {
+                                 const int *__restrict__ perm, const int *__restrict__ piv, int ldp,
+                                 const double *__restrict__ scale) {
   const MatDesc l = ld[blockIdx.y], f = fd[blockIdx.y];
   const int k = blockIdx.x;
   const int kept = l.rank[0];
@@ -136,7 +139,11 @@ __global__ void scatter_w_kernel(const MatDesc *__restrict__ ld, const MatDesc *
   const double2 *src = l.u + (size_t)k * l.lda;
   const int *pw = perm + (size_t)blockIdx.y * ldp;
   const int *vw = piv + (size_t)blockIdx.y * ldp;
-  for (int i = threadIdx.x; i < l.m; i += blockDim.x) w[pw[vw[i]]] = src[i];
+  const double *sw = scale ? scale + (size_t)blockIdx.y * ldp : nullptr;
+  for (int i = threadIdx.x; i < l.m; i += blockDim.x) {
+    const int c = pw[vw[i]];
+    w[c] = sw ? cscale(src[i], sw[c]) : src[i];
+  }
 }
 
 // out[w][i] = singular value i of matrix w (zero past its n), ld entries per matrix
@@ -303,6 +310,158 @@ __global__ __launch_bounds__(256) void build_t_kernel(const MatDesc *__restrict_
   }
 }
 
+
+// ------------------------------------------------ inverse of the triangle
+// X = R^{-1} for the n x n upper triangle R of a QR'd matrix, in TI x TI
+// blocks: the diagonal blocks first (trinv_diag_kernel), then the blocks at
+// block distance d = 1, 2, ... from the diagonal (trinv_off_kernel), each
+// from X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj, whose X_kj lie nearer the
+// diagonal and are already formed.  X must be zero below the diagonal.
+constexpr int TI = 64;
+constexpr int TK = 16;   // inner-dimension chunk staged in LDS
+
+__device__ inline double2 crecip(double2 a) {
+  const double d = 1.0 / cabs2(a);
+  return cz(a.x * d, -a.y * d);
+}
+
+// one workgroup (TI threads) per (diagonal block, matrix); thread t solves
+// R_jj x = e_t by back substitution
+__global__ __launch_bounds__(TI) void trinv_diag_kernel(const MatDesc *__restrict__ rd,
+                                                        const MatDesc *__restrict__ xd) {
+  const MatDesc r = rd[blockIdx.y], x = xd[blockIdx.y];
+  const int n = x.n;
+  const int j0 = blockIdx.x * TI;
+  if (j0 >= n) return;
+  const int nb = min(TI, n - j0);
+  __shared__ double2 Rs[TI][TI + 1];   // [column][row]
+  __shared__ double2 Xs[TI][TI + 1];   // [column][row]
+  const int t = threadIdx.x;
+  for (int c = 0; c < nb; ++c)
+    Rs[c][t] = (t <= c) ? r.a[(size_t)(j0 + c) * r.lda + j0 + t] : cz(0.0, 0.0);
+  __syncthreads();
+  if (t < nb) {
+    for (int i = 0; i < TI; ++i) Xs[t][i] = cz(0.0, 0.0);
+    Xs[t][t] = crecip(Rs[t][t]);
+    for (int i = t - 1; i >= 0; --i) {
+      double2 acc = cz(0.0, 0.0);
+      for (int k = i + 1; k <= t; ++k) cfma(acc, Rs[k][i], Xs[t][k]);
+      Xs[t][i] = cmul(cz(-acc.x, -acc.y), crecip(Rs[i][i]));
+    }
+  }
+  __syncthreads();
+  if (t < nb)
+    for (int c = 0; c < nb; ++c) x.a[(size_t)(j0 + c) * x.lda + j0 + t] = Xs[c][t];
+}
+
+// blocks (i, i + d) of every matrix: workgroup (i, matrix), 256 threads, a
+// 4 x 4 tile of the 64 x 64 block per thread (rows ty + 16 a, columns
+// tx + 16 b)
+__global__ __launch_bounds__(256) void trinv_off_kernel(const MatDesc *__restrict__ rd,
+                                                        const MatDesc *__restrict__ xd, int d) {
+  const MatDesc r = rd[blockIdx.y], x = xd[blockIdx.y];
+  const int n = x.n;
+  const int i0 = blockIdx.x * TI, j0 = (blockIdx.x + d) * TI;
+  if (j0 >= n) return;
+  const int ni = TI, nj = min(TI, n - j0);   // row block i is whole (it precedes j)
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ double2 As[TK][TI];
+  __shared__ double2 Bs[TK][TI];
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
+  // T = sum_k R[i rows, k] X[k, j cols] over k in [i0 + TI, j0 + nj)
+  const int kend = j0 + nj;
+  for (int k0 = i0 + TI; k0 < kend; k0 += TK) {
+    for (int e = tid; e < TK * TI; e += 256) {
+      const int kk = e / TI, q = e % TI;
+      const int k = k0 + kk;
+      As[kk][q] = (k < kend) ? r.a[(size_t)k * r.lda + i0 + q] : cz(0.0, 0.0);
+      Bs[kk][q] = (k < kend && q < nj) ? x.a[(size_t)(j0 + q) * x.lda + k] : cz(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
+  }
+  // X_ij = -X_ii T: T through LDS, X_ii in chunks of TK columns
+  __shared__ double2 Ts[TI][TI + 1];   // [row][column]
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Ts[ty + 16 * a][tx + 16 * b] = acc[a][b];
+  __syncthreads();
+  double2 out[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) out[a][b] = cz(0.0, 0.0);
+  for (int k0 = 0; k0 < ni; k0 += TK) {
+    for (int e = tid; e < TK * TI; e += 256) {
+      const int kk = e / TI, q = e % TI;
+      As[kk][q] = x.a[(size_t)(i0 + k0 + kk) * x.lda + i0 + q];   // X_ii[q][k0 + kk]
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Ts[k0 + kk][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cfma(out[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = tx + 16 * b;
+      if (col < nj) x.a[(size_t)(j0 + col) * x.lda + i0 + ty + 16 * a] = cz(-out[a][b].x, -out[a][b].y);
+    }
+}
+
+// out[w][j] = (sum_{i<=j} |R_ij|^2, sum_{i<=j} |X_ij|^2): one wave per column
+__global__ __launch_bounds__(256) void trinv_norm_kernel(const MatDesc *__restrict__ rd,
+                                                         const MatDesc *__restrict__ xd, double2 *out, int ld) {
+  const MatDesc r = rd[blockIdx.y], x = xd[blockIdx.y];
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= x.n) return;
+  double sr = 0.0, sx = 0.0;
+  for (int i = lane; i <= j; i += 64) {
+    sr += cabs2(r.a[(size_t)j * r.lda + i]);
+    sx += cabs2(x.a[(size_t)j * x.lda + i]);
+  }
+  sr = wave_sum(sr);
+  sx = wave_sum(sx);
+  if (lane == 0) out[(size_t)blockIdx.y * ld + j] = cz(sr, sx);
+}
+
+// d.u = the first d.rank[0] columns of the identity (rows past them zero)
+__global__ void identity_u_kernel(const MatDesc *__restrict__ descs) {
+  const MatDesc d = descs[blockIdx.y];
+  const int k = blockIdx.x;
+  if (k >= d.rank[0]) return;
+  double2 *u = d.u + (size_t)k * (d.ldu ? d.ldu : d.lda);
+  for (int i = threadIdx.x; i < d.m; i += blockDim.x) u[i] = cz(i == k ? 1.0 : 0.0, 0.0);
+}
 }  // namespace
 
 // bytes of n complex entries rounded up to 256 (the arena alignment)
@@ -316,11 +475,105 @@ static void upload_descs(DevBuf &buf, const std::vector<MatDesc> &h, hipStream_t
   HIP_CHECK(hipMemcpyAsync(buf.p, h.data(), h.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
 }
 
+// The equilibrated columns of the periodizer's Q are usually independent well
+// within the cutoff; the truncated SVD then keeps every singular value and
+// the pseudoinverse is D P R^{-1} Q_1^H, with Q_1 R the QR of the ordered,
+// scaled columns (P their order, D the scaling).  Since cond_2(R) <=
+// ||R||_F ||R^{-1}||_F, a bound below 1/rel_cutoff shows that no singular
+// value falls under the cutoff, without the SVD: then U = Q_1 and
+// W = D P R^{-1} are formed and true is returned.  Otherwise (some matrix of
+// the batch may need truncating) nothing is kept and false is returned.
+static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, double rel_cutoff,
+                        const double *cscl, const std::vector<MatDesc> &in, hipStream_t s) {
+  const int W = (int)n2.size();
+  const int n2max = *std::max_element(n2.begin(), n2.end());
+  int *flags = g.small.as<int>();
+  std::vector<size_t> ox(W);
+  size_t tx = 0;
+  for (int w = 0; w < W; ++w) {
+    ox[w] = tx;
+    tx += arena_bytes((size_t)round_up(n2[w], 16) * n2[w]);
+  }
+  DevBuf xa(tx), dx;
+  std::vector<MatDesc> hx(W);
+  for (int w = 0; w < W; ++w) {
+    MatDesc d{};
+    d.a = arena_at(xa, ox[w]);
+    d.u = d.a;
+    d.m = n2[w]; d.n = n2[w]; d.lda = round_up(n2[w], 16);
+    d.rank = flags + W + w;
+    hx[w] = d;
+  }
+  upload_descs(dx, hx, s);
+  launch_zero(xa.as<double2>(), (long)(tx / sizeof(double2)), s);
+  const int nblk = cdiv(n2max, TI);
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk, W), dim3(TI), 0, s, g.d_qc.as<MatDesc>(), dx.as<MatDesc>());
+  for (int d = 1; d < nblk; ++d)
+    hipLaunchKernelGGL(trinv_off_kernel, dim3(nblk - d, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+                       dx.as<MatDesc>(), d);
+  DevBuf nrm((size_t)W * n2max * sizeof(double2));
+  hipLaunchKernelGGL(trinv_norm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+                     dx.as<MatDesc>(), nrm.as<double2>(), n2max);
+  HIP_CHECK(hipGetLastError());
+  std::vector<double2> hn((size_t)W * n2max);
+  HIP_CHECK(hipMemcpyAsync(hn.data(), nrm.p, hn.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  for (int w = 0; w < W; ++w) {
+    double sr = 0.0, sx = 0.0;
+    for (int j = 0; j < n2[w]; ++j) {
+      sr += hn[(size_t)w * n2max + j].x;
+      sx += hn[(size_t)w * n2max + j].y;
+    }
+    const double bound = std::sqrt(sr) * std::sqrt(sx);
+    if (!std::isfinite(bound) || !(bound * rel_cutoff < 1.0)) return false;
+  }
+  // every singular value is kept: rank n2, U = Q_1, W = D P R^{-1}
+  g.kept = n2;
+  g.rows = n2;
+  g.cols = n2;
+  g.pivoted = false;
+  g.direct = true;
+  g.jacobi_ms = g.jacobi_bytes = g.jacobi_flops = 0.0;
+  g.jacobi_launches = 0;
+  g.jacobi_unconverged = 0;
+  HIP_CHECK(hipMemcpyAsync(flags + W, n2.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(identity_u_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_qc.as<MatDesc>());
+  HIP_CHECK(hipGetLastError());
+  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s);
+  g.h_fin.resize(W);
+  std::vector<size_t> of(W);
+  {
+    size_t tf = 0;
+    for (int w = 0; w < W; ++w) {
+      of[w] = tf;
+      tf += arena_bytes((size_t)round_up(in[w].n, 16) * n2[w]);
+    }
+    g.fin_w.alloc(tf);
+  }
+  for (int w = 0; w < W; ++w) {
+    MatDesc d{};
+    d.m = in[w].m; d.n = in[w].n; d.lda = g.h_qc[w].lda;
+    d.u = g.h_qc[w].u;
+    d.w = arena_at(g.fin_w, of[w]);
+    d.ldg = round_up(in[w].n, 16);
+    d.rank = flags + W + w;
+    g.h_fin[w] = d;
+  }
+  upload_descs(g.d_fin, g.h_fin, s);
+  hipLaunchKernelGGL(scatter_w_kernel, dim3(n2max, W), dim3(256), 0, s, dx.as<MatDesc>(), g.d_fin.as<MatDesc>(),
+                     g.perm.as<int>(), g.piv.as<int>(), nmax, cscl);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(s));
+  return true;
+}
+
 void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
-                 hipStream_t s) {
+                 hipStream_t s, bool equilibrate) {
   const int W = (int)in.size();
   int nmax = 0, mmax = 0;
   for (auto &d : in) { nmax = std::max(nmax, d.n); mmax = std::max(mmax, d.m); }
+  g.direct = false;
+  g.jacobi_unconverged = 0;
   upload_descs(g.d_in, in, s);
   // 1. column norms, selection and ordering
   DevBuf norms((size_t)W * nmax * sizeof(double));
@@ -331,16 +584,24 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   HIP_CHECK(hipMemcpyAsync(hn.data(), norms.p, hn.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   std::vector<int> perm((size_t)W * nmax, 0), n2(W), rr(W);
+  std::vector<double> scale(equilibrate ? (size_t)W * nmax : 0, 0.0);
   g.maxcol.assign(W, 0.0);
   for (int w = 0; w < W; ++w) {
     const int n = in[w].n;
     const double *nw = hn.data() + (size_t)w * nmax;
     double mx = 0.0;
     for (int c = 0; c < n; ++c) mx = std::max(mx, nw[c]);
-    g.maxcol[w] = mx;
+    // equilibrated: every kept column scaled to unit norm (the largest is 1);
+    // only columns that vanish, or whose scaling would leave the exponent
+    // range, are dropped
+    g.maxcol[w] = equilibrate ? 1.0 : mx;
+    const double keep_min = equilibrate ? 1e-250 * mx : 1e-15 * mx;
     std::vector<int> idx;
     for (int c = 0; c < n; ++c)
-      if (nw[c] >= 1e-15 * mx && mx > 0.0) idx.push_back(c);
+      if (nw[c] >= keep_min && nw[c] > 0.0 && mx > 0.0) {
+        idx.push_back(c);
+        if (equilibrate) scale[(size_t)w * nmax + c] = 1.0 / nw[c];
+      }
     // largest norm first; ties keep their column order
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return nw[x] > nw[y]; });
     n2[w] = (int)idx.size();
@@ -350,6 +611,13 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   }
   g.perm.alloc(perm.size() * sizeof(int));
   HIP_CHECK(hipMemcpyAsync(g.perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  g.colscale.release();
+  if (equilibrate) {
+    g.colscale.alloc(scale.size() * sizeof(double));
+    HIP_CHECK(hipMemcpyAsync(g.colscale.p, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));   // `scale` goes out of scope
+  }
+  const double *cscl = equilibrate ? g.colscale.as<double>() : nullptr;
   const int n2max = *std::max_element(n2.begin(), n2.end());
   const bool pivot = n2max >= pivot_min_cols;
   g.pivoted = pivot;
@@ -387,7 +655,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   }
   upload_descs(g.d_qc, g.h_qc, s);
   hipLaunchKernelGGL(gather_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_in.as<MatDesc>(), g.d_qc.as<MatDesc>(),
-                     g.perm.as<int>(), nmax);
+                     g.perm.as<int>(), nmax, cscl);
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
   if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
@@ -402,6 +670,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     HIP_CHECK(hipMemcpyAsync(g.piv.p, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));
   }
+  if (equilibrate && direct_pinv(g, n2, nmax, rel_cutoff, cscl, in, s)) return;
   if (pivot) {
     g.h_rq.resize(W);
     {
@@ -511,6 +780,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   g.jacobi_launches = js.launches;
   g.jacobi_bytes = js.bytes;
   g.jacobi_flops = js.flops;
+  g.jacobi_unconverged = js.unconverged;
   jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
   // 5. explicit factors
   const int rmax = *std::max_element(rr.begin(), rr.end());
@@ -554,7 +824,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   upload_descs(g.d_fin, g.h_fin, s);
   if (kmax > 0) {
     hipLaunchKernelGGL(scatter_w_kernel, dim3(kmax, W), dim3(256), 0, s, g.d_lq.as<MatDesc>(), g.d_fin.as<MatDesc>(),
-                       g.perm.as<int>(), g.piv.as<int>(), nmax);
+                       g.perm.as<int>(), g.piv.as<int>(), nmax, cscl);
     HIP_CHECK(hipGetLastError());
   }
   HIP_CHECK(hipStreamSynchronize(s));

@@ -9,6 +9,7 @@ namespace mfs {
 
 struct GradedPinv {
   DevBuf d_in, d_qc, d_rq, d_rqu, d_lq, d_fin, perm, piv, small;
+  DevBuf colscale;   // [W][nmax] 1 / column norm of each kept column (equilibrated factorisations)
   // one allocation per kind for all matrices of the batch (per-matrix pieces
   // at aligned offsets): the QR'd copies and their tau, T and U, the pivoted
   // triangles, the LQ/Jacobi factors, and W
@@ -18,17 +19,19 @@ struct GradedPinv {
   std::vector<int> cols, rows, kept;
   hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the unpivoted blocked QR
   bool pivoted = false;              // the triangle went through the pivoted QR
+  bool direct = false;               // every singular value kept: U = Q_1, W = D P R^{-1} (no SVD)
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;
   double jacobi_bytes = 0.0;
   double jacobi_flops = 0.0;
+  int jacobi_unconverged = 0;        // matrices whose Jacobi reached the sweep cap
   // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
   const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
   // free the factorisation's work, keeping what the apply reads (U in
   // qc_fac, W in fin_w, the kept ranks in small)
   void release_work() {
     d_in.release(); d_qc.release(); d_rq.release(); d_rqu.release(); d_lq.release();
-    perm.release(); piv.release();
+    perm.release(); piv.release(); colscale.release();
     qc_a.release(); rq_a.release(); rq_fac.release(); lq_a.release(); lq_fac.release();
   }
   // singular values of every matrix, [W][ldo] (descending, zero past n);
@@ -40,8 +43,11 @@ struct GradedPinv {
 // column-pivoted QR of the triangle is taken before the LQ when the widest
 // kept triangle has at least pivot_min_cols columns (0: always); below that
 // the norm ordering alone preconditions Jacobi.
+// equilibrate: factor A D instead of A, D scaling every kept column to unit
+// norm, so that the relative cutoff judges linear dependence rather than
+// column size; W then holds D V S^+ and the pseudoinverse is D (A D)^+.
 void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
-                 hipStream_t s);
+                 hipStream_t s, bool equilibrate = false);
 
 // Widest periodizer triangle factored without the pivoted QR (measured:
 // 1257 columns at k = 10 gain nothing from it, 9701 at k = 2 pi 13 gain 30%).

@@ -10,23 +10,43 @@
 namespace mfs {
 
 // ------------------------------------------------------------ device buffer
+// Device memory of the calling thread's current device.  Blocks of 1 MiB
+// and more come from a per-device cache (pool.cpp): release keeps them for
+// the next request of about their size, after the device has finished the
+// work queued before the release (the rule hipFree keeps).
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  int dev = 0;
+  size_t cached = 0;   // size of the cached block behind p (0: plain hipMalloc)
   DevBuf() = default;
   explicit DevBuf(size_t n) { alloc(n); }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev), cached(o.cached) {
+    o.p = nullptr; o.bytes = 0; o.cached = 0;
+  }
   DevBuf &operator=(DevBuf &&o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; dev = o.dev; cached = o.cached;
+      o.p = nullptr; o.bytes = 0; o.cached = 0;
+    }
     return *this;
   }
   void alloc(size_t n);
   void release();
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
+// Idle bytes held by the cache of device dev; free them all (pool_trim).
+size_t pool_idle_bytes(int dev);
+void pool_trim(int dev);
+// bytes of live DevBufs on device dev, their peak since pool_reset_peak, idle cached bytes
+void pool_stats(int dev, size_t *in_use, size_t *peak, size_t *idle);
+void pool_reset_peak(int dev);
+// Free device memory of the current device counting the cache's idle blocks.
+size_t device_free_bytes();
 
 // ------------------------------------------------------ batched matrices
 // A matrix taking part in a batched QR / Jacobi SVD / pseudoinverse apply.
@@ -81,6 +101,9 @@ void launch_rhs(const BodyData &b, int nw, const double *kvec_dev, double2 *out,
 // out[r][b][x] = scale * sum_l in[r][l][x] e^{sgn 2 pi i b l / P}, r < nr, x < X
 void launch_dft(int nr, int P, int X, const double2 *in, double2 *out, int sgn, double scale,
                 hipStream_t s);
+// out[r][b][x] = (1/P) sum_l in[r][x][l] e^{-2 pi i b l / P}: angle samples laid
+// out [nr][X][P] to modes [nr][P][X]
+void launch_angle_to_modes(int nr, int P, int X, const double2 *in, double2 *out, hipStream_t s);
 // sigma[r][l][j] = (1/qs) sum_n c[r][bin(n)][j] e^{+i n 2 pi l / qs}, j < N;
 // c has ldc entries per bin (N, or 2N for the exterior half of a
 // transmission body's coefficients)
@@ -92,6 +115,7 @@ struct JacStats {
   int launches = 0;
   double bytes = 0.0;    // algorithmic HBM bytes of the sweeps
   double flops = 0.0;    // algorithmic FP64 flops of the sweeps
+  int unconverged = 0;   // matrices still rotating when the sweep cap was reached
 };
 JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
                  hipStream_t s);
@@ -152,6 +176,7 @@ struct NsumPlan {
   int dense_S = 0;
   double dense_k = 0.0;
   size_t dense_bytes = 0;
+  size_t dense_alg_bytes = 0;   // dense_bytes less the padding of partly filled tiles
 };
 // out[r][t] = sum_img w[g][img][r] sum_s K(x_t - a ex - b ey, y_s) sigma[r][s]
 // w: device [ngroups][9][nrhs] complex; src: SoA x y z [S]; sigma [nrhs][S]

@@ -615,10 +615,18 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
     off += (size_t)g.nimg * S * (paired ? dense_kept(g) : round_up(std::max(g.nt, 1), 64));
   }
   const size_t bytes = off * sizeof(double2);
+  // the values the method needs, without the tile padding: every real target
+  // whose values are stored (half of a self-paired wall group)
+  size_t alg = 0;
+  for (const NsumGroup &g : plan.groups) {
+    const size_t real = !paired ? (size_t)g.nt
+                        : g.pkind == 1 ? (size_t)g.mt
+                        : g.pkind == 2 ? (size_t)g.nt
+                        : g.pkind == 4 ? (size_t)(g.nt + 1) / 2 : 0;
+    alg += (size_t)g.nimg * S * real * sizeof(double2);
+  }
   if (bytes > max_bytes) return false;
-  size_t fr = 0, tot = 0;
-  HIP_CHECK(hipMemGetInfo(&fr, &tot));
-  if (bytes + ((size_t)2 << 30) > fr) return false;   // keep 2 GiB of headroom
+  if (bytes + ((size_t)2 << 30) > device_free_bytes()) return false;   // keep 2 GiB of headroom
   plan.dense.alloc(bytes);
   plan.sigT.alloc((size_t)S * MAXR * sizeof(double2));
   plan.koff.alloc(koff.size() * sizeof(size_t));
@@ -649,6 +657,7 @@ bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const doub
   plan.dense_S = S;
   plan.dense_k = k;
   plan.dense_bytes = bytes;
+  plan.dense_alg_bytes = alg;
   return true;
 }
 

@@ -43,20 +43,15 @@ struct Finished {
   std::vector<mfs_c128> kz, a, b, field;
 };
 
-// One admission group: its waves' Q^+ factors live while one of them iterates.
-struct Group {
-  std::unique_ptr<Solver> S;
-};
-
 struct Slot {
   int state = 0;   // 0 free, 1 admitting, 2 factored (joins at the next iteration), 3 iterating
   Request req;
-  std::shared_ptr<Group> grp;
-  MatDesc qd{};
+  MatDesc qd{};   // Q^+ factors in the slot's own storage (slot_fac)
   cplx al = 1.0, be = 1.0;
   double kv[3] = {0.0, 0.0, 0.0};
   std::vector<RBOrder> orders;
   int qrank = 0;
+  bool q_converged = true;   // the Jacobi SVD of the wave's Q (if one ran) converged
   // GMRES
   int j = 0;
   double beta0 = 0.0, resid = 0.0;
@@ -77,6 +72,11 @@ struct mfs_server {
   hipStream_t s_it = nullptr, s_ad = nullptr;
   std::unique_ptr<mfs::Solver> it;      // the slot pool: plans, near field, B~, bases, work
   mfs::DevBuf qd, zero;                 // Q^+ descriptors of the slots; zeros for empty ones
+  // every slot's Q^+ factors, U (rows x NQb, leading dimension ldq) then W
+  // (round_up(NQb, 16) x NQb), and the slots' kept ranks: allocated with the
+  // server, so the factors of the waves in flight never add memory
+  mfs::DevBuf slot_fac, slot_rank;
+  size_t slot_stride = 0;
   std::vector<mfs::MatDesc> hq;
   std::vector<mfs::Slot> slots;
   std::mutex mu;
@@ -87,7 +87,10 @@ struct mfs_server {
   bool stop = false, failed = false;
   std::string fail_msg;
   int admitting = 0;
-  double wave_factor_bytes = 0.0, wave_work_bytes = 0.0, fixed_bytes = 0.0;
+  // memory: fixed_bytes (stored near field, Krylov bases, the slots' factor
+  // storage) is held for the server's life; an admission group of g waves
+  // holds g * wave_work_bytes more while it is factored
+  double wave_work_bytes = 0.0, fixed_bytes = 0.0;
   std::thread t_ad, t_it;
 };
 
@@ -116,15 +119,11 @@ void fail(mfs_server *sv, const std::string &msg) {
 
 // waves the admission thread may take now (mu held)
 int admissible(mfs_server *sv) {
-  int freeslots = 0, resident = 0;
-  for (auto &s : sv->slots) {
+  int freeslots = 0;
+  for (auto &s : sv->slots)
     if (s.state == 0) ++freeslots;
-    else ++resident;
-  }
   int g = std::min({(int)sv->pending.size(), freeslots, sv->cfg.admit_batch});
-  while (g > 0 && sv->fixed_bytes + (resident + g) * sv->wave_factor_bytes + g * sv->wave_work_bytes >
-                      (double)sv->cfg.hbm_budget)
-    --g;
+  while (g > 0 && sv->fixed_bytes + g * sv->wave_work_bytes > (double)sv->cfg.hbm_budget) --g;
   return g;
 }
 
@@ -146,9 +145,8 @@ void admit(mfs_server *sv, const std::vector<int> &ks, const std::vector<Request
   BodyData &b = body_of(sv->op, sv->body);
   const int g = (int)ks.size();
   hipStream_t s = sv->s_ad;
-  auto grp = std::make_shared<Group>();
-  grp->S.reset(new Solver(sv->op, b, sv->lat, g, sv->cfg.maxit, s));
-  Solver &A = *grp->S;
+  std::unique_ptr<Solver> As(new Solver(sv->op, b, sv->lat, g, sv->cfg.maxit, s));
+  Solver &A = *As;
   A.al.resize(g);
   A.be.resize(g);
   A.kv.resize(3 * g);
@@ -159,6 +157,26 @@ void admit(mfs_server *sv, const std::vector<int> &ks, const std::vector<Request
   MFS_REQUIRE(A.NQmax <= sv->it->NQmax, "server: Q wider than the pool's bound");
   A.Q.clear();
   A.gp.release_work();
+  // the factors move into the slots' own storage; the group's arenas go
+  // when A does, at the end of this call
+  std::vector<MatDesc> sq(g);
+  for (int i = 0; i < g; ++i) {
+    const MatDesc &f = A.gp.h_fin[i];
+    const int kept = A.qrank[i];
+    char *base = static_cast<char *>(sv->slot_fac.p) + (size_t)ks[i] * sv->slot_stride;
+    MatDesc d = f;
+    d.u = reinterpret_cast<double2 *>(base);
+    d.w = reinterpret_cast<double2 *>(base + (size_t)f.lda * sv->it->NQmax * sizeof(double2));
+    d.rank = sv->slot_rank.as<int>() + ks[i];
+    MFS_REQUIRE(f.lda == sv->it->ldq && f.ldg <= round_up(sv->it->NQmax, 16) && kept <= sv->it->NQmax,
+                "server: factors larger than a slot's storage");
+    if (kept > 0) {
+      HIP_CHECK(hipMemcpyAsync(d.u, f.u, (size_t)f.lda * kept * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(d.w, f.w, (size_t)f.ldg * kept * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    }
+    HIP_CHECK(hipMemcpyAsync(d.rank, &A.qrank[i], sizeof(int), hipMemcpyHostToDevice, s));
+    sq[i] = d;
+  }
   // right-hand sides and the first Krylov vector of every wave in its slot
   Solver &P = *sv->it;
   const int MP = P.MP;
@@ -186,13 +204,13 @@ void admit(mfs_server *sv, const std::vector<int> &ks, const std::vector<Request
   std::lock_guard<std::mutex> lk(sv->mu);
   for (int i = 0; i < g; ++i) {
     Slot &sl = sv->slots[ks[i]];
-    sl.grp = grp;
-    sl.qd = A.gp.h_fin[i];
+    sl.qd = sq[i];
     sl.al = A.al[i];
     sl.be = A.be[i];
     for (int c = 0; c < 3; ++c) sl.kv[c] = A.kv[3 * i + c];
     sl.orders = A.orders[i];
     sl.qrank = A.qrank[i];
+    sl.q_converged = A.gp.jacobi_unconverged == 0;
     sl.j = 0;
     sl.beta0 = beta0[i];
     sl.resid = beta0[i] > 0 ? 1.0 : 0.0;
@@ -406,24 +424,20 @@ void iter_loop(mfs_server *sv) {
         f.eps_flux = r.eps_flux;
         f.q_rank = r.q_rank;
         f.nq_cols = r.nq_cols;
-        f.st = (sl.resid <= sv->cfg.tol || sl.beta0 == 0.0) ? MFS_OK : MFS_ENOTCONV;
+        f.st = ((sl.resid <= sv->cfg.tol || sl.beta0 == 0.0) && sl.q_converged) ? MFS_OK : MFS_ENOTCONV;
         f.latency_ms = std::chrono::duration<double, std::milli>(t_done - sl.req.t_submit).count();
         out.emplace_back(sl.req.ticket, std::move(f));
       }
-      std::vector<std::shared_ptr<Group>> release;   // freed outside the lock
       {
         std::lock_guard<std::mutex> lk(sv->mu);
         for (auto &p : out) sv->done[p.first] = std::move(p.second);
         for (int k : fin) {
-          Slot &sl = sv->slots[k];
-          sl.state = 0;
-          release.push_back(std::move(sl.grp));
+          sv->slots[k].state = 0;
           sv->hq[k] = empty_desc(sv);
         }
         descs_dirty = true;
         sv->cv_ad.notify_all();
       }
-      release.clear();
     }
   } catch (const Error &e) {
     fail(sv, e.msg);
@@ -474,11 +488,15 @@ mfs_status mfs_server_create(mfs_ctx *ctx, const mfs_op *op, int32_t body, const
     const int ob = ((int)std::ceil(lat->N0 * lat->ex) + 3) * ((int)std::ceil(lat->N0 * lat->ey) + 3);
     const int NQb = NH + 2 * ob;
     const double rows = 8.0 * lat->M1 * lat->M1;
-    sv->wave_factor_bytes = (rows * NQb + (double)NQb * NQb) * sizeof(double2);
     sv->wave_work_bytes = (4.0 * rows * NQb + 8.0 * (double)NQb * NQb) * sizeof(double2);
     const double basis = (double)W * (cfg->maxit + 1) * b.P * b.rows * sizeof(double2);
-    const double need = basis + sv->wave_factor_bytes + sv->wave_work_bytes;
-    if ((double)cfg->hbm_budget < need) MFS_THROW(MFS_ENOMEM, "server: hbm_budget below one wave in flight");
+    const int ldq = round_up((int)rows, 16);
+    sv->slot_stride = ((size_t)ldq * NQb + (size_t)round_up(NQb, 16) * NQb) * sizeof(double2);
+    const double need = basis + (double)W * sv->slot_stride + sv->wave_work_bytes;
+    if ((double)cfg->hbm_budget < need)
+      MFS_THROW(MFS_ENOMEM, "server: hbm_budget below the slots' storage and one wave's factorisation");
+    size_t in0 = 0, in1 = 0;
+    pool_stats(ctx->device, &in0, nullptr, nullptr);
     sv->it.reset(new Solver(op, b, *lat, W, cfg->maxit, sv->s_it));
     Solver &S = *sv->it;
     S.NQmax = NQb;
@@ -487,11 +505,12 @@ mfs_status mfs_server_create(mfs_ctx *ctx, const mfs_op *op, int32_t body, const
     S.kv.assign(3 * W, 0.0);
     S.orders.assign(W, {});
     S.qrank.assign(W, 0);
-    S.near_limit = (size_t)std::max(0.0, (double)cfg->hbm_budget - need - (double)(W - 1) * sv->wave_factor_bytes);
+    S.near_limit = (size_t)std::max(0.0, (double)cfg->hbm_budget - need);
     S.setup_bvals();
     S.setup_sums();
     S.time_nsum = false;
-    sv->fixed_bytes = basis + (double)S.psurf.dense_bytes + (double)S.pwalls.dense_bytes;
+    sv->slot_fac.alloc((size_t)W * sv->slot_stride);
+    sv->slot_rank.alloc((size_t)W * sizeof(int));
     sv->zero.alloc(4096);
     HIP_CHECK(hipMemsetAsync(sv->zero.p, 0, 4096, sv->s_it));
     sv->qd.alloc((size_t)W * sizeof(MatDesc));
@@ -499,6 +518,20 @@ mfs_status mfs_server_create(mfs_ctx *ctx, const mfs_op *op, int32_t body, const
     S.qdesc = sv->qd.as<MatDesc>();
     upload(sv->qd.p, sv->hq.data(), W * sizeof(MatDesc), sv->s_it);
     HIP_CHECK(hipStreamSynchronize(sv->s_it));
+    // held for the server's life: what the set-up above allocated (measured;
+    // at least the bases, the slots' storage and the stored near field), and
+    // the buffers of one recovery of `slots` waves (the iteration thread
+    // forms their amplitudes and fields: eta, the q_field-node strengths and
+    // the target sums with up to 51 partial slices)
+    pool_stats(ctx->device, &in1, nullptr, nullptr);
+    const double listed = basis + (double)W * sv->slot_stride + (double)S.psurf.dense_bytes +
+                          (double)S.pwalls.dense_bytes;
+    const double ntp = (double)round_up(std::max(cfg->ntargets, 1), 64);
+    const double recover = 16.0 * W * ((double)b.P * b.rows + (double)cfg->q_field * b.N + 51.0 * ntp) +
+                           24.0 * cfg->q_field * b.N;
+    sv->fixed_bytes = std::max(in1 > in0 ? (double)(in1 - in0) : 0.0, listed) + recover;
+    if (sv->fixed_bytes + sv->wave_work_bytes > (double)cfg->hbm_budget)
+      MFS_THROW(MFS_ENOMEM, "server: hbm_budget below the resident storage and one wave's factorisation");
     sv->slots.resize(W);
     sv->t_ad = std::thread(admit_loop, sv);
     sv->t_it = std::thread(iter_loop, sv);

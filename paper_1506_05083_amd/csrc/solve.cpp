@@ -20,10 +20,11 @@
 
 namespace mfs {
 
+size_t apply_pinv_work_bytes(const BodyData &b) { return (size_t)b.nd * 32 * b.cols * sizeof(double2); }
+
 void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double2 *x, double2 *out,
-                     hipStream_t s) {
-  const size_t need = (size_t)b.nd * 32 * b.cols * sizeof(double2);
-  double2 *yw = op_workspace(op, need);
+                     hipStream_t s, double2 *yw) {
+  if (!yw) yw = op_workspace(op, apply_pinv_work_bytes(b));
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = std::min(16, nrhs - r0);
     PinvJob j{};
@@ -41,6 +42,29 @@ void apply_pinv_body(const mfs_op *op, const BodyData &b, int nrhs, const double
     j.ywork = yw;
     launch_pinv_apply(j, s);
   }
+}
+
+void check_apply_args(const mfs_op *op, int nrhs, const void *in, int in_layout, const void *out, int out_layout) {
+  if (!op->factored) MFS_THROW(MFS_ESTATE, "mfs_factor_modes has not run");
+  MFS_REQUIRE(nrhs >= 0 && (nrhs == 0 || (in && out)), "bad arguments");
+  MFS_REQUIRE(in_layout == MFS_LAYOUT_MODES || in_layout == MFS_LAYOUT_ANGLE,
+              "in_layout must be MFS_LAYOUT_MODES or MFS_LAYOUT_ANGLE");
+  MFS_REQUIRE(out_layout == MFS_LAYOUT_MODES || out_layout == MFS_LAYOUT_POINTS,
+              "out_layout must be MFS_LAYOUT_MODES or MFS_LAYOUT_POINTS");
+}
+
+void apply_solution_layouts(const mfs_op *op, const BodyData &b, int nrhs, const double2 *in, int in_layout,
+                            double2 *out, int out_layout, double2 *in_modes, double2 *out_modes, double2 *yw,
+                            hipStream_t s) {
+  if (nrhs == 0) return;
+  const double2 *x = in;
+  if (in_layout == MFS_LAYOUT_ANGLE) {
+    launch_angle_to_modes(nrhs, b.P, b.rows, in, in_modes, s);
+    x = in_modes;
+  }
+  double2 *c = out_layout == MFS_LAYOUT_POINTS ? out_modes : out;
+  apply_pinv_body(op, b, nrhs, x, c, s, yw);
+  if (out_layout == MFS_LAYOUT_POINTS) launch_point_strengths(nrhs, b.P, b.P, b.N, c, out, s, b.cols);
 }
 
 }  // namespace mfs
@@ -256,10 +280,19 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       double nb = 0.0;
       for (double x : S.nsum_bytes) nb += x;
       timing->near_bytes = S.nsum_bytes.empty() ? 0.0 : nb / (double)S.nsum_bytes.size();
+      double na = 0.0;
+      for (double x : S.nsum_alg_bytes) na += x;
+      timing->near_alg_bytes = S.nsum_alg_bytes.empty() ? 0.0 : na / (double)S.nsum_alg_bytes.size();
+      timing->near_mode = S.near_mode;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (notconv) {
       set_error("GMRES reached maxit before the tolerance");
+      return MFS_ENOTCONV;
+    }
+    if (S.gp.jacobi_unconverged > 0) {
+      set_error("the Jacobi SVD of the periodizer Q of " + std::to_string(S.gp.jacobi_unconverged) +
+                " wave(s) reached its sweep cap; the results use the factors of the last sweep");
       return MFS_ENOTCONV;
     }
     return MFS_OK;

@@ -54,7 +54,11 @@ struct Solver {
   int nsplit_s = 1, nsplit_w = 1;
   // timing: events around every neighbour-sum launch, the dense bytes each streamed
   std::vector<hipEvent_t> nsum_ev;
-  std::vector<double> nsum_bytes;
+  std::vector<double> nsum_bytes, nsum_alg_bytes;
+  // where the neighbour sums' kernel values come from: 0 evaluated on the fly
+  // (near-field budget 0), 1 stored, 2 on the fly because the stored field
+  // did not fit the budget or the free device memory
+  int near_mode = 0;
   bool time_nsum = true;
   double near_fill_ms = 0.0;
 
@@ -127,9 +131,13 @@ struct Solver {
     upload(qdescs.p, h_qdescs.data(), W * sizeof(MatDesc), s);
     HIP_CHECK(hipStreamSynchronize(s));   // ordbufs are released on return
     progress("periodizer: Q filled for %d waves, %d x %d at most; factoring", W, rows, NQmax);
-    graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s);
+    // Q's columns equilibrated: the harmonics of high degree are smaller than
+    // the low ones by far more than the cutoff on the walls, and would
+    // otherwise be dropped whatever their use
+    graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s, true);
     qrank = gp.kept;
-    progress("periodizer: factored (%s triangle; Jacobi %.0f ms, %d launches)", gp.pivoted ? "pivoted" : "ordered",
+    progress("periodizer: factored (%s; Jacobi %.0f ms, %d launches)",
+             gp.direct ? "full rank, no SVD" : gp.pivoted ? "pivoted triangle" : "ordered triangle",
              gp.jacobi_ms, gp.jacobi_launches);
     setup_bvals();
   }
@@ -162,6 +170,10 @@ struct Solver {
       float ms = 0.f;
       HIP_CHECK(hipEventElapsedTime(&ms, f0, f1));
       near_fill_ms = (psurf.dense.p || pwalls.dense.p) ? ms : 0.0;
+      near_mode = (psurf.dense.p && pwalls.dense.p) ? 1 : 2;
+      if (near_mode == 2)
+        progress("near field: %s stored; the other sums run on the fly (budget or free memory too small)",
+                 psurf.dense.p ? "surface sums" : "nothing");
       (void)hipEventDestroy(f0);
       (void)hipEventDestroy(f1);
     }
@@ -311,6 +323,7 @@ struct Solver {
       nsum_ev.push_back(e0);
       nsum_ev.push_back(e1);
       nsum_bytes.push_back((double)plan.dense_bytes);
+      nsum_alg_bytes.push_back((double)plan.dense_alg_bytes);
     }
   }
 

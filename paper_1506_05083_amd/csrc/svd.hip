@@ -675,7 +675,10 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
   HIP_CHECK(hipGetLastError());
   // rotation threshold 4 sqrt(n) eps, n of each matrix (set in the kernel)
   const double tol = 4.0 * 2.220446049250313e-16;
-  const int max_sweeps = 40;
+  // sweep cap; MFS_JACOBI_MAX_SWEEPS lowers it (a test of the not-converged
+  // status forces a cap of one sweep)
+  int max_sweeps = 40;
+  if (const char *e = getenv("MFS_JACOBI_MAX_SWEEPS")) max_sweeps = std::max(1, std::min(40, atoi(e)));
   const bool dbg = getenv("MFS_DEBUG") != nullptr;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
@@ -730,6 +733,9 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
               sweep, nact, nrot, nchecked);
     if (!any) break;
   }
+  // matrices that still rotated in the last sweep allowed did not converge
+  if (sweep == max_sweeps)
+    for (int i = 0; i < nmat; ++i) st.unconverged += active[i] ? 1 : 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;

@@ -39,9 +39,13 @@ def main():
     out = {
         "source": "oracle (tests/golden/make_golden.py)",
         "workload": "periodic_k10, incidence 0, GMRES tol 1e-12",
+        "lattice": {"ex": lat.ex, "ey": lat.ey, "z0": lat.z0, "p": lat.p, "N0": lat.N0, "M1": lat.M1},
         "theta": w.theta, "phi": w.phi,
         "iters": int(res["iters"]),
+        "gmres_resid": float(res["hist"][-1]),
         "eps_flux": ps.eps_flux(res["a"], res["b"]),
+        "eps_per": ps.eps_per(res["c"], res["d"], pr.q_field),
+        "eps_bc": ps.eps_bc(res["c"], res["d"], b.q),
         "m": o.m.tolist(), "n": o.n.tolist(),
         "a_re": res["a"].real.tolist(), "a_im": res["a"].imag.tolist(),
         "b_re": res["b"].real.tolist(), "b_im": res["b"].imag.tolist(),
@@ -51,7 +55,8 @@ def main():
     }
     with open(os.path.join(HERE, "periodic_k10_wave0.json"), "w") as f:
         json.dump(out, f)
-    print(f"wrote golden in {out['seconds']:.0f} s, {out['iters']} iterations, eps_flux {out['eps_flux']:.2e}")
+    print(f"wrote golden in {out['seconds']:.0f} s, {out['iters']} iterations, eps_flux {out['eps_flux']:.2e}, "
+          f"eps_per {out['eps_per']:.2e}, eps_bc {out['eps_bc']:.2e}")
 
 
 if __name__ == "__main__":

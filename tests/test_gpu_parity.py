@@ -340,11 +340,15 @@ def test_sixteen_wave_batch_matches_small_batches(mfs, ctx):
     assert worst < 1e-12
 
 
-def test_periodic_k10_full_size_vs_golden(mfs, ctx):
+@pytest.mark.parametrize("tol", [1e-12, 1e-10])
+def test_periodic_k10_full_size_vs_golden(mfs, ctx, tol):
     """Full size of the benchmark workload, in the benchmark's launch
     configuration (all 8 incidences in one batched solve), against the
-    oracle's stored solution of incidence 0 (tests/golden/make_golden.py):
-    Bragg amplitudes and cell fields to 1e-10."""
+    oracle's stored solution of incidence 0 (tests/golden/make_golden.py,
+    GMRES to 1e-12): Bragg amplitudes and cell fields to 1e-10, at the parity
+    tolerance 1e-12 and at the benchmark's GMRES tolerance 1e-10 (the
+    '@1e-10 rel err' of the throughput figure); every incidence's flux
+    balance to 1e-10."""
     import json
     import os
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "periodic_k10_wave0.json")))
@@ -354,7 +358,7 @@ def test_periodic_k10_full_size_vs_golden(mfs, ctx):
     op = make_op(mfs, ctx, b)
     op.factor_modes(1e-10)
     tg = np.array(gold["targets"])
-    res = mfs.solve_incident(ctx, op, _lat(mfs, lat), [(w.theta, w.phi) for w in pr.waves], tol=1e-12,
+    res = mfs.solve_incident(ctx, op, _lat(mfs, lat), [(w.theta, w.phi) for w in pr.waves], tol=tol,
                              maxit=100, targets=tg, q_field=gold["q_field"])
     r = res[0]
     assert r.m.tolist() == gold["m"] and r.n.tolist() == gold["n"]
@@ -364,7 +368,50 @@ def test_periodic_k10_full_size_vs_golden(mfs, ctx):
     ea = np.max(np.abs(r.a - ga)) / np.max(np.abs(ga))
     eb = np.max(np.abs(r.b - gb)) / np.max(np.abs(gb))
     eu = np.linalg.norm(r.field - gu) / np.linalg.norm(gu)
-    log(f"[k10] iters gpu {r.iters} oracle {gold['iters']} a {ea:.2e} b {eb:.2e} u {eu:.2e} "
-        f"flux {r.eps_flux:.2e} (oracle {gold['eps_flux']:.2e})")
+    log(f"[k10 tol {tol:g}] iters gpu {r.iters} oracle {gold['iters']} a {ea:.2e} b {eb:.2e} u {eu:.2e} "
+        f"flux {max(x.eps_flux for x in res):.2e} (oracle {gold['eps_flux']:.2e})")
     assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
-    assert all(x.eps_flux < 1e-7 for x in res)
+    assert all(x.eps_flux < 1e-10 for x in res)
+
+
+@pytest.mark.parametrize("name", ["sphere", "cup"])
+def test_apply_angle_samples_to_point_strengths(mfs, ctx, name):
+    """The apply call with its angle-sample input and point-strength output
+    (angle DFT, per-mode pseudoinverse, inverse DFT: eq. (fhatquad), Sec. 4.2,
+    the point-source form of Sec. 4.1) against the oracle's chain rhs_modes ->
+    solve_modes -> point_strengths, compared through the field the strengths
+    radiate at the test points (the strengths themselves are not unique);
+    and the angle input against the mode input on the GPU's own operator."""
+    import torch
+    pr = CASES[name]()
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    g = geometry.build_geometry(b)
+    w = pr.waves[0]
+    kv = W.wave_vector(b.k, w)
+    X, Nn = geometry.surface_points(g, b.P)                        # [P, M, 3]
+    f = -1j * (Nn @ kv) * np.exp(1j * (X @ kv))                     # [P, M]
+    f_angle = torch.from_numpy(np.ascontiguousarray(f.T)[None]).cuda()   # [1, M, P]
+    sig = mfs.apply_solution_op(op, f_angle, in_layout=mfs.LAYOUT_ANGLE,
+                                out_layout=mfs.LAYOUT_POINTS).cpu().numpy()[0]   # [P, N]
+    A = onebody.modal_blocks(b, g)
+    co = onebody.solve_modes(A, onebody.rhs_modes(b, g, w))
+    sig_o = onebody.point_strengths(co, b.P)
+    Y = geometry.source_ring_points(g, b.P)
+    u = onebody.field_from_points(b.k, Y, sig, pr.targets)
+    uo = onebody.field_from_points(b.k, Y, sig_o, pr.targets)
+    err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    # the mode-layout path on the same operator: the same field up to the
+    # rounding of the angle transform
+    c_modes = mfs.apply_solution_op(op, mfs.rhs_modes(op, kv[None]))
+    c_angle = mfs.apply_solution_op(op, f_angle, in_layout=mfs.LAYOUT_ANGLE)
+    u_m = mfs.field_free(op, c_modes, pr.q_field, pr.targets).cpu().numpy()[0]
+    u_a = mfs.field_free(op, c_angle, pr.q_field, pr.targets).cpu().numpy()[0]
+    ec = float(np.linalg.norm(u_a - u_m) / np.linalg.norm(u_m))
+    log(f"[apply layouts] {name}: field of the point strengths vs oracle {err:.2e}; "
+        f"angle vs mode input {ec:.2e}")
+    assert err < 1e-10
+    assert ec < 1e-11
+    with pytest.raises(mfs.MfsError):
+        mfs.apply_solution_op(op, f_angle, in_layout=7)

@@ -181,3 +181,31 @@ def test_server_transmission_matches_plain(mfs):
             f"eps_flux {res.eps_flux:.2e}")
         assert d <= 1e-12
         assert res.eps_flux < 1e-6
+
+
+def test_server_memory_within_budget(mfs, setup):
+    """With a budget that leaves room to factor one wave at a time, the
+    device memory the library holds (its allocator's count of live buffers,
+    peak over the whole run) stays within hbm_budget while six requests are
+    admitted, factored, iterated and recovered, and the results are those of
+    the one-at-a-time plain solves."""
+    pr, ctx, op, L, waves, ref = setup
+    budget = 1 << 30
+    mfs.reset_memory_peak(0)
+    base = mfs.memory_stats(0)["in_use"]
+    srv = mfs.Server(ctx, op, L, slots=4, admit_batch=4, tol=1e-12, maxit=100, targets=pr.targets,
+                     q_field=pr.q_field, hbm_budget=budget)
+    try:
+        tks = [srv.submit(*w) for w in waves]
+        got = [srv.wait(t) for t in tks]
+    finally:
+        srv.close()
+    st = mfs.memory_stats(0)
+    held = st["peak"] - base
+    log(f"[server memory] budget {budget / 2**20:.0f} MiB, peak held {held / 2**20:.0f} MiB, "
+        f"after close {(st['in_use'] - base) / 2**20:.0f} MiB")
+    assert held <= budget
+    assert st["in_use"] - base <= 0
+    for i, (res, _, ok) in enumerate(got):
+        assert ok
+        assert same(res, ref[i]) <= 1e-12

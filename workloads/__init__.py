@@ -183,12 +183,12 @@ def sphere_free_space() -> Problem:
 
 def periodic_k10(nwaves: int = 8) -> Problem:
     """Unit square lattice, k = 10, r = 0.3 (1 + 0.1 cos 3t); N = 200,
-    M = 240 (midpoint), tau = 0.1, P = 64, q = 400, z0 = 0.6; periodizer
-    p = 36, N0 = 14, M1 = 30 (eps_flux ~ 4e-9, eps_per ~ 2e-8 with the
-    oracle); incidences from seed 2."""
+    M = 240 (midpoint), tau = 0.1, P = 64, q = 400; periodizer z0 = 0.7,
+    p = 32, N0 = 18, M1 = 28 (chosen by convergence of eps_flux and eps_per
+    to ~1e-12 with Q's columns equilibrated); incidences from seed 2."""
     shape = Shape(0.3, 0.1, 3)
     b = Body(shape, N=200, M=240, P=64, q=400, k=10.0, tau=0.1, colloc="mid")
-    lat = Lattice(1.0, 1.0, 0.6, p=36, N0=14, M1=30)
+    lat = Lattice(1.0, 1.0, 0.7, p=32, N0=18, M1=28)
     waves = tuple(sample_waves(b.k, lat, nwaves, seed=2))
     return Problem("periodic_k10", b, lat, waves, cell_grid(lat, shape), q_field=256,
                    gmres_tol=1e-10)
