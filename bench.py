@@ -409,31 +409,22 @@ def main():
                      "frac": nsum_tflops / PEAK_FP64, "traffic": None,
                      "launch_ms": nsum_avg, "pairs_per_launch": pairs, "flops_per_pair": flops_pair,
                      "share_of_step": nsum_share}
-    jac_ms = float(np.median([t["jacobi_ms"] for t in tms]))
-    jac_launch_ms = jac_ms / max(1, int(np.median([t["jacobi_launches"] for t in tms])))
-    jac_bytes = float(np.median([t["jacobi_bytes"] / max(1, t["jacobi_launches"]) for t in tms]))
-    jac_flops = float(np.median([t["jacobi_flops"] / max(1, t["jacobi_launches"]) for t in tms]))
-    jac_gbs = jac_bytes / (jac_launch_ms * 1e-3) / 1e9
-    jac_tflops = jac_flops / (jac_launch_ms * 1e-3) / 1e12
-    jac_common = {"kernel": "jac_gram_mfma_kernel + jac_inner_kernel<16> + jac_apply_mfma_kernel "
-                            "(periodizer pseudoinverse, 8 waves; per launch, three launches a round)",
-                  "traffic": None, "launch_ms": jac_launch_ms, "bytes_per_launch": jac_bytes,
-                  "flops_per_launch": jac_flops, "flops_per_byte": jac_flops / max(jac_bytes, 1.0),
-                  "share_of_step": jac_ms / ms_step}
-    # the bound is the one the kernel's arithmetic intensity selects against
-    # the FP64 / HBM balance of the chip
-    if jac_flops / max(jac_bytes, 1.0) >= PEAK_FP64 * 1e12 / (PEAK_HBM * 1e9):
-        roof_jac = {"bound": "alu", "achieved": jac_tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                    "frac": jac_tflops / PEAK_FP64, **jac_common}
-    else:
-        roof_jac = {"bound": "hbm", "achieved": jac_gbs, "peak": PEAK_HBM, "unit": "GB/s",
-                    "frac": jac_gbs / PEAK_HBM, **jac_common}
+    # the periodizer's blocked QR of the 8 waves' Q (one batch): FP64 rate of
+    # its kernels against the FP64 peak (its trailing update is a dense
+    # contraction, 8 m n^2 - 8 n^3 / 3 flops per matrix)
+    q_qr_ms = float(np.median([t["q_qr_ms"] for t in tms]))
+    q_qr_fl = float(np.median([t["q_qr_flops"] for t in tms]))
+    roof_qr = {"bound": "alu", "kernel": "bqr_* blocked Householder QR of the periodizer Q (8 waves, one batch)",
+               "achieved": q_qr_fl / (q_qr_ms * 1e-3) / 1e12, "peak": PEAK_FP64, "unit": "TFLOP/s",
+               "frac": q_qr_fl / (q_qr_ms * 1e-3) / 1e12 / PEAK_FP64, "traffic": None, "launch_ms": q_qr_ms,
+               "flops_per_launch": q_qr_fl, "share_of_step": q_qr_ms / ms_step,
+               "post_qr_ms": float(np.median([t["q_post_ms"] for t in tms])),
+               "jacobi_ms": float(np.median([t["jacobi_ms"] for t in tms]))}
     # the dominant single kernel: the stored-near-field sum when it is used
-    # (the Jacobi share is split over its three kernels), else the larger share
-    if near_bytes > 0 or roof_nsum["share_of_step"] >= roof_jac["share_of_step"]:
-        roofline, other = roof_nsum, roof_jac
+    if near_bytes > 0 or roof_nsum["share_of_step"] >= roof_qr["share_of_step"]:
+        roofline, other = roof_nsum, roof_qr
     else:
-        roofline, other = roof_jac, roof_nsum
+        roofline, other = roof_qr, roof_nsum
     line = {
         "metric": "FP64 modal fill+QR TFLOP/s; incident-wave solves/s, p50/p99 @1e-10 rel err",
         "value": nw * K / t_total,

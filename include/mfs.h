@@ -156,6 +156,10 @@ typedef struct {
   int32_t near_mode;      /* 0: sums evaluated on the fly (budget 0); 1: stored
                              near field; 2: on the fly because the stored field
                              did not fit the budget or the free device memory */
+  double q_qr_ms;         /* blocked Householder QR of the waves' Q (one batch) */
+  double q_qr_flops;      /* its algorithmic flops, sum of 8 m n^2 - 8 n^3 / 3  */
+  double q_post_ms;       /* the rest of Q^+: triangle inverse (or the SVD path)
+                             and the explicit factors                         */
 } mfs_solve_timing;
 
 const char *mfs_last_error(void);

@@ -79,7 +79,8 @@ class SolveTiming(C.Structure):
                 ("nsum_launches", C.c_int32), ("jacobi_ms", C.c_double),
                 ("jacobi_launches", C.c_int32), ("jacobi_bytes", C.c_double),
                 ("jacobi_flops", C.c_double), ("near_fill_ms", C.c_double),
-                ("near_bytes", C.c_double), ("near_alg_bytes", C.c_double), ("near_mode", C.c_int32)]
+                ("near_bytes", C.c_double), ("near_alg_bytes", C.c_double), ("near_mode", C.c_int32),
+                ("q_qr_ms", C.c_double), ("q_qr_flops", C.c_double), ("q_post_ms", C.c_double)]
 
 
 _SIGS = {

@@ -464,6 +464,27 @@ __global__ void identity_u_kernel(const MatDesc *__restrict__ descs) {
 }
 }  // namespace
 
+// Two HIP events around a stretch of work on a stream.
+struct EvPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  explicit EvPair(hipStream_t s) {
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventRecord(e0, s));
+  }
+  void stop(hipStream_t s) { (void)hipEventRecord(e1, s); }
+  double ms() const {
+    float t = 0.f;
+    return hipEventElapsedTime(&t, e0, e1) == hipSuccess ? (double)t : 0.0;
+  }
+  ~EvPair() {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  EvPair(const EvPair &) = delete;
+  EvPair &operator=(const EvPair &) = delete;
+};
+
 // bytes of n complex entries rounded up to 256 (the arena alignment)
 static size_t arena_bytes(size_t n) { return (n * sizeof(double2) + 255) / 256 * 256; }
 static double2 *arena_at(const DevBuf &b, size_t off) {
@@ -657,8 +678,23 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   hipLaunchKernelGGL(gather_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_in.as<MatDesc>(), g.d_qc.as<MatDesc>(),
                      g.perm.as<int>(), nmax, cscl);
   HIP_CHECK(hipGetLastError());
+  EvPair qre(s);
   qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
+  qre.stop(s);
   if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
+  g.qr_flops = 0.0;
+  for (int w = 0; w < W; ++w) {
+    const double m = in[w].m, n = n2[w];
+    g.qr_flops += 8.0 * m * n * n - 8.0 * n * n * n / 3.0;
+  }
+  EvPair poste(s);
+  struct Finish {   // the QR and post-QR times, however graded_pinv returns
+    GradedPinv &g; EvPair &a, &b; hipStream_t s;
+    ~Finish() {
+      b.stop(s);
+      if (hipStreamSynchronize(s) == hipSuccess) { g.qr_ms = a.ms(); g.post_ms = b.ms(); }
+    }
+  } fin{g, qre, poste, s};
   // the triangle that the row selection and the LQ read: R_1, or with
   // pivoting R from the column-pivoted QR R_1 P_2 = Q_2 R
   const MatDesc *tri = g.d_qc.as<MatDesc>();

@@ -25,6 +25,12 @@ struct GradedPinv {
   double jacobi_bytes = 0.0;
   double jacobi_flops = 0.0;
   int jacobi_unconverged = 0;        // matrices whose Jacobi reached the sweep cap
+  // the unpivoted blocked QR of the ordered columns: time (HIP events) and
+  // algorithmic flops, sum over matrices of 8 m n^2 - 8 n^3 / 3
+  double qr_ms = 0.0, qr_flops = 0.0;
+  // everything after that QR (triangle inverse or pivoted QR, LQ, Jacobi, and
+  // the explicit factors U and W), HIP events
+  double post_ms = 0.0;
   // descriptors for launch_pinv_apply (mode 1): u (m x kept), w (n x kept)
   const MatDesc *apply_descs() const { return d_fin.as<MatDesc>(); }
   // free the factorisation's work, keeping what the apply reads (U in

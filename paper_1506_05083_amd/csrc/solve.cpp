@@ -284,6 +284,9 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       for (double x : S.nsum_alg_bytes) na += x;
       timing->near_alg_bytes = S.nsum_alg_bytes.empty() ? 0.0 : na / (double)S.nsum_alg_bytes.size();
       timing->near_mode = S.near_mode;
+      timing->q_qr_ms = S.gp.qr_ms;
+      timing->q_qr_flops = S.gp.qr_flops;
+      timing->q_post_ms = S.gp.post_ms;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (notconv) {
