@@ -273,6 +273,22 @@ mfs_status mfs_apply_solution_op(const mfs_op *op, int32_t body, int32_t nrhs,
                                  const mfs_c128 *in, int32_t in_layout,
                                  mfs_c128 *out, int32_t out_layout, void *stream);
 
+/* mfs_apply_solution_op without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, layouts, results and
+ * errors as mfs_apply_solution_op; the caller still provides in and out.
+ * Its work memory (the per-mode work buffer, nd x 32 x N complex values for
+ * nd = P/2+1 distinct modes, plus the [nrhs][P][M] / [nrhs][P][N]
+ * intermediates of an ANGLE input / POINTS output) lives in a static 64 MiB
+ * device array that every GPU the library runs on holds until the process
+ * ends; a call that would need more returns EINVAL and writes nothing.  All
+ * calls on one GPU share that array, which keeps the last call's contents:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads) race, so serialise them (one stream, or an external lock). */
+mfs_status mfs_apply_solution_op_noalloc(const mfs_op *op, int32_t body, int32_t nrhs,
+                                         const mfs_c128 *in, int32_t in_layout,
+                                         mfs_c128 *out, int32_t out_layout, void *stream);
+
 /* Right-hand side of eq. (linsys): f = -du^i/dn at the P x M surface points
  * then f_hat_n = (1/P) sum_l f(phi_l) e^{-i n phi_l} (eq. (fhatquad), q = P).
  * For a transmission body [f_hat; f_hat'] of eq. (trans): f = -u^i in rows

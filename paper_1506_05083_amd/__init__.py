@@ -104,6 +104,8 @@ _SIGS = {
     "mfs_set_near_field_budget": (C.c_int, [C.c_void_p, C.c_uint64]),
     "mfs_apply_solution_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                         C.c_void_p, C.c_int32, C.c_void_p]),
+    "mfs_apply_solution_op_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                                C.c_void_p, C.c_int32, C.c_void_p]),
     "mfs_rhs_modes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_void_p, C.c_void_p]),
     "mfs_point_strengths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
@@ -341,6 +343,15 @@ def apply_solution_op(op: Operator, x, body: int = 0, in_layout: int = 0, out_la
     out = torch.empty((x.shape[0], b.P, ncol), dtype=torch.complex128, device=x.device)
     _check(lib().mfs_apply_solution_op(op.h, body, x.shape[0], _dev(x), in_layout, _dev(out), out_layout,
                                        _stream()))
+    return out
+
+
+def apply_solution_op_noalloc(op: Operator, x, out, body: int = 0, in_layout: int = 0, out_layout: int = 0):
+    """apply_solution_op into a caller-provided `out`, with no allocation by
+    the library (its work memory is a static device array shared by the
+    calls on one GPU)."""
+    _check(lib().mfs_apply_solution_op_noalloc(op.h, body, x.shape[0], _dev(x), in_layout, _dev(out), out_layout,
+                                               _stream()))
     return out
 
 
