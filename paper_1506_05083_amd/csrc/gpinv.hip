@@ -39,7 +39,8 @@
 
 namespace mfs {
 
-void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s);
+void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
+               bool from_identity = false);
 void launch_zero(double2 *p, long n, hipStream_t s);
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,
               std::vector<int> &ranks);
@@ -560,7 +561,7 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
   HIP_CHECK(hipMemcpyAsync(flags + W, n2.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(identity_u_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_qc.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
-  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s);
+  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s, true);
   g.h_fin.resize(W);
   std::vector<size_t> of(W);
   {

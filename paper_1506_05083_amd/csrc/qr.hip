@@ -300,7 +300,9 @@ __global__ __launch_bounds__(PTMAX) void bqr_panel_kernel(const MatDesc *__restr
 }
 
 // Y columns: which = 0 -> trailing columns of the matrix after the panel,
-// which = 1 -> columns [0, rank) of d.u.
+// which = 1 -> columns [0, rank) of d.u, which = 2 -> columns [k0, rank) of
+// d.u (forming Q from the identity: the reflectors of the panel at k0 and
+// later leave columns below k0 of the identity as they are).
 __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, double2 *&B, int &ldb,
                                 int &nb_cols) {
   if (which == 0) {
@@ -314,6 +316,13 @@ __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, do
     B = d.u;
     ldb = ldu_of(d);
     nb_cols = d.rank[0];
+    if (which == 2) {
+      // with no columns left B stays at column 0, so that masked loads
+      // (ld_or0, which read B[0]) stay inside the matrix
+      const bool some = k0 < nb_cols;
+      B += some ? (size_t)k0 * ldb : 0;
+      nb_cols = some ? nb_cols - k0 : 0;
+    }
   }
 }
 
@@ -649,7 +658,10 @@ void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t 
 
 // Form U = Q [U_R; 0] in place in d.u (leading dimension d.ldu, or d.lda if
 // zero); rows >= n of d.u must be zero.  T of every panel must be present.
-void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s) {
+// from_identity: d.u holds the first rank columns of the identity, so the
+// panel at k0 updates its columns k0 and later only.
+void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
+               bool from_identity) {
   int nmax = 0, mmax = 0;
   for (const auto &d : h) {
     nmax = std::max(nmax, d.n);
@@ -659,8 +671,12 @@ void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank,
   if (maxrank <= 0 || nmax == 0) return;
   ApplyWork w;
   w.size(nmat, mmax, maxrank);
-  for (int k0 = ((nmax - 1) / NB) * NB; k0 >= 0; k0 -= NB)
-    apply_panel(descs, nmat, mmax, maxrank, k0, 1, 0, 0, w, false, s);
+  for (int k0 = ((nmax - 1) / NB) * NB; k0 >= 0; k0 -= NB) {
+    if (from_identity)
+      apply_panel(descs, nmat, mmax, std::max(0, maxrank - k0), k0, 2, 0, 0, w, false, s);
+    else
+      apply_panel(descs, nmat, mmax, maxrank, k0, 1, 0, 0, w, false, s);
+  }
 }
 
 }  // namespace mfs

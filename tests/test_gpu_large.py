@@ -1,6 +1,6 @@
 """The large configuration at its full size on the GPU: sound-hard cups of
 Fig. 1(c) on the unit lattice at k = 2 pi 13, N = 450, M = 540, P = 144
-(NP = 64800), q = 540, periodizer p = 90, N0 = 30, M1 = 56.  The oracle
+(NP = 64800), q = 540, periodizer z0 = 0.55, p = 90, N0 = 40, M1 = 56.  The oracle
 cannot solve it whole, so it is checked on outputs the oracle computes one
 by one (the modal fill at sampled rows for every mode, the singular values
 of three modes, the on-the-fly neighbour sum at sampled surface targets)
@@ -124,7 +124,9 @@ def test_large_solve_one_wave(large):
         f"GMRES {tm['gmres'] / 1e3:.1f} s")
     assert r.iters < pr.maxit and r.resid <= pr.gmres_tol
     assert np.all(np.isfinite(r.a)) and np.all(np.isfinite(r.b)) and np.all(np.isfinite(r.field))
-    assert r.eps_flux < 1e-6
+    # the periodizer converged to ~1e-10 (worst incidence 7e-11 at GMRES
+    # 1e-12); GMRES to 1e-10 adds its own residual
+    assert max(x.eps_flux for x in res) < 1e-9
 
 
 def test_large_transmission_one_wave(large):
@@ -163,4 +165,4 @@ def test_large_transmission_one_wave(large):
         f"periodizer {tm['periodizer'] / 1e3:.1f} s, GMRES {tm['gmres'] / 1e3:.1f} s")
     assert r.iters < pr.maxit and r.resid <= pr.gmres_tol
     assert np.all(np.isfinite(r.a)) and np.all(np.isfinite(r.b)) and np.all(np.isfinite(r.field))
-    assert r.eps_flux < 1e-6
+    assert r.eps_flux < 1e-8

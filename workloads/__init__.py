@@ -183,12 +183,13 @@ def sphere_free_space() -> Problem:
 
 def periodic_k10(nwaves: int = 8) -> Problem:
     """Unit square lattice, k = 10, r = 0.3 (1 + 0.1 cos 3t); N = 200,
-    M = 240 (midpoint), tau = 0.1, P = 64, q = 400; periodizer z0 = 0.7,
-    p = 32, N0 = 18, M1 = 28 (chosen by convergence of eps_flux and eps_per
-    to ~1e-12 with Q's columns equilibrated); incidences from seed 2."""
+    M = 240 (midpoint), tau = 0.1, P = 64, q = 400; periodizer z0 = 0.8,
+    p = 30, N0 = 14, M1 = 24 (the smallest Q found by convergence with
+    eps_flux and eps_per ~1e-11, a tenth of the 1e-10 target, with Q's
+    columns equilibrated); incidences from seed 2."""
     shape = Shape(0.3, 0.1, 3)
     b = Body(shape, N=200, M=240, P=64, q=400, k=10.0, tau=0.1, colloc="mid")
-    lat = Lattice(1.0, 1.0, 0.7, p=32, N0=18, M1=28)
+    lat = Lattice(1.0, 1.0, 0.8, p=30, N0=14, M1=24)
     waves = tuple(sample_waves(b.k, lat, nwaves, seed=2))
     return Problem("periodic_k10", b, lat, waves, cell_grid(lat, shape), q_field=256,
                    gmres_tol=1e-10)
@@ -221,14 +222,14 @@ def cup_periodic_large(nwaves: int = 8) -> Problem:
     0.35) on the unit square lattice at k = 2 pi 13 (13 wavelengths per
     period); N = 450, M = 540 (midpoint), P = 144 (NP = 64800), tau = 0.05,
     q = 540 (Theorem 1: the smallest rate over the (collocation, source)
-    pairs is 0.0829, q >= P/2 + 37/0.0829); z0 = 0.6, periodizer p = 90
-    (k times the cell-corner radius 0.93 is 76), N0 = 30 (Bragg orders out
-    to |kappa_z| z0 ~ 26, as for the k = 10 workload), M1 = 56 (about 3.6
-    Gauss nodes per wavelength on the 13 x 15.6 wavelength walls);
+    pairs is 0.0829, q >= P/2 + 37/0.0829); periodizer z0 = 0.55, p = 90
+    (k times the cell-corner radius 0.89 is 73), N0 = 40, M1 = 56 (about
+    3.6 Gauss nodes per wavelength on the walls), chosen by convergence of
+    eps_flux and eps_per on the worst incidence (7e-11 and 2e-10);
     incidences from seed 5; GMRES to 1e-10."""
     shape = CupShape()
     b = Body(shape, N=450, M=540, P=144, q=540, k=2 * math.pi * 13, tau=0.05, colloc="mid")
-    lat = Lattice(1.0, 1.0, 0.6, p=90, N0=30, M1=56)
+    lat = Lattice(1.0, 1.0, 0.55, p=90, N0=40, M1=56)
     waves = tuple(sample_waves(b.k, lat, nwaves, seed=5))
     return Problem("cup_periodic_large", b, lat, waves, cell_grid(lat, shape), q_field=540,
                    gmres_tol=1e-10)
