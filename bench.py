@@ -338,6 +338,10 @@ def main():
     ap.add_argument("--large-waves", type=int, default=8,
                     help="incidences of the large-cup measurement (0 skips it)")
     args = ap.parse_args()
+    # stage lines from the library on stderr (the large configuration's
+    # factorisation runs for minutes; its Jacobi sweeps and GMRES iterations
+    # report as they finish)
+    os.environ.setdefault("MFS_PROGRESS", "1")
     if args.only == "batch":
         print(json.dumps(run_batch_build(args.batch_obstacles)))
         return

@@ -130,11 +130,17 @@ _SIGS = {
 
 
 def lib():
-    """Load libmfs.so (raises RuntimeError if it has not been built)."""
+    """Load libmfs.so (raises RuntimeError if it has not been built).
+
+    PyTorch is imported first: its ROCm build brings its own HIP runtime
+    (libamdhip64.so.7), and a process must hold one HIP runtime only (two
+    copies cannot both open the GPU), so libmfs's dependency on
+    libamdhip64.so.7 has to resolve to the copy torch has already loaded."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1506_05083_amd.build`")
+        import torch  # noqa: F401  (loads torch's HIP runtime before libmfs)
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

@@ -40,7 +40,7 @@
 namespace mfs {
 
 void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
-               bool from_identity = false);
+               bool from_identity = false, int nb = kQRNB);
 void launch_zero(double2 *p, long n, hipStream_t s);
 void jac_sort(const MatDesc *descs, const std::vector<MatDesc> &h, double rel_cutoff, hipStream_t s,
               std::vector<int> &ranks);
@@ -561,7 +561,7 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
   HIP_CHECK(hipMemcpyAsync(flags + W, n2.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(identity_u_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_qc.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
-  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s, true);
+  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s, true, g.qr_nb);
   g.h_fin.resize(W);
   std::vector<size_t> of(W);
   {
@@ -650,26 +650,30 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   // one allocation per kind for the whole batch (a matrix's pieces at 256-byte
   // aligned offsets): thousands of matrices cost no allocation each
   std::vector<size_t> oa(W), of(W);
+  // panel width of the blocked QR of the ordered columns, measured for this
+  // size class (qr_tuned_nb)
+  g.qr_nb = qr_tuned_nb(in, s);
+  const int nbq = g.qr_nb;
   {
     size_t ta = 0, tf = 0;
     for (int w = 0; w < W; ++w) {
-      const int ldq = in[w].lda, n = n2[w], npan = cdiv(n, kQRNB);
+      const int ldq = in[w].lda, n = n2[w], npan = cdiv(n, nbq);
       oa[w] = ta;
       ta += arena_bytes((size_t)ldq * n);
       of[w] = tf;
-      tf += arena_bytes((size_t)n + (size_t)npan * kQRNB * kQRNB + (size_t)ldq * n);
+      tf += arena_bytes((size_t)n + (size_t)npan * nbq * nbq + (size_t)ldq * n);
     }
     g.qc_a.alloc(ta);
     g.qc_fac.alloc(tf);
   }
   for (int w = 0; w < W; ++w) {
     const int m = in[w].m, ldq = in[w].lda, n = n2[w];
-    const int npan = cdiv(n, kQRNB);
+    const int npan = cdiv(n, nbq);
     MatDesc d{};
     double2 *p = arena_at(g.qc_fac, of[w]);
     d.a = arena_at(g.qc_a, oa[w]); d.m = m; d.n = n; d.lda = ldq;
     d.tau = p; p += n;
-    d.T = p; p += (size_t)npan * kQRNB * kQRNB;
+    d.T = p; p += (size_t)npan * nbq * nbq;
     d.u = p;
     d.flag = flags + 2 * W + w;   // unused by QR; kept distinct
     d.rank = flags + W + w;       // shared with the Jacobi descriptor (kept rank)
@@ -680,7 +684,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
                      g.perm.as<int>(), nmax, cscl);
   HIP_CHECK(hipGetLastError());
   EvPair qre(s);
-  qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s);
+  qr_factor(g.d_qc.as<MatDesc>(), g.h_qc, s, nbq);
   qre.stop(s);
   if (g.ev_qr_done) HIP_CHECK(hipEventRecord(g.ev_qr_done, s));
   g.qr_flops = 0.0;
@@ -837,7 +841,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     upload_descs(g.d_rqu, g.h_rqu, s);
     qr_form_u(g.d_rqu.as<MatDesc>(), g.h_rqu, kmax, s);
   }
-  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, kmax, s);
+  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, kmax, s, false, nbq);
   qr_form_u(g.d_lq.as<MatDesc>(), g.h_lq, kmax, s);
   g.h_fin.resize(W);
   {

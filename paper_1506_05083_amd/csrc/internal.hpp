@@ -67,7 +67,7 @@ struct MatDesc {
   int ldu;        // leading dimension of u (0: lda)
 };
 
-constexpr int kQRNB = 32;   // Householder panel width
+constexpr int kQRNB = 32;   // Householder panel width where it is not tuned (pivoted triangles, LQ)
 
 // One body of an operator: geometry and its P/2+1 distinct mode blocks.
 // Sound-hard (km = 0): blocks A'_n, rows = M, cols = N.  Transmission
@@ -120,8 +120,13 @@ struct JacStats {
 JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_mode, double rel_cutoff,
                  hipStream_t s);
 
-// batched QR of nmat matrices described by descs (device) / h (host copy)
-void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s);
+// batched QR of nmat matrices described by descs (device) / h (host copy),
+// panels of nb = 16, 32 or 64 columns (each matrix's T holds cdiv(n, nb)
+// nb x nb factors)
+void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s, int nb = kQRNB);
+// the panel width for a batch like h: measured once per size class and GPU
+// model (see qr.hip), or MFS_QR_NB
+int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s);
 
 // y = A^+ x with the kept factors: job layout
 //   mode 0 (one-body blocks): mat d = distinct mode, columns = bins d and P-d

@@ -21,21 +21,24 @@
 //   bqr_update       C -= V W2, 64 x 64 tiles, 4 x 4 outputs per thread.
 // The same three apply kernels with T in place of T^H, run over the panels
 // in reverse, form U = Q [U_R; 0] for the explicit left singular vectors.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+
 #include "internal.hpp"
 
 namespace mfs {
 namespace {
 
-constexpr int NB = kQRNB;   // panel width
 constexpr int CH = 256;     // rows per workgroup in the panel column step
 constexpr int KR = 256;     // rows per workgroup of V^H Y (split-K slice)
 constexpr int KS = 16;      // rows per LDS stage in V^H Y
 constexpr int YT = 128;     // columns of Y per workgroup in V^H Y
 constexpr int WT = 64;      // columns per workgroup in W2 and in the update
 constexpr int UR = 64;      // rows per workgroup in the update
-constexpr int NPART = NB + 1;
-constexpr int SUB = CH / NPART;   // threads per slot summing the chunk partials
-static_assert(SUB >= 1, "a column-step workgroup sums every partial slot");
 
 // element r of Householder vector i of the panel starting at column k0
 __device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
@@ -49,9 +52,13 @@ __device__ inline int ldu_of(const MatDesc &d) { return d.ldu ? d.ldu : d.lda; }
 // Panel column step s (s = -1: partial sums of step 0 only).
 // part: [mat][2][nchmax][NPART] (slot [0].x: |x(2:)|^2, slot 1 + c: x^H a_c)
 // side: [mat][2][NB] row j of the panel columns
+template <int NB>
 __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__ descs, int k0, int s,
                                                      double2 *__restrict__ part, double2 *__restrict__ side,
                                                      int nchmax) {
+  constexpr int NPART = NB + 1;
+  constexpr int SUB = CH / NPART;   // threads per slot summing the chunk partials
+  static_assert(SUB >= 1, "a column-step workgroup sums every partial slot");
   const MatDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -199,7 +206,9 @@ __global__ __launch_bounds__(CH) void bqr_col_kernel(const MatDesc *__restrict__
 // r >= j, |x(2:)|^2 over r > j, LAPACK's zlarfg reflector.
 constexpr int PTMAX = 512;             // threads (rows) of the one-launch panel
 constexpr int PWMAX = PTMAX / 64;
+template <int NB>
 __global__ __launch_bounds__(PTMAX) void bqr_panel_kernel(const MatDesc *__restrict__ descs, int k0) {
+  constexpr int NPART = NB + 1;
   const MatDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -328,8 +337,10 @@ __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, do
 
 // P[mat][kc][i][c] = sum over rows of slice kc of conj(V[r][i]) Y[r][c],
 // Y = [V | B] (withV) or B.  Thread -> V columns vi + 8k, Y columns yj + 32k2.
+template <int NB>
 __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0, int which,
                                                       int withV, double2 *__restrict__ P, int ldp, int nkcmax) {
+  constexpr int VA = NB / 8;   // V columns per thread
   const MatDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -347,9 +358,9 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
   __shared__ double2 Ys[KS][YT + 1];
   const int tid = threadIdx.x;
   const int vi = tid & 7, yj = tid >> 3;
-  double2 acc[4][4];
+  double2 acc[VA][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < VA; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
   for (int r0 = rbeg; r0 < rend; r0 += KS) {
@@ -381,14 +392,13 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
     __syncthreads();
 #pragma unroll 4
     for (int rr = 0; rr < KS; ++rr) {
-      double2 v[4], y[4];
+      double2 v[VA], y[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        v[k] = Vs[rr][vi + 8 * k];
-        y[k] = Ys[rr][yj + 32 * k];
-      }
+      for (int k = 0; k < VA; ++k) v[k] = Vs[rr][vi + 8 * k];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 4; ++k) y[k] = Ys[rr][yj + 32 * k];
+#pragma unroll
+      for (int a = 0; a < VA; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) cfmac(acc[a][b], v[a], y[b]);
     }
@@ -396,7 +406,7 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
   }
   double2 *out = P + ((size_t)blockIdx.z * nkcmax + blockIdx.y) * NB * ldp;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < VA; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int c = c0 + yj + 32 * b;
@@ -406,6 +416,7 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
 
 // T of the panel (forward, columnwise): T[i][i] = tau_i,
 // T[0:i, i] = -tau_i T[0:i, 0:i] (V^H V)[0:i, i]; V^H V from the slices of P.
+template <int NB>
 __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ descs, int k0,
                                                     const double2 *__restrict__ P, int ldp, int nkcmax) {
   const MatDesc d = descs[blockIdx.x];
@@ -456,6 +467,7 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
 
 // W2[mat][i][c] = sum_h op(T)[i][h] W[h][c], W = V^H B summed over the slices;
 // op(T) = T^H (trans, QR) or T.
+template <int NB>
 __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__ descs, int k0, int which,
                                                      int withV, int trans, const double2 *__restrict__ P,
                                                      int ldp, int nkcmax, double2 *__restrict__ W2,
@@ -511,6 +523,7 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
 
 // B[r][c] -= sum_i V[r][i] W2[i][c], rows r >= k0; thread -> rows tx + 16a,
 // columns ty + 16b of a 64 x 64 tile.
+template <int NB>
 __global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restrict__ descs, int k0, int which,
                                                          const double2 *__restrict__ W2, int ldw) {
   const MatDesc d = descs[blockIdx.z];
@@ -595,38 +608,39 @@ __global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restri
 struct ApplyWork {
   DevBuf P, W2;
   int ldp = 0, ldw = 0, nkcmax = 0;
-  void size(int nmat, int mmax, int ncols) {
-    ldp = NB + ncols;
+  void size(int nmat, int mmax, int ncols, int nb) {
+    ldp = nb + ncols;
     ldw = std::max(ncols, 1);
     nkcmax = cdiv(std::max(mmax, 1), KR);
-    P.alloc((size_t)nmat * nkcmax * NB * ldp * sizeof(double2));
-    W2.alloc((size_t)nmat * NB * ldw * sizeof(double2));
+    P.alloc((size_t)nmat * nkcmax * nb * ldp * sizeof(double2));
+    W2.alloc((size_t)nmat * nb * ldw * sizeof(double2));
   }
 };
 
 // C <- (I - V T V^H)^{op} C for the panel at k0 (which/withV/trans as above)
+template <int NB>
 void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0, int which, int withV,
                  int trans, ApplyWork &w, bool build_t, hipStream_t s) {
   const int ny = (withV ? NB : 0) + ncols_max;
   const int nkc = cdiv(std::max(mmax - k0, 1), KR);
   if (ny > 0)
-    hipLaunchKernelGGL(bqr_vhy_kernel, dim3(cdiv(ny, YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
+    hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
                        w.P.as<double2>(), w.ldp, w.nkcmax);
   if (build_t)
-    hipLaunchKernelGGL(bqr_t_kernel, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
+    hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
                        w.nkcmax);
   if (ncols_max > 0) {
-    hipLaunchKernelGGL(bqr_w2_kernel, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
+    hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
                        withV, trans, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw);
-    hipLaunchKernelGGL(bqr_update_kernel, dim3(cdiv(std::max(mmax - k0, 1), UR), cdiv(ncols_max, WT), nmat),
+    hipLaunchKernelGGL(bqr_update_kernel<NB>, dim3(cdiv(std::max(mmax - k0, 1), UR), cdiv(ncols_max, WT), nmat),
                        dim3(256), 0, s, descs, k0, which, w.W2.as<double2>(), w.ldw);
   }
   HIP_CHECK(hipGetLastError());
 }
 
-}  // namespace
-
-void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
+template <int NB>
+void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
+  constexpr int NPART = NB + 1;
   int nmax = 0, mmax = 0;
   for (const auto &d : h) {
     nmax = std::max(nmax, d.n);
@@ -638,30 +652,27 @@ void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t 
   DevBuf part((size_t)nmat * 2 * nchmax * NPART * sizeof(double2));
   DevBuf side((size_t)nmat * 2 * NB * sizeof(double2));
   ApplyWork w;
-  w.size(nmat, mmax, nmax);
+  w.size(nmat, mmax, nmax, NB);
   for (int k0 = 0; k0 < nmax; k0 += NB) {
     const int nbp = std::min(NB, nmax - k0);
     if (mmax - k0 <= PTMAX) {
       // every matrix's remaining rows fit one workgroup: the panel in one launch
       const int threads = round_up(std::max(mmax - k0, 1), 64);
-      hipLaunchKernelGGL(bqr_panel_kernel, dim3(nmat), dim3(threads), 0, s, descs, k0);
+      hipLaunchKernelGGL(bqr_panel_kernel<NB>, dim3(nmat), dim3(threads), 0, s, descs, k0);
     } else {
       const int nch = cdiv(std::max(mmax - k0, 1), CH);
       for (int st = -1; st < nbp; ++st)
-        hipLaunchKernelGGL(bqr_col_kernel, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st, part.as<double2>(),
-                           side.as<double2>(), nchmax);
+        hipLaunchKernelGGL(bqr_col_kernel<NB>, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st,
+                           part.as<double2>(), side.as<double2>(), nchmax);
     }
     HIP_CHECK(hipGetLastError());
-    apply_panel(descs, nmat, mmax, std::max(0, nmax - k0 - NB), k0, 0, 1, 1, w, true, s);
+    apply_panel<NB>(descs, nmat, mmax, std::max(0, nmax - k0 - NB), k0, 0, 1, 1, w, true, s);
   }
 }
 
-// Form U = Q [U_R; 0] in place in d.u (leading dimension d.ldu, or d.lda if
-// zero); rows >= n of d.u must be zero.  T of every panel must be present.
-// from_identity: d.u holds the first rank columns of the identity, so the
-// panel at k0 updates its columns k0 and later only.
-void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
-               bool from_identity) {
+template <int NB>
+void qr_form_u_t(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
+                 bool from_identity) {
   int nmax = 0, mmax = 0;
   for (const auto &d : h) {
     nmax = std::max(nmax, d.n);
@@ -670,12 +681,166 @@ void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank,
   const int nmat = (int)h.size();
   if (maxrank <= 0 || nmax == 0) return;
   ApplyWork w;
-  w.size(nmat, mmax, maxrank);
+  w.size(nmat, mmax, maxrank, NB);
   for (int k0 = ((nmax - 1) / NB) * NB; k0 >= 0; k0 -= NB) {
     if (from_identity)
-      apply_panel(descs, nmat, mmax, std::max(0, maxrank - k0), k0, 2, 0, 0, w, false, s);
+      apply_panel<NB>(descs, nmat, mmax, std::max(0, maxrank - k0), k0, 2, 0, 0, w, false, s);
     else
-      apply_panel(descs, nmat, mmax, maxrank, k0, 1, 0, 0, w, false, s);
+      apply_panel<NB>(descs, nmat, mmax, maxrank, k0, 1, 0, 0, w, false, s);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------- panel width tuner
+// The panel width trades the panel's column steps (one reduction over all
+// rows per column, whatever the width) against the passes of the trailing
+// update over the matrix (one per panel): which wins depends on the
+// matrices' shape and the GPU.  The first batch of a size class (the number
+// of rows and of columns, each rounded to a half octave) on a GPU model
+// times the QR of up to 8 of its matrices with every width and keeps the
+// fastest; later batches of that class reuse it.  MFS_QR_NB = 16, 32 or 64
+// fixes the width; MFS_QR_TUNE_FILE names a file that keeps the choices
+// across processes (one "key width" line per class).
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+int half_octave(int x) { return x <= 1 ? 0 : (int)std::floor(2.0 * std::log2((double)x)); }
+
+std::string tune_key(int mmax, int nmax) {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + "/m" + std::to_string(half_octave(mmax)) + "/n" + std::to_string(half_octave(nmax));
+}
+
+void tune_load() {   // g_tune_mu held
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *f = std::getenv("MFS_QR_TUNE_FILE");
+  if (!f) return;
+  std::FILE *fp = std::fopen(f, "r");
+  if (!fp) return;
+  char key[256];
+  int nb = 0;
+  while (std::fscanf(fp, "%255s %d", key, &nb) == 2)
+    if (nb == 16 || nb == 32 || nb == 64) g_tune[key] = nb;
+  std::fclose(fp);
+}
+
+void tune_store(const std::string &key, int nb) {   // g_tune_mu held
+  g_tune[key] = nb;
+  if (const char *f = std::getenv("MFS_QR_TUNE_FILE")) {
+    if (std::FILE *fp = std::fopen(f, "a")) {
+      std::fprintf(fp, "%s %d\n", key.c_str(), nb);
+      std::fclose(fp);
+    }
+  }
+}
+
+}  // namespace
+
+int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
+  if (const char *e = std::getenv("MFS_QR_NB")) {
+    const int nb = std::atoi(e);
+    MFS_REQUIRE(nb == 16 || nb == 32 || nb == 64, "MFS_QR_NB must be 16, 32 or 64");
+    return nb;
+  }
+  int nmax = 0, mmax = 0;
+  for (const auto &d : h) {
+    nmax = std::max(nmax, d.n);
+    mmax = std::max(mmax, d.m);
+  }
+  if (h.empty() || nmax == 0) return kQRNB;
+  const std::string key = tune_key(mmax, nmax);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load();
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) return it->second;
+  // up to 8 of the batch's largest matrices, copied (the QR works in place)
+  std::vector<int> idx(h.size());
+  for (size_t i = 0; i < h.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+    return (double)h[x].m * h[x].n > (double)h[y].m * h[y].n;
+  });
+  idx.resize(std::min<size_t>(idx.size(), 8));
+  std::vector<MatDesc> hc;
+  std::vector<size_t> off;
+  size_t tot = 0;
+  for (int i : idx) {
+    const MatDesc &d = h[i];
+    off.push_back(tot);
+    // a, tau, and T for the widest panel (cdiv(n, 16) panels of 64 x 64 bound every width)
+    tot += ((size_t)d.lda * d.n + d.n + (size_t)cdiv(d.n, 16) * 64 * 64 + 16) * sizeof(double2);
+  }
+  DevBuf buf(tot), dd;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    const MatDesc &d = h[idx[k]];
+    MatDesc c{};
+    double2 *p = reinterpret_cast<double2 *>(static_cast<char *>(buf.p) + off[k]);
+    c.a = p; c.m = d.m; c.n = d.n; c.lda = d.lda;
+    c.tau = p + (size_t)d.lda * d.n;
+    c.T = c.tau + d.n;
+    hc.push_back(c);
+  }
+  dd.alloc(hc.size() * sizeof(MatDesc));
+  HIP_CHECK(hipMemcpyAsync(dd.p, hc.data(), hc.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  int best = kQRNB;
+  float best_ms = 0.f;
+  std::string report;
+  for (int nb : {16, 32, 64}) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {   // the first run loads the kernels
+      for (size_t k = 0; k < idx.size(); ++k)
+        HIP_CHECK(hipMemcpyAsync(hc[k].a, h[idx[k]].a, (size_t)hc[k].lda * hc[k].n * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipEventRecord(e0, s));
+      qr_factor(dd.as<MatDesc>(), hc, s, nb);
+      HIP_CHECK(hipEventRecord(e1, s));
+      HIP_CHECK(hipEventSynchronize(e1));
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    report += " " + std::to_string(nb) + ": " + std::to_string(ms) + " ms";
+    if (nb == 16 || ms < best_ms) { best = nb; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  progress("QR panel width for %s: %d (%s)", key.c_str(), best, report.c_str());
+  tune_store(key, best);
+  return best;
+}
+
+void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s, int nb) {
+  switch (nb) {
+    case 16: qr_factor_t<16>(descs, h, s); break;
+    case 32: qr_factor_t<32>(descs, h, s); break;
+    case 64: qr_factor_t<64>(descs, h, s); break;
+    default: MFS_THROW(MFS_EINVAL, "QR panel width must be 16, 32 or 64");
+  }
+}
+
+// Form U = Q [U_R; 0] in place in d.u (leading dimension d.ldu, or d.lda if
+// zero); rows >= n of d.u must be zero.  T of every panel (of width nb, the
+// width the QR ran with) must be present.  from_identity: d.u holds the
+// first rank columns of the identity, so the panel at k0 updates its
+// columns k0 and later only.
+void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
+               bool from_identity, int nb) {
+  switch (nb) {
+    case 16: qr_form_u_t<16>(descs, h, maxrank, s, from_identity); break;
+    case 32: qr_form_u_t<32>(descs, h, maxrank, s, from_identity); break;
+    case 64: qr_form_u_t<64>(descs, h, maxrank, s, from_identity); break;
+    default: MFS_THROW(MFS_EINVAL, "QR panel width must be 16, 32 or 64");
   }
 }
 

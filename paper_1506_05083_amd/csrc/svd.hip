@@ -731,6 +731,8 @@ JacStats jac_run_t(const MatDesc *descs, const std::vector<MatDesc> &h, int init
     if (dbg)
       fprintf(stderr, "[jacobi] nmat %d n %d sweep %d active %d rotating tasks %ld checked %ld\n", nmat, nmax,
               sweep, nact, nrot, nchecked);
+    progress("Jacobi sweep %d (%d matrices, up to %d columns): %d still rotating, %.0f ms", sweep + 1, nmat, nmax,
+             nact, ms);
     if (!any) break;
   }
   // matrices that still rotated in the last sweep allowed did not converge

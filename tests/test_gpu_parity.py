@@ -312,6 +312,35 @@ def test_wide_jacobi_blocks(mfs, ctx, small_oracle, monkeypatch):
         assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
 
 
+@pytest.mark.parametrize("nb", [16, 32, 64])
+def test_qr_panel_widths(mfs, ctx, small_oracle, monkeypatch, nb):
+    """Every panel width the QR tuner can pick (16, 32, 64), forced through
+    MFS_QR_NB: the one-body factors' singular values against LAPACK on the
+    GPU's own blocks and, with the periodizer Q factored at that width too,
+    the periodic solve against the oracle (amplitudes and fields 1e-10)."""
+    pr, g, out = small_oracle
+    b = pr.body
+    monkeypatch.setenv("MFS_QR_NB", str(nb))
+    op = make_op(mfs, ctx, b)
+    blocks = op.blocks().cpu().numpy().transpose(0, 2, 1)
+    op.factor_modes(1e-10)
+    sv = op.singular_values(0)
+    e = 0.0
+    for n in range(blocks.shape[0]):
+        s_own = np.linalg.svd(blocks[n], compute_uv=False)
+        e = max(e, float(np.max(np.abs(sv[n][: s_own.size] - s_own)) / s_own[0]))
+    res = mfs.solve_incident(ctx, op, _lat(mfs, pr.lattice), [(w.theta, w.phi) for w in pr.waves], tol=1e-12,
+                             maxit=100, targets=pr.targets, q_field=pr.q_field)
+    for i, r in enumerate(res):
+        o = out[i]
+        ea = np.max(np.abs(r.a - o["res"]["a"])) / np.max(np.abs(o["res"]["a"]))
+        eb = np.max(np.abs(r.b - o["res"]["b"])) / np.max(np.abs(o["res"]["b"]))
+        eu = np.linalg.norm(r.field - o["u"]) / np.linalg.norm(o["u"])
+        log(f"[qr nb={nb}] sv {e:.2e} wave {i} a {ea:.2e} b {eb:.2e} u {eu:.2e}")
+        assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+    assert e < 1e-13
+
+
 def test_sixteen_wave_batch_matches_small_batches(mfs, ctx):
     """Twelve incidences in one batched solve (the stored-field sums then run
     with 16 right-hand sides: the matrix-core mirror form with two column
