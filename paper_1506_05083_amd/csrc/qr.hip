@@ -335,18 +335,44 @@ __device__ inline void y_source(const MatDesc &d, int k0, int nbp, int which, do
   }
 }
 
+// Element (r, c) of Y = [V | B] (the nv = NB columns of the panel's
+// Householder vectors first when withV, then the ny - nv columns of B),
+// zero for rows r >= rend and columns c >= ny: one load, whose base is a
+// column inside its matrix also when the element is masked (ld_or0 then
+// reads the base's first element).
+__device__ inline double2 yel(const MatDesc &d, int k0, int nv, const double2 *B, int ldb, int ny, int r, int c,
+                              int rend) {
+  const bool isv = c < nv;
+  const int vc = k0 + c;   // matrix column of a V column
+  const bool vin = isv && vc < d.n;
+  const double2 *p = isv ? d.a + (size_t)(vin ? vc : 0) * d.lda : B + (size_t)(c < ny ? c - nv : 0) * ldb;
+  const bool ok = r < rend && (isv ? (vin && r > vc) : c < ny);
+  const double2 x = ld_or0(p, r, ok);
+  return csel(vin && r == vc && r < rend, cz(1.0, 0.0), x);
+}
+
 // P[mat][kc][i][c] = sum over rows of slice kc of conj(V[r][i]) Y[r][c],
-// Y = [V | B] (withV) or B.  Thread -> V columns vi + 8k, Y columns yj + 32k2.
+// Y = [V | B] (withV) or B, on the FP64 matrix cores.  The slice's rows are
+// staged through LDS KS at a time (coalesced loads down the columns); a
+// 16 x 16 tile of P is one v_mfma_f64_16x16x4f64 chain per real product
+// (four per complex one), the NB x YT tile of the workgroup split over its
+// four waves so that a wave keeps one 16-row block of V^H: NB = 64, one
+// block and 8 column blocks a wave; 32, 4; 16, 2.  cend (which = 0): the
+// trailing columns end before matrix column cend.
 template <int NB>
 __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0, int which,
-                                                      int withV, double2 *__restrict__ P, int ldp, int nkcmax) {
-  constexpr int VA = NB / 8;   // V columns per thread
+                                                      int withV, int cend, double2 *__restrict__ P, int ldp,
+                                                      int nkcmax) {
+  constexpr int CB = YT / 16;                 // 16-column blocks of the tile
+  constexpr int TPW = (NB / 16) * CB / 4;     // 16 x 16 tiles per wave
+  static_assert(TPW >= 1 && TPW <= CB && CB % TPW == 0, "a wave's tiles share one row block");
   const MatDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
   double2 *B;
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
   const int nv = withV ? NB : 0;
   const int ny = nv + max(nb_cols, 0);
   const int c0 = blockIdx.x * YT;
@@ -356,15 +382,19 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
   const int rend = min(d.m, rbeg + KR);
   __shared__ double2 Vs[KS][NB + 1];
   __shared__ double2 Ys[KS][YT + 1];
-  const int tid = threadIdx.x;
-  const int vi = tid & 7, yj = tid >> 3;
-  double2 acc[VA][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const int ib = (wv * TPW) / CB, cb0 = (wv * TPW) % CB;
+  dx4 re[TPW], im[TPW];
 #pragma unroll
-  for (int a = 0; a < VA; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
-  for (int r0 = rbeg; r0 < rend; r0 += KS) {
-    double2 vv[KS * NB / 256], yy[KS * YT / 256];
+  for (int u = 0; u < TPW; ++u) {
+    re[u] = dx4{0.0, 0.0, 0.0, 0.0};
+    im[u] = re[u];
+  }
+  // stage r0's rows in registers (coalesced down the columns); the next
+  // stage's loads are issued before the current stage's products
+  double2 vv[KS * NB / 256], yy[KS * YT / 256];
+  auto load_stage = [&](int r0) {
 #pragma unroll
     for (int u = 0; u < KS * NB / 256; ++u) {
       const int idx = tid + 256 * u, rr = idx % KS, i = idx / KS;
@@ -374,11 +404,11 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
 #pragma unroll
     for (int u = 0; u < KS * YT / 256; ++u) {
       const int idx = tid + 256 * u, rr = idx % KS, cc = idx / KS;
-      const int r = r0 + rr, c = c0 + cc;
-      const double2 yv = vel(d, k0, c < nv ? c : 0, r);
-      const double2 yb = ld_or0(B, (size_t)(c - nv) * ldb + r, r < rend && c >= nv && c < ny);
-      yy[u] = csel(r < rend && c < nv, yv, yb);
+      yy[u] = yel(d, k0, nv, B, ldb, ny, r0 + rr, c0 + cc, rend);
     }
+  };
+  load_stage(rbeg);
+  for (int r0 = rbeg; r0 < rend; r0 += KS) {
 #pragma unroll
     for (int u = 0; u < KS * NB / 256; ++u) {
       const int idx = tid + 256 * u;
@@ -390,35 +420,43 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
       Ys[idx % KS][idx / KS] = yy[u];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < KS; ++rr) {
-      double2 v[VA], y[4];
+    if (r0 + KS < rend) load_stage(r0 + KS);
 #pragma unroll
-      for (int k = 0; k < VA; ++k) v[k] = Vs[rr][vi + 8 * k];
+    for (int kk = 0; kk < KS; kk += 4) {
+      // A[i][k] = conj(V[row k][col i]) (lane l16 + 16 k4 holds A[l16][k4]),
+      // B[k][c] = Y[row k][col c]
+      const double2 a = Vs[kk + k4][16 * ib + l16];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) y[k] = Ys[rr][yj + 32 * k];
-#pragma unroll
-      for (int a = 0; a < VA; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) cfmac(acc[a][b], v[a], y[b]);
+      for (int u = 0; u < TPW; ++u) {
+        const double2 y = Ys[kk + k4][16 * (cb0 + u) + l16];
+        re[u] = mfma_f64(a.x, y.x, re[u]);
+        re[u] = mfma_f64(a.y, y.y, re[u]);
+        im[u] = mfma_f64(a.x, y.y, im[u]);
+        im[u] = mfma_f64(-a.y, y.x, im[u]);
+      }
     }
     __syncthreads();
   }
+  // lane l16 + 16 k4 holds P[16 ib + k4 + 4 v][column block's l16] in element v
   double2 *out = P + ((size_t)blockIdx.z * nkcmax + blockIdx.y) * NB * ldp;
 #pragma unroll
-  for (int a = 0; a < VA; ++a)
+  for (int u = 0; u < TPW; ++u) {
+    const int c = c0 + 16 * (cb0 + u) + l16;
+    if (c < ny) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int c = c0 + yj + 32 * b;
-      if (c < ny) out[(size_t)(vi + 8 * a) * ldp + c] = acc[a][b];
+      for (int v = 0; v < 4; ++v) out[(size_t)(16 * ib + k4 + 4 * v) * ldp + c] = cz(re[u][v], im[u][v]);
     }
+  }
 }
 
 // T of the panel (forward, columnwise): T[i][i] = tau_i,
 // T[0:i, i] = -tau_i T[0:i, 0:i] (V^H V)[0:i, i]; V^H V from the slices of P.
+// Written to the matrix's T of panel k0 / NB, or to Tx[mat] if Tx is set
+// (an inner panel's T, needed only until its update is done).
 template <int NB>
 __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ descs, int k0,
-                                                    const double2 *__restrict__ P, int ldp, int nkcmax) {
+                                                    const double2 *__restrict__ P, int ldp, int nkcmax,
+                                                    double2 *__restrict__ Tx) {
   const MatDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -458,7 +496,7 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
     if (tid == i) Tsh[i][i] = ti;
     __syncthreads();
   }
-  double2 *T = d.T + (size_t)(k0 / NB) * NB * NB;
+  double2 *T = Tx ? Tx + (size_t)blockIdx.x * NB * NB : d.T + (size_t)(k0 / NB) * NB * NB;
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int r = idx % NB, c = idx / NB;
     T[idx] = (r <= c && c < nbp) ? Tsh[r][c] : cz(0.0, 0.0);
@@ -466,18 +504,20 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
 }
 
 // W2[mat][i][c] = sum_h op(T)[i][h] W[h][c], W = V^H B summed over the slices;
-// op(T) = T^H (trans, QR) or T.
+// op(T) = T^H (trans, QR) or T; T from Tx[mat] if Tx is set (bqr_t_kernel).
 template <int NB>
 __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__ descs, int k0, int which,
-                                                     int withV, int trans, const double2 *__restrict__ P,
-                                                     int ldp, int nkcmax, double2 *__restrict__ W2,
-                                                     int ldw) {
+                                                     int withV, int trans, int cend,
+                                                     const double2 *__restrict__ P, int ldp, int nkcmax,
+                                                     double2 *__restrict__ W2, int ldw,
+                                                     const double2 *__restrict__ Tx) {
   const MatDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
   double2 *B;
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
   const int c0 = blockIdx.x * WT;
   if (c0 >= nb_cols) return;
   const int nv = withV ? NB : 0;
@@ -485,7 +525,7 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
   __shared__ double2 Ts[NB][NB + 1];
   __shared__ double2 Ws[NB][WT + 1];
   const int tid = threadIdx.x;
-  const double2 *T = d.T + (size_t)(k0 / NB) * NB * NB;
+  const double2 *T = Tx ? Tx + (size_t)blockIdx.y * NB * NB : d.T + (size_t)(k0 / NB) * NB * NB;
   for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = T[idx];
   const double2 *base = P + (size_t)blockIdx.y * nkcmax * NB * ldp;
   {
@@ -521,86 +561,70 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
   }
 }
 
-// B[r][c] -= sum_i V[r][i] W2[i][c], rows r >= k0; thread -> rows tx + 16a,
-// columns ty + 16b of a 64 x 64 tile.
+// B[r][c] -= sum_i V[r][i] W2[i][c], rows r >= k0, on the FP64 matrix cores,
+// formed transposed so that a fragment row of the product is a column of B
+// (16 consecutive rows per lane group: 256-byte segments):
+// D[c][r] = sum_i W2[i][c] V[r][i].  Workgroup: a 64 x 64 tile of B; wave
+// w takes its columns c0 + 16 w .. + 15 and all 64 rows (four 16-row
+// blocks, four real products each per 4-step of i).  V and W2 come
+// straight from global memory (L2: every wave and every column tile of the
+// panel reads the same V).  cend (which = 0): the trailing columns end
+// before matrix column cend.
 template <int NB>
 __global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restrict__ descs, int k0, int which,
-                                                         const double2 *__restrict__ W2, int ldw) {
+                                                         int cend, const double2 *__restrict__ W2, int ldw) {
   const MatDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
   double2 *B;
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
+  if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
   const int c0 = blockIdx.y * WT;
   if (c0 >= nb_cols) return;
   const int r0 = k0 + blockIdx.x * UR;
   if (r0 >= d.m) return;
-  __shared__ double2 Vs[UR][NB + 1];
-  __shared__ double2 Ws[NB][WT + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  // the tile of B is fetched first, its latency hidden behind the product
-  double2 cv[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const int cw = c0 + 16 * wv;   // this wave's first column (no barriers: an idle wave may leave)
+  if (cw >= nb_cols) return;
+  const double2 *w2 = W2 + (size_t)blockIdx.z * NB * ldw;
+  constexpr int RB = UR / 16;
+  dx4 re[RB], im[RB];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int c = c0 + ty + 16 * b, r = r0 + tx + 16 * a;
-      cv[a][b] = ld_or0(B, (size_t)c * ldb + r, c < nb_cols && r < d.m);
-    }
-  {
-    double2 vv[UR * NB / 256], ww[NB * WT / 256];
-    const double2 *w = W2 + (size_t)blockIdx.z * NB * ldw;
-#pragma unroll
-    for (int u = 0; u < UR * NB / 256; ++u) {
-      const int idx = tid + 256 * u, rr = idx % UR, i = idx / UR;
-      vv[u] = vel(d, k0, i, r0 + rr);   // zero for rows >= m
-    }
-#pragma unroll
-    for (int u = 0; u < NB * WT / 256; ++u) {
-      const int idx = tid + 256 * u, cc = idx % WT, i = idx / WT;
-      ww[u] = ld_or0(w, (size_t)i * ldw + c0 + cc, c0 + cc < nb_cols);
-    }
-#pragma unroll
-    for (int u = 0; u < UR * NB / 256; ++u) {
-      const int idx = tid + 256 * u;
-      Vs[idx % UR][idx / UR] = vv[u];
-    }
-#pragma unroll
-    for (int u = 0; u < NB * WT / 256; ++u) {
-      const int idx = tid + 256 * u;
-      Ws[idx / WT][idx % WT] = ww[u];
-    }
+  for (int rb = 0; rb < RB; ++rb) {
+    re[rb] = dx4{0.0, 0.0, 0.0, 0.0};
+    im[rb] = re[rb];
   }
-  __syncthreads();
-  double2 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
 #pragma unroll 4
-  for (int i = 0; i < NB; ++i) {
-    double2 v[4], x[4];
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const int i = 4 * ks + k4;
+    // A[c][i] = W2[i][c] (lane l16 + 16 k4 holds A[l16][k4]); B[i][r] = V[r][i]
+    const double2 a = ld_or0(w2, (size_t)i * ldw + cw + l16, cw + l16 < nb_cols);
+    double2 v[RB];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = Vs[tx + 16 * k][i];
-      x[k] = Ws[i][ty + 16 * k];
+    for (int rb = 0; rb < RB; ++rb) v[rb] = vel(d, k0, i, r0 + 16 * rb + l16);   // zero for rows >= m
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      re[rb] = mfma_f64(a.x, v[rb].x, re[rb]);
+      re[rb] = mfma_f64(-a.y, v[rb].y, re[rb]);
+      im[rb] = mfma_f64(a.x, v[rb].y, im[rb]);
+      im[rb] = mfma_f64(a.y, v[rb].x, im[rb]);
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) cfma(acc[a][b], v[a], x[b]);
   }
+  // lane l16 + 16 k4 holds D[k4 + 4 e][l16] in element e: column cw + k4 + 4 e, row r0 + 16 rb + l16
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int c = c0 + ty + 16 * b;
+  for (int e = 0; e < 4; ++e) {
+    const int c = cw + k4 + 4 * e;
     if (c >= nb_cols) continue;
     double2 *col = B + (size_t)c * ldb;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = r0 + tx + 16 * a;
-      if (r < d.m) col[r] = csub(cv[a][b], acc[a][b]);
+    for (int rb = 0; rb < RB; ++rb) {
+      const int r = r0 + 16 * rb + l16;
+      if (r < d.m) {
+        const double2 x = col[r];
+        col[r] = cz(x.x - re[rb][e], x.y - im[rb][e]);
+      }
     }
   }
 }
@@ -617,30 +641,67 @@ struct ApplyWork {
   }
 };
 
-// C <- (I - V T V^H)^{op} C for the panel at k0 (which/withV/trans as above)
+// C <- (I - V T V^H)^{op} C for the panel at k0 (which/withV/trans as above).
+// cend: with which = 0, the trailing columns end before matrix column cend;
+// Tx: T of the panel to and from Tx[mat] instead of the matrix's T.
+constexpr int kNoEnd = 0x7fffffff;
 template <int NB>
 void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0, int which, int withV,
-                 int trans, ApplyWork &w, bool build_t, hipStream_t s) {
+                 int trans, ApplyWork &w, bool build_t, hipStream_t s, int cend = kNoEnd,
+                 double2 *Tx = nullptr) {
   const int ny = (withV ? NB : 0) + ncols_max;
   const int nkc = cdiv(std::max(mmax - k0, 1), KR);
   if (ny > 0)
     hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
-                       w.P.as<double2>(), w.ldp, w.nkcmax);
+                       cend, w.P.as<double2>(), w.ldp, w.nkcmax);
   if (build_t)
     hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
-                       w.nkcmax);
+                       w.nkcmax, Tx);
   if (ncols_max > 0) {
     hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
-                       withV, trans, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw);
+                       withV, trans, cend, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw, Tx);
     hipLaunchKernelGGL(bqr_update_kernel<NB>, dim3(cdiv(std::max(mmax - k0, 1), UR), cdiv(ncols_max, WT), nmat),
-                       dim3(256), 0, s, descs, k0, which, w.W2.as<double2>(), w.ldw);
+                       dim3(256), 0, s, descs, k0, which, cend, w.W2.as<double2>(), w.ldw);
   }
   HIP_CHECK(hipGetLastError());
 }
 
+// Householder vectors and tau of the columns [k0, k0 + NI) (NI = 16), the
+// column steps of bqr_col_kernel or the one-launch bqr_panel_kernel
+struct PanelWork {
+  static constexpr int NI = 16;
+  DevBuf part, side;
+  int nchmax = 0;
+  void size(int nmat, int mmax) {
+    nchmax = cdiv(mmax, CH);
+    part.alloc((size_t)nmat * 2 * nchmax * (NI + 1) * sizeof(double2));
+    side.alloc((size_t)nmat * 2 * NI * sizeof(double2));
+  }
+  void factor(const MatDesc *descs, int nmat, int mmax, int nmax, int k0, hipStream_t s) {
+    const int nbp = std::min(NI, nmax - k0);
+    if (mmax - k0 <= PTMAX) {
+      // every matrix's remaining rows fit one workgroup: the panel in one launch
+      const int threads = round_up(std::max(mmax - k0, 1), 64);
+      hipLaunchKernelGGL(bqr_panel_kernel<NI>, dim3(nmat), dim3(threads), 0, s, descs, k0);
+    } else {
+      const int nch = cdiv(std::max(mmax - k0, 1), CH);
+      for (int st = -1; st < nbp; ++st)
+        hipLaunchKernelGGL(bqr_col_kernel<NI>, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st,
+                           part.as<double2>(), side.as<double2>(), nchmax);
+    }
+    HIP_CHECK(hipGetLastError());
+  }
+};
+
+// Two-level blocking: panels of NB columns (the block reflector whose T the
+// matrix keeps and whose trailing update is one pass over the matrix)
+// factored as NB / 16 inner panels of 16 columns, each applied only to the
+// rest of its NB-column panel (its T in a scratch buffer).  NB = 16 is the
+// plain one-level form.
 template <int NB>
 void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
-  constexpr int NPART = NB + 1;
+  constexpr int NI = PanelWork::NI;
+  static_assert(NB % NI == 0, "outer panels are whole inner panels");
   int nmax = 0, mmax = 0;
   for (const auto &d : h) {
     nmax = std::max(nmax, d.n);
@@ -648,25 +709,23 @@ void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_
   }
   const int nmat = (int)h.size();
   if (nmax == 0 || nmat == 0) return;
-  const int nchmax = cdiv(mmax, CH);
-  DevBuf part((size_t)nmat * 2 * nchmax * NPART * sizeof(double2));
-  DevBuf side((size_t)nmat * 2 * NB * sizeof(double2));
-  ApplyWork w;
+  PanelWork pw;
+  pw.size(nmat, mmax);
+  ApplyWork w, wi;
   w.size(nmat, mmax, nmax, NB);
-  for (int k0 = 0; k0 < nmax; k0 += NB) {
-    const int nbp = std::min(NB, nmax - k0);
-    if (mmax - k0 <= PTMAX) {
-      // every matrix's remaining rows fit one workgroup: the panel in one launch
-      const int threads = round_up(std::max(mmax - k0, 1), 64);
-      hipLaunchKernelGGL(bqr_panel_kernel<NB>, dim3(nmat), dim3(threads), 0, s, descs, k0);
-    } else {
-      const int nch = cdiv(std::max(mmax - k0, 1), CH);
-      for (int st = -1; st < nbp; ++st)
-        hipLaunchKernelGGL(bqr_col_kernel<NB>, dim3(nch, nmat), dim3(CH), 0, s, descs, k0, st,
-                           part.as<double2>(), side.as<double2>(), nchmax);
+  DevBuf tx;
+  if (NB > NI) {
+    wi.size(nmat, mmax, NB - NI, NI);
+    tx.alloc((size_t)nmat * NI * NI * sizeof(double2));
+  }
+  for (int K0 = 0; K0 < nmax; K0 += NB) {
+    for (int k0 = K0; k0 < std::min(K0 + NB, nmax); k0 += NI) {
+      pw.factor(descs, nmat, mmax, nmax, k0, s);
+      const int rest = std::min(K0 + NB, nmax) - (k0 + NI);   // inner columns still to update
+      if (NB > NI && rest > 0)
+        apply_panel<NI>(descs, nmat, mmax, rest, k0, 0, 1, 1, wi, true, s, K0 + NB, tx.as<double2>());
     }
-    HIP_CHECK(hipGetLastError());
-    apply_panel<NB>(descs, nmat, mmax, std::max(0, nmax - k0 - NB), k0, 0, 1, 1, w, true, s);
+    apply_panel<NB>(descs, nmat, mmax, std::max(0, nmax - K0 - NB), K0, 0, 1, 1, w, true, s);
   }
 }
 
@@ -764,13 +823,23 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
   tune_load();
   auto it = g_tune.find(key);
   if (it != g_tune.end()) return it->second;
-  // up to 8 of the batch's largest matrices, copied (the QR works in place)
+  // the batch's largest matrices, copied (the QR works in place): up to 8,
+  // and no more than 2^25 elements in all once the first is taken
   std::vector<int> idx(h.size());
   for (size_t i = 0; i < h.size(); ++i) idx[i] = (int)i;
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
     return (double)h[x].m * h[x].n > (double)h[y].m * h[y].n;
   });
-  idx.resize(std::min<size_t>(idx.size(), 8));
+  {
+    size_t keep = 0, elems = 0;
+    while (keep < idx.size() && keep < 8) {
+      const size_t e = (size_t)h[idx[keep]].lda * h[idx[keep]].n;
+      if (keep > 0 && elems + e > ((size_t)1 << 25)) break;
+      elems += e;
+      ++keep;
+    }
+    idx.resize(keep);
+  }
   std::vector<MatDesc> hc;
   std::vector<size_t> off;
   size_t tot = 0;
@@ -800,7 +869,9 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
   std::string report;
   for (int nb : {16, 32, 64}) {
     float ms = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {   // the first run loads the kernels
+    // the first run loads the kernels; it is repeated unless it ran long
+    // enough (50 ms) for the load to be lost in it
+    for (int rep = 0; rep < 2 && (rep == 0 || ms < 50.f); ++rep) {
       for (size_t k = 0; k < idx.size(); ++k)
         HIP_CHECK(hipMemcpyAsync(hc[k].a, h[idx[k]].a, (size_t)hc[k].lda * hc[k].n * sizeof(double2),
                                  hipMemcpyDeviceToDevice, s));
@@ -834,14 +905,48 @@ void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t 
 // width the QR ran with) must be present.  from_identity: d.u holds the
 // first rank columns of the identity, so the panel at k0 updates its
 // columns k0 and later only.
+//
+// Forming U is all trailing-update work (no panel to factor), so it always
+// runs with 64-column block reflectors, whatever width the QR ran with:
+// for a QR of panels of 16 or 32 columns, T of every 64 consecutive
+// reflectors is formed first from their Householder vectors and tau
+// (V^H V and the forward recurrence, as bqr_t_kernel does after a panel)
+// into a buffer of its own, and U is formed with those.
 void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
                bool from_identity, int nb) {
-  switch (nb) {
-    case 16: qr_form_u_t<16>(descs, h, maxrank, s, from_identity); break;
-    case 32: qr_form_u_t<32>(descs, h, maxrank, s, from_identity); break;
-    case 64: qr_form_u_t<64>(descs, h, maxrank, s, from_identity); break;
-    default: MFS_THROW(MFS_EINVAL, "QR panel width must be 16, 32 or 64");
+  MFS_REQUIRE(nb == 16 || nb == 32 || nb == 64, "QR panel width must be 16, 32 or 64");
+  int nmax = 0, mmax = 0;
+  for (const auto &d : h) {
+    nmax = std::max(nmax, d.n);
+    mmax = std::max(mmax, d.m);
   }
+  const int nmat = (int)h.size();
+  if (maxrank <= 0 || nmax == 0 || nmat == 0) return;
+  if (nb == 64 || nmax <= nb) {
+    switch (nb) {
+      case 16: qr_form_u_t<16>(descs, h, maxrank, s, from_identity); break;
+      case 32: qr_form_u_t<32>(descs, h, maxrank, s, from_identity); break;
+      default: qr_form_u_t<64>(descs, h, maxrank, s, from_identity); break;
+    }
+    return;
+  }
+  std::vector<MatDesc> h2(h);
+  std::vector<size_t> off(nmat);
+  size_t tot = 0;
+  for (int i = 0; i < nmat; ++i) {
+    off[i] = tot;
+    tot += (size_t)cdiv(std::max(h[i].n, 1), 64) * 64 * 64;
+  }
+  DevBuf t64(tot * sizeof(double2)), d2(nmat * sizeof(MatDesc));
+  for (int i = 0; i < nmat; ++i) h2[i].T = t64.as<double2>() + off[i];
+  HIP_CHECK(hipMemcpyAsync(d2.p, h2.data(), nmat * sizeof(MatDesc), hipMemcpyHostToDevice, s));
+  {
+    ApplyWork w;
+    w.size(nmat, mmax, 0, 64);
+    for (int k0 = 0; k0 < nmax; k0 += 64)   // V^H V of the group only (no trailing columns), then T
+      apply_panel<64>(d2.as<MatDesc>(), nmat, mmax, 0, k0, 0, 1, 1, w, true, s, k0 + 64);
+  }
+  qr_form_u_t<64>(d2.as<MatDesc>(), h2, maxrank, s, from_identity);
 }
 
 }  // namespace mfs
