@@ -449,7 +449,8 @@ def main():
         "batch_solve_ms_p50": float(np.percentile(solve_ms, 50)),
         "batch_solve_ms_p99": float(np.percentile(solve_ms, 99)),
         "step_ms_max": float(max(1e3 * r[4] for r in recs)),
-        "near_field": {0: "on the fly (budget 0)", 1: "stored", 2: "on the fly (did not fit)"}[near_modes[-1]],
+        "near_field": {0: "on the fly (budget 0)", 1: "stored", 2: "on the fly (did not fit)",
+                       3: "low-rank image blocks (did not fit)"}[near_modes[-1]],
         "stage_ms": {k: float(np.median([t[k] for t in tms])) for k in ("rhs", "periodizer", "gmres", "recover")},
         "gmres_iters": [r.iters for r in res],
         "eps_flux_max": float(max(r.eps_flux for r in res)),

@@ -155,7 +155,12 @@ typedef struct {
                              tile of each group: the values the method needs */
   int32_t near_mode;      /* 0: sums evaluated on the fly (budget 0); 1: stored
                              near field; 2: on the fly because the stored field
-                             did not fit the budget or the free device memory */
+                             did not fit the budget or the free device memory;
+                             3: it did not fit, and the surface sums use
+                             low-rank factors of the image blocks (the wall
+                             sums on the fly); near_fill_ms is then the time
+                             to build the factors (0 if an earlier solve on
+                             the same lattice built them)                    */
   double q_qr_ms;         /* blocked Householder QR of the waves' Q (one batch) */
   double q_qr_flops;      /* its algorithmic flops, sum of 8 m n^2 - 8 n^3 / 3  */
   double q_post_ms;       /* the rest of Q^+: triangle inverse (or the SVD path)
@@ -240,7 +245,13 @@ mfs_status mfs_op_timing(const mfs_op *op, double *ms);
 
 /* Singular values (descending) of the distinct blocks of one body, host
  * out [P/2+1][N] ([P/2+1][2N] for a transmission body).  ESTATE before
- * mfs_factor_modes. */
+ * mfs_factor_modes.  All zero when the environment set MFS_OPINV=cod for
+ * the factorisation: the truncated pseudoinverses were then taken as
+ * complete orthogonal decompositions (pivoted QR of the triangle, cut where
+ * the trailing block's Frobenius norm falls to rel_cutoff times the largest
+ * singular value, then the inverse of its LQ factor), which form none; the
+ * ranks are those kept by that cut.  The periodizer's Q takes that form by
+ * default from 4096 kept columns on (MFS_QPINV=svd or cod decides). */
 mfs_status mfs_op_singular_values(const mfs_op *op, int32_t body, double *out);
 
 /* Layouts of mfs_apply_solution_op. */

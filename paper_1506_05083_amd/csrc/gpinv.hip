@@ -35,6 +35,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <string>
+
 #include "gpinv.hpp"
 
 namespace mfs {
@@ -68,6 +70,50 @@ __global__ void gather_kernel(const MatDesc *__restrict__ src, const MatDesc *__
   const int c = perm[(size_t)blockIdx.y * ldp + i];
   const double f = scale ? scale[(size_t)blockIdx.y * ldp + c] : 1.0;
   for (int r = threadIdx.x; r < d.m; r += blockDim.x) d.a[(size_t)i * d.lda + r] = cscale(s.a[(size_t)c * s.lda + r], f);
+}
+
+// y = R x, R = triu(a[0:n, 0:n]) (thread per row; a column's rows are
+// contiguous, so each step over j is one coalesced read)
+__global__ void trimv_kernel(const MatDesc *__restrict__ d, const double2 *__restrict__ x,
+                             double2 *__restrict__ y, int ld) {
+  const MatDesc m = d[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.x * blockDim.x;
+  if (j0 >= m.n) return;
+  const double2 *xw = x + (size_t)blockIdx.y * ld;
+  double2 acc = cz(0.0, 0.0);
+  for (int j = j0; j < m.n; ++j)
+    if (i < m.n && j >= i) cfma(acc, m.a[(size_t)j * m.lda + i], xw[j]);
+  if (i < m.n) y[(size_t)blockIdx.y * ld + i] = acc;
+}
+
+// z = R^H y (one wave per column j: sum over rows i <= j of conj(R_ij) y_i)
+__global__ __launch_bounds__(256) void trimhv_kernel(const MatDesc *__restrict__ d, const double2 *__restrict__ y,
+                                                     double2 *__restrict__ z, int ld) {
+  const MatDesc m = d[blockIdx.y];
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= m.n) return;
+  const double2 *yw = y + (size_t)blockIdx.y * ld;
+  double2 acc = cz(0.0, 0.0);
+  for (int i = lane; i <= j; i += 64) cfmac(acc, m.a[(size_t)j * m.lda + i], yw[i]);
+  acc = wave_sum(acc);
+  if (lane == 0) z[(size_t)blockIdx.y * ld + j] = acc;
+}
+
+// Complete orthogonal decomposition: U_L = I and L^{-1} = (R_L^{-1})^H in
+// place of the Jacobi's U_L and V_L S^+ (x: R_L^{-1}, upper triangular)
+__global__ void cod_prep_kernel(const MatDesc *__restrict__ qd, const MatDesc *__restrict__ ld,
+                                const MatDesc *__restrict__ xd) {
+  const MatDesc q = qd[blockIdx.y], l = ld[blockIdx.y], x = xd[blockIdx.y];
+  const int k = blockIdx.x;
+  const int r = l.n;
+  if (k >= r) return;
+  double2 *uq = q.u + (size_t)k * q.lda;
+  double2 *ul = l.u + (size_t)k * l.lda;
+  for (int i = threadIdx.x; i < q.m; i += blockDim.x) uq[i] = cz(i == k ? 1.0 : 0.0, 0.0);
+  for (int i = threadIdx.x; i < l.m; i += blockDim.x)
+    ul[i] = (i >= k && i < r) ? cconj(x.a[(size_t)i * x.lda + k]) : cz(0.0, 0.0);
 }
 
 // squared norms of the rows of R = triu(a[0:n, 0:n])
@@ -497,6 +543,54 @@ static void upload_descs(DevBuf &buf, const std::vector<MatDesc> &h, hipStream_t
   HIP_CHECK(hipMemcpyAsync(buf.p, h.data(), h.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
 }
 
+// Largest singular value of each triangle (n2[w] x n2[w], upper) by power
+// iteration on R^H R from the all-ones vector; iters rounds.  Blocking.
+static std::vector<double> tri_sigma1(const MatDesc *tri, const std::vector<int> &n2, int ld, hipStream_t s,
+                                      int iters = 10) {
+  const int W = (int)n2.size();
+  const int nmax = *std::max_element(n2.begin(), n2.end());
+  std::vector<double2> hx((size_t)W * ld, cz(0.0, 0.0));
+  for (int w = 0; w < W; ++w)
+    for (int i = 0; i < n2[w]; ++i) hx[(size_t)w * ld + i] = cz(1.0 / std::sqrt((double)n2[w]), 0.0);
+  DevBuf x(hx.size() * sizeof(double2)), y(hx.size() * sizeof(double2));
+  std::vector<double> s1(W, 0.0);
+  for (int it = 0; it < iters; ++it) {
+    HIP_CHECK(hipMemcpyAsync(x.p, hx.data(), hx.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(trimv_kernel, dim3(cdiv(nmax, 256), W), dim3(256), 0, s, tri, x.as<double2>(),
+                       y.as<double2>(), ld);
+    hipLaunchKernelGGL(trimhv_kernel, dim3(cdiv(nmax, 4), W), dim3(256), 0, s, tri, y.as<double2>(),
+                       x.as<double2>(), ld);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(hx.data(), x.p, hx.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (int w = 0; w < W; ++w) {
+      double nrm = 0.0;
+      for (int i = 0; i < n2[w]; ++i) nrm += cabs2(hx[(size_t)w * ld + i]);
+      nrm = std::sqrt(nrm);   // ||R^H R x|| for the unit vector x: sigma_1^2 in the limit
+      s1[w] = std::sqrt(nrm);
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = 0; i < n2[w]; ++i) hx[(size_t)w * ld + i] = cscale(hx[(size_t)w * ld + i], inv);
+    }
+  }
+  return s1;
+}
+
+// Whether the truncated pseudoinverse after the pivoted QR of the triangle
+// is taken as a complete orthogonal decomposition (truncated at the pivoted
+// triangle's trailing Frobenius norm, then L^{-1} of its LQ) instead of the
+// Jacobi SVD of L.  Default: for the periodizer's equilibrated Q from
+// kCodMinCols columns on, the SVD otherwise.  MFS_QPINV=svd or cod decides
+// for every equilibrated batch (the periodizer), MFS_OPINV=cod takes it for
+// the one-body operators' blocks too (no singular values are then formed).
+constexpr int kCodMinCols = 4096;
+static bool use_cod(bool equilibrate, bool pivot, int n2max) {
+  if (!pivot) return false;
+  const char *e = std::getenv(equilibrate ? "MFS_QPINV" : "MFS_OPINV");
+  if (e && std::string(e) == "cod") return true;
+  if (e && std::string(e) == "svd") return false;
+  return equilibrate && n2max >= kCodMinCols;
+}
+
 // The equilibrated columns of the periodizer's Q are usually independent well
 // within the cutoff; the truncated SVD then keeps every singular value and
 // the pseudoinverse is D P R^{-1} Q_1^H, with Q_1 R the QR of the ordered,
@@ -774,6 +868,25 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     }
     rr[w] = std::max(r, 1);
   }
+  // complete orthogonal decomposition: keep the rows of the pivoted triangle
+  // until the trailing block's Frobenius norm is at most rel_cutoff times the
+  // largest singular value (the rank-revealing counterpart of the SVD cut)
+  const bool cod = use_cod(equilibrate, pivot, n2max);
+  g.cod = cod;
+  if (cod) {
+    const std::vector<double> s1 = tri_sigma1(tri, n2, n2max, s);
+    for (int w = 0; w < W; ++w) {
+      const double thr = rel_cutoff * s1[w];
+      double suf = 0.0;
+      int r = rr[w];
+      for (int i = rr[w] - 1; i >= 0; --i) {
+        suf += hr[(size_t)w * n2max + i];
+        if (std::sqrt(suf) > thr) { r = i + 1; break; }
+        r = i;
+      }
+      rr[w] = std::max(r, 1);
+    }
+  }
   g.rows = rr;
   g.cols = n2;
   // 3. QR of R_top^H (n2 x r)  and  4. Jacobi on L = (R factor)^H
@@ -816,18 +929,57 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   hipLaunchKernelGGL(transpose_top_kernel, dim3(1024, W), dim3(256), 0, s, tri, g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
   qr_factor(g.d_lq.as<MatDesc>(), g.h_lq, s);
-  const JacStats js = jac_run(g.d_lq.as<MatDesc>(), g.h_lq, 1, rel_cutoff, s);
-  g.jacobi_ms = js.ms;
-  g.jacobi_launches = js.launches;
-  g.jacobi_bytes = js.bytes;
-  g.jacobi_flops = js.flops;
-  g.jacobi_unconverged = js.unconverged;
-  jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
-  // 5. explicit factors
   const int rmax = *std::max_element(rr.begin(), rr.end());
+  DevBuf xa, dx;   // COD: X = R_L^{-1}
+  if (cod) {
+    // every kept row stays: L^{-1} = (R_L^{-1})^H in place of V_L S^+, U_L = I
+    g.kept = rr;
+    g.jacobi_ms = g.jacobi_bytes = g.jacobi_flops = 0.0;
+    g.jacobi_launches = 0;
+    g.jacobi_unconverged = 0;
+    HIP_CHECK(hipMemcpyAsync(flags + W, rr.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+    std::vector<size_t> ox(W);
+    size_t tx = 0;
+    for (int w = 0; w < W; ++w) {
+      ox[w] = tx;
+      tx += arena_bytes((size_t)round_up(rr[w], 16) * rr[w]);
+    }
+    xa.alloc(tx);
+    std::vector<MatDesc> hx(W);
+    for (int w = 0; w < W; ++w) {
+      MatDesc d{};
+      d.a = arena_at(xa, ox[w]);
+      d.m = rr[w]; d.n = rr[w]; d.lda = round_up(rr[w], 16);
+      d.rank = flags + W + w;
+      hx[w] = d;
+    }
+    upload_descs(dx, hx, s);
+    launch_zero(xa.as<double2>(), (long)(tx / sizeof(double2)), s);
+    const int nblk = cdiv(rmax, TI);
+    hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk, W), dim3(TI), 0, s, g.d_lq.as<MatDesc>(), dx.as<MatDesc>());
+    for (int d = 1; d < nblk; ++d)
+      hipLaunchKernelGGL(trinv_off_kernel, dim3(nblk - d, W), dim3(256), 0, s, g.d_lq.as<MatDesc>(),
+                         dx.as<MatDesc>(), d);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));   // hx goes out of scope
+  } else {
+    const JacStats js = jac_run(g.d_lq.as<MatDesc>(), g.h_lq, 1, rel_cutoff, s);
+    g.jacobi_ms = js.ms;
+    g.jacobi_launches = js.launches;
+    g.jacobi_bytes = js.bytes;
+    g.jacobi_flops = js.flops;
+    g.jacobi_unconverged = js.unconverged;
+    jac_sort(g.d_lq.as<MatDesc>(), g.h_lq, rel_cutoff, s, g.kept);
+  }
+  // 5. explicit factors
   int kmax = 0;
   for (int k : g.kept) kmax = std::max(kmax, k);
-  hipLaunchKernelGGL(prep_uv_kernel, dim3(rmax, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(), g.d_lq.as<MatDesc>());
+  if (cod)
+    hipLaunchKernelGGL(cod_prep_kernel, dim3(rmax, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+                       g.d_lq.as<MatDesc>(), dx.as<MatDesc>());
+  else
+    hipLaunchKernelGGL(prep_uv_kernel, dim3(rmax, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
+                       g.d_lq.as<MatDesc>());
   HIP_CHECK(hipGetLastError());
   // U = Q_1 [U_L; 0], or Q_1 [Q_2 [U_L; 0]; 0] with pivoting (the
   // reflectors of the pivoted triangle act on the first n2 rows first);
@@ -874,7 +1026,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
 void GradedPinv::singular_values(int ldo, std::vector<double> &out, hipStream_t s) const {
   const int W = (int)h_lq.size();
   out.assign((size_t)W * ldo, 0.0);
-  if (W == 0 || ldo <= 0) return;
+  if (W == 0 || ldo <= 0 || cod) return;   // the decomposition forms no singular values
   DevBuf buf(out.size() * sizeof(double));
   hipLaunchKernelGGL(sv_gather_kernel, dim3(W), dim3(256), 0, s, d_lq.as<MatDesc>(), ldo, buf.as<double>());
   HIP_CHECK(hipGetLastError());

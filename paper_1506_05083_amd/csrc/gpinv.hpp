@@ -20,6 +20,7 @@ struct GradedPinv {
   hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the unpivoted blocked QR
   bool pivoted = false;              // the triangle went through the pivoted QR
   bool direct = false;               // every singular value kept: U = Q_1, W = D P R^{-1} (no SVD)
+  bool cod = false;                  // truncated complete orthogonal decomposition in place of the SVD
   int qr_nb = kQRNB;                 // panel width of the QR of the ordered columns
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
   int jacobi_launches = 0;

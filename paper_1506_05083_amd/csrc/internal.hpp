@@ -75,6 +75,8 @@ constexpr int kQRNB = 32;   // Householder panel width where it is not tuned (pi
 // rows = 2M (values, then normal derivatives) by cols = 2N (exterior
 // coefficients with the sources inside, then interior coefficients at km
 // with the sources srho2, sz2 outside).
+struct NearLowRank;
+
 struct BodyData {
   int M, N, P, q, nd, ldA;
   int rows, cols;
@@ -91,6 +93,10 @@ struct BodyData {
   std::vector<int> rank;
   std::vector<double> h_sv;   // [nd][cols] singular values after mfs_factor_modes (descending, zero-filled)
   DevBuf src_P;       // point sources at q = P angles, SoA x y z [P*N] each
+  // low-rank factors of the surface image blocks of A_else for one lattice
+  // (built on first use by a periodic solve whose stored near field does
+  // not fit; kept for later solves on the same lattice)
+  std::shared_ptr<NearLowRank> lowrank;
 };
 
 // ---------------------------------------------------------- launchers
@@ -193,6 +199,42 @@ int nsum_splits(const NsumPlan &plan, int S);
 // allocated) if it would take more than max_bytes or leave under 2 GiB free.
 bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,
                       size_t max_bytes, hipStream_t s);
+
+// ------------------------------------------------- low-rank image blocks
+// A_else on the surface (eq. (A)) as a sum over the eight neighbour images
+// of K_e[t][s] = dG/dn_t(x_t - e, y_s), t = l M + m, s = l N + j.  Images
+// that a rotation of the lattice about the body's axis carries into each
+// other share one factorisation K_e ~ U X (U: T x ell with orthonormal
+// columns, X = U^H K_e: ell x S): the rotation by 2 pi / nrot shifts the
+// angle index l by P / nrot on both sides, so
+// K_{R^r e}[t][s] = K_e[R^-r t][R^-r s].  Square lattices with P divisible
+// by 4: the classes (1, 0) and (1, 1), four rotations each; otherwise the
+// half-turn: four classes, two rotations each.
+struct NearLowRank {
+  int T = 0, S = 0, P = 0, M = 0, N = 0;
+  int nrot = 0, ncls = 0;
+  int shiftT = 0, shiftS = 0;   // index shifts of one rotation step
+  double ex = 0.0, ey = 0.0, k = 0.0;
+  struct Cls {
+    int a = 0, b = 0;           // representative image (a e_x + b e_y)
+    int ell = 0, ldu = 0;       // kept columns of U (a multiple of 16); leading dimension of U
+    int img[4] = {0, 0, 0, 0};  // index of image R^r (a, b) in the surface group's image list
+    double tail = 0.0;          // |R_ell,ell| / max |R_ii| of the sketch's QR at the kept width
+    DevBuf U, X;                // U column-major [ell][ldu]; X source-major [S][ell]
+  } cls[4];
+  double build_ms = 0.0;
+  size_t bytes = 0;
+};
+// Factors for the surface plan `psurf` of body b on lattice lat (nullptr if
+// they would not fit in the free device memory).  Blocking.
+std::shared_ptr<NearLowRank> build_near_lowrank(const BodyData &b, const NsumPlan &psurf, double ex, double ey,
+                                                hipStream_t s);
+// out[r][t] (r < nrhs, row stride ldo) = the eight images' phased sum of the
+// point strengths sigma[r][S], weights w[img][nrhs] (the surface group's).
+// work: device scratch of lowrank_work_bytes(lr, nrhs) bytes.
+size_t lowrank_work_bytes(const NearLowRank &lr, int nrhs);
+void lowrank_apply(const NearLowRank &lr, int nrhs, const double2 *sigma, const double2 *w, double2 *out,
+                   size_t ldo, void *work, hipStream_t s);
 
 // ----------------------------------------------------------- harmonics
 // Fill rows of Q (S block and -W blocks) for one wave.

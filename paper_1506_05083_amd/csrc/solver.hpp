@@ -49,6 +49,9 @@ struct Solver {
   // plans
   NsumPlan psurf, pwalls;
   DevBuf wsurf, wwalls;
+  // low-rank image blocks of the surface sums (when their stored values do not fit)
+  std::shared_ptr<NearLowRank> lowrank;
+  DevBuf LRW;
   // work
   DevBuf V, Z, XIN, C, SIG, GS, GH, WR, CY, XI, PART, YW, H1, SC;
   int nsplit_s = 1, nsplit_w = 1;
@@ -137,7 +140,9 @@ struct Solver {
     graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s, true);
     qrank = gp.kept;
     progress("periodizer: factored (%s; Jacobi %.0f ms, %d launches)",
-             gp.direct ? "full rank, no SVD" : gp.pivoted ? "pivoted triangle" : "ordered triangle",
+             gp.direct ? "full rank, no SVD"
+             : gp.cod  ? "pivoted triangle, truncated complete orthogonal decomposition"
+             : gp.pivoted ? "pivoted triangle" : "ordered triangle",
              gp.jacobi_ms, gp.jacobi_launches);
     setup_bvals();
   }
@@ -176,6 +181,31 @@ struct Solver {
                  psurf.dense.p ? "surface sums" : "nothing");
       (void)hipEventDestroy(f0);
       (void)hipEventDestroy(f1);
+    }
+    // Surface sums from low-rank factors of the image blocks when their
+    // stored values did not fit (MFS_NEAR_LOWRANK: 0 never, 1 then
+    // (default), 2 whenever the surface values are not stored).  The factors
+    // depend on the body and the lattice only and stay with the operator.
+    {
+      const char *e = std::getenv("MFS_NEAR_LOWRANK");
+      const int mode = e ? std::atoi(e) : 1;
+      if (!psurf.dense.p && !b.trans() && W <= 16 && mode > 0 && (near_mode == 2 || mode == 2)) {
+        auto &c = b.lowrank;
+        if (!(c && c->ex == lat.ex && c->ey == lat.ey && c->k == b.k && c->P == P && c->M == M && c->N == N)) {
+          c.reset();
+          c = build_near_lowrank(b, psurf, lat.ex, lat.ey, s);
+          near_fill_ms = c ? c->build_ms : 0.0;
+        } else {
+          near_fill_ms = 0.0;
+        }
+        lowrank = c;
+        if (lowrank) {
+          LRW.alloc(lowrank_work_bytes(*lowrank, W));
+          near_mode = 3;
+          progress("near field: surface sums from low-rank image blocks (%.2f GB, built in %.0f ms)",
+                   lowrank->bytes / 1e9, lowrank->build_ms);
+        }
+      }
     }
     // work buffers
     V.alloc((size_t)W * (maxit + 1) * MP * sizeof(double2));
@@ -327,6 +357,25 @@ struct Solver {
     }
   }
 
+  // the surface sums of the point strengths in SIG from the low-rank image
+  // blocks, timed like the direct sums (bytes: the factors streamed)
+  void surface_sum_lowrank(double2 *out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_nsum) {
+      HIP_CHECK(hipEventCreate(&e0));
+      HIP_CHECK(hipEventCreate(&e1));
+      HIP_CHECK(hipEventRecord(e0, s));
+    }
+    lowrank_apply(*lowrank, W, SIG.as<double2>(), wsurf.as<double2>(), out, psurf.ntarget_pad, LRW.p, s);
+    if (time_nsum) {
+      HIP_CHECK(hipEventRecord(e1, s));
+      nsum_ev.push_back(e0);
+      nsum_ev.push_back(e1);
+      nsum_bytes.push_back((double)lowrank->bytes);
+      nsum_alg_bytes.push_back((double)lowrank->bytes);
+    }
+  }
+
   // XI = Q^+ (C c) for mode coefficients in C
   void c_then_qpinv(const double2 *cmodes) {
     launch_point_strengths(W, P, P, N, cmodes, SIG.as<double2>(), s, Nc);
@@ -343,7 +392,8 @@ struct Solver {
   void apply_op(const double2 *x, double2 *out) {
     pinv_A0(x, C.as<double2>());
     launch_point_strengths(W, P, P, N, C.as<double2>(), SIG.as<double2>(), s, Nc);
-    nsum(psurf, wsurf, GS.as<double2>());
+    if (lowrank) surface_sum_lowrank(GS.as<double2>());
+    else nsum(psurf, wsurf, GS.as<double2>());
     if (!b.trans()) {
       launch_dft_ld(W, P, M, GS.as<double2>(), psurf.ntarget_pad, GH.as<double2>(), -1, 1.0 / P, s, M);
     } else {

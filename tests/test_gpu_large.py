@@ -129,6 +129,55 @@ def test_large_solve_one_wave(large):
     assert max(x.eps_flux for x in res) < 1e-9
 
 
+def test_large_low_rank_matches_on_the_fly(large, monkeypatch):
+    """The same incidence with the surface sums from the low-rank image
+    blocks (the default when the stored field does not fit, as here) and
+    evaluated on the fly: Bragg amplitudes and cell fields agree to 1e-10."""
+    mfs, pr, ctx, op, blocks, ranks = large
+    lat = pr.lattice
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    kw = dict(tol=1e-12, maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field, timing=True)
+    waves = [(w.theta, w.phi) for w in pr.waves]
+    monkeypatch.setenv("MFS_NEAR_LOWRANK", "1")
+    res_lr, tm_lr = mfs.solve_incident(ctx, op, L, waves, **kw)
+    monkeypatch.setenv("MFS_NEAR_LOWRANK", "0")
+    res_f, tm_f = mfs.solve_incident(ctx, op, L, waves, **kw)
+    assert int(tm_lr["near_mode"]) == 3 and int(tm_f["near_mode"]) == 2
+    a, b = res_lr[0], res_f[0]
+    ea = np.max(np.abs(a.a - b.a)) / np.max(np.abs(b.a))
+    eb = np.max(np.abs(a.b - b.b)) / np.max(np.abs(b.b))
+    eu = np.linalg.norm(a.field - b.field) / np.linalg.norm(b.field)
+    log(f"[large low rank] build {tm_lr['near_fill_ms'] / 1e3:.1f} s; surface+wall sums {tm_lr['nsum_avg']:.2f} ms "
+        f"avg against {tm_f['nsum_avg']:.2f} ms on the fly; GMRES {tm_lr['gmres'] / 1e3:.2f} s against "
+        f"{tm_f['gmres'] / 1e3:.2f} s; iters {a.iters} / {b.iters}; a {ea:.2e} b {eb:.2e} u {eu:.2e}")
+    assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+
+
+def test_large_cod_matches_svd(large, monkeypatch):
+    """The periodizer's truncated pseudoinverse (Q: 25088 x 10805, about 90
+    directions cut) as the complete orthogonal decomposition (the default at
+    this width) and as the Jacobi SVD, same incidence: Bragg amplitudes and
+    cell fields agree, and both balance the energy flux."""
+    mfs, pr, ctx, op, blocks, ranks = large
+    lat = pr.lattice
+    L = mfs.lattice(lat.ex, lat.ey, lat.z0, lat.p, lat.N0, lat.M1)
+    kw = dict(tol=1e-12, maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field, timing=True)
+    waves = [(w.theta, w.phi) for w in pr.waves]
+    monkeypatch.setenv("MFS_QPINV", "cod")
+    res_c, tm_c = mfs.solve_incident(ctx, op, L, waves, **kw)
+    monkeypatch.setenv("MFS_QPINV", "svd")
+    res_s, tm_s = mfs.solve_incident(ctx, op, L, waves, **kw)
+    a, b = res_c[0], res_s[0]
+    ea = np.max(np.abs(a.a - b.a)) / np.max(np.abs(b.a))
+    eb = np.max(np.abs(a.b - b.b)) / np.max(np.abs(b.b))
+    eu = np.linalg.norm(a.field - b.field) / np.linalg.norm(b.field)
+    log(f"[large cod] periodizer {tm_c['periodizer'] / 1e3:.1f} s (kept {a.q_rank} of {a.nq_cols}) against "
+        f"{tm_s['periodizer'] / 1e3:.1f} s with the Jacobi SVD (kept {b.q_rank}); a {ea:.2e} b {eb:.2e} u {eu:.2e}; "
+        f"eps_flux {a.eps_flux:.2e} / {b.eps_flux:.2e}")
+    assert ea < 1e-9 and eb < 1e-9 and eu < 1e-9
+    assert a.eps_flux < 1e-9 and b.eps_flux < 1e-9
+
+
 def test_large_transmission_one_wave(large):
     """The transmission variant at full size (km = 1.5 k, 1080 x 900 mode
     blocks): the four value/derivative sub-blocks at sampled rows against

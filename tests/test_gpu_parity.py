@@ -246,17 +246,23 @@ def test_neighbour_sum_parity(mfs, ctx, small_oracle):
         assert rel(gu[0], ref) < 1e-12
 
 
-@pytest.mark.parametrize("near", ["dense", "on_the_fly"])
-def test_periodic_solve_parity_small(mfs, ctx, small_oracle, near):
+@pytest.mark.parametrize("near", ["dense", "on_the_fly", "low_rank", "low_rank_halfturn"])
+def test_periodic_solve_parity_small(mfs, ctx, small_oracle, near, monkeypatch):
     """Whole periodic path on the GPU (Q fill and factorisation, batched
     GMRES with the neighbour sums, recovery) for two incidences against the
     oracle: Bragg amplitudes and cell fields to 1e-10, with the near-field
-    kernel values stored once (default) and evaluated every iteration."""
+    kernel values stored once (default), evaluated every iteration, or (the
+    surface sums) from low-rank factors of the image blocks, in the
+    quarter-turn form (two classes of four images) and the half-turn form
+    (four classes of two)."""
     pr, g, out = small_oracle
     b = pr.body
     op = make_op(mfs, ctx, b)
-    if near == "on_the_fly":
+    if near != "dense":
         op.set_near_field_budget(0)
+    if near.startswith("low_rank"):
+        monkeypatch.setenv("MFS_NEAR_LOWRANK", "2")
+        monkeypatch.setenv("MFS_LOWRANK_HALFTURN", "1" if near.endswith("halfturn") else "0")
     op.factor_modes(1e-10)
     L = _lat(mfs, pr.lattice)
     res = mfs.solve_incident(ctx, op, L, [(w.theta, w.phi) for w in pr.waves], tol=1e-12, maxit=100,
@@ -341,6 +347,34 @@ def test_qr_panel_widths(mfs, ctx, small_oracle, monkeypatch, nb):
     assert e < 1e-13
 
 
+def test_cod_operator_fields(mfs, ctx, monkeypatch):
+    """The one-body factorisation with the truncated complete orthogonal
+    decomposition (MFS_OPINV=cod: pivoted QR of the triangle, cut at the
+    trailing Frobenius norm, inverse of the LQ factor) in place of the Jacobi
+    SVD, on rank-deficient bodies (the k = 10 body and two of the batch's):
+    the free-space field against the oracle's truncated-SVD solution, 1e-10;
+    the coefficients differ (the kept ranks are not the SVD's) but the field
+    the method computes does not."""
+    monkeypatch.setenv("MFS_OPINV", "cod")
+    bodies = [W.periodic_k10(1).body] + W.batch_obstacles(2)
+    tg = W.fibonacci_sphere(24, 2.0)
+    for i, b in enumerate(bodies):
+        op = make_op(mfs, ctx, b)
+        ranks = op.factor_modes(1e-10)
+        w = W.sample_waves(b.k, None, 1, seed=40 + i)[0]
+        kv = W.wave_vector(b.k, w)[None, :]
+        c = mfs.apply_solution_op(op, mfs.rhs_modes(op, kv))
+        u = mfs.field_free(op, c, 2 * b.P, tg).cpu().numpy()[0]
+        g = geometry.build_geometry(b)
+        A = onebody.modal_blocks(b, g)
+        co = onebody.solve_modes(A, onebody.rhs_modes(b, g, w))
+        uo = onebody.field(b, g, co, tg, 2 * b.P)
+        err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+        svr = [int(np.sum(s > 1e-10 * s[0])) for s in (np.linalg.svd(A[n], compute_uv=False) for n in range(3))]
+        log(f"[cod] body {i}: N={b.N} M={b.M} P={b.P} ranks {list(ranks[:3])} (SVD {svr}) field err {err:.2e}")
+        assert err < 1e-10
+
+
 def test_sixteen_wave_batch_matches_small_batches(mfs, ctx):
     """Twelve incidences in one batched solve (the stored-field sums then run
     with 16 right-hand sides: the matrix-core mirror form with two column
@@ -402,6 +436,39 @@ def test_periodic_k10_full_size_vs_golden(mfs, ctx, tol):
         f"flux {max(x.eps_flux for x in res):.2e} (oracle {gold['eps_flux']:.2e})")
     assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
     assert all(x.eps_flux < (1e-11 if tol < 1e-11 else 3e-10) for x in res)
+
+
+def test_periodic_k10_low_rank_vs_golden(mfs, ctx, monkeypatch):
+    """The benchmark workload with its surface sums from the low-rank image
+    blocks (randomised range finder, QR, projection; ranks well below the
+    15360 x 12800 blocks, so the truncation is exercised) instead of the
+    stored values: all 8 incidences in one batch, incidence 0 against the
+    oracle's stored solution, Bragg amplitudes and cell fields to 1e-10."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "periodic_k10_wave0.json")))
+    pr = W.periodic_k10(8)
+    b, lat = pr.body, pr.lattice
+    monkeypatch.setenv("MFS_NEAR_LOWRANK", "2")
+    op = make_op(mfs, ctx, b)
+    op.set_near_field_budget(0)
+    op.factor_modes(1e-10)
+    tg = np.array(gold["targets"])
+    res, tm = mfs.solve_incident(ctx, op, _lat(mfs, lat), [(w.theta, w.phi) for w in pr.waves], tol=1e-12,
+                                 maxit=100, targets=tg, q_field=gold["q_field"], timing=True)
+    assert int(tm["near_mode"]) == 3
+    r = res[0]
+    assert r.m.tolist() == gold["m"] and r.n.tolist() == gold["n"]
+    ga = np.array(gold["a_re"]) + 1j * np.array(gold["a_im"])
+    gb = np.array(gold["b_re"]) + 1j * np.array(gold["b_im"])
+    gu = np.array(gold["u_re"]) + 1j * np.array(gold["u_im"])
+    ea = np.max(np.abs(r.a - ga)) / np.max(np.abs(ga))
+    eb = np.max(np.abs(r.b - gb)) / np.max(np.abs(gb))
+    eu = np.linalg.norm(r.field - gu) / np.linalg.norm(gu)
+    log(f"[k10 low rank] build {tm['near_fill_ms']:.1f} ms, sums {tm['nsum_avg']:.3f} ms avg; iters gpu {r.iters} "
+        f"oracle {gold['iters']} a {ea:.2e} b {eb:.2e} u {eu:.2e} flux {max(x.eps_flux for x in res):.2e}")
+    assert ea < 1e-10 and eb < 1e-10 and eu < 1e-10
+    assert all(x.eps_flux < 1e-11 for x in res)
 
 
 @pytest.mark.parametrize("name", ["sphere", "cup"])
