@@ -35,6 +35,15 @@ def qr_flops(M: int, N: int) -> float:
     return 8.0 * M * N * N - 8.0 * N ** 3 / 3.0
 
 
+def fill_flops(bodies) -> float:
+    """Algorithmic FP64 work of the modal fill, per (collocation, source)
+    pair: q/2 + 1 kernel samples (about 20 flops each, the reciprocal square
+    root and the sine-cosine counted as one flop each) and the cosine sums of
+    the P/2 + 1 distinct modes, 4 flops per (sample, mode) (a real weight
+    times a complex sample)."""
+    return float(sum(b.M * b.N * (b.q // 2 + 1) * (20 + 4 * (b.P // 2 + 1)) for b in bodies))
+
+
 def nsum_pairs(pr: W.Problem) -> float:
     """Kernel evaluations of one A_else action: 8 images x (P M) targets x (P N) sources."""
     b = pr.body
@@ -121,12 +130,40 @@ def run_batch_build(count: int):
     tm = op.timing()
     flops = sum((b.P // 2 + 1) * qr_flops(b.M, b.N) for b in bodies)
     gbytes = sum((b.P // 2 + 1) * ((b.M + 15) // 16 * 16) * b.N * 16 for b in bodies) / 1e9
+    fflops = fill_flops(bodies)
     del op
+    # the same build with the truncation as a complete orthogonal
+    # decomposition (MFS_OPINV=cod; the library then forms no singular values)
+    os.environ["MFS_OPINV"] = "cod"
+    try:
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        op = mfs.build_operator(ctx, specs)
+        t4 = time.perf_counter()
+        op.factor_modes(1e-10)
+        t5 = time.perf_counter()
+        tmc = op.timing()
+        del op
+    finally:
+        del os.environ["MFS_OPINV"]
+    # the builds' idle blocks (about 35 GB each) go back to the device before
+    # the next measurement
+    torch.cuda.synchronize()
+    mfs.release_cached_memory(0)
+    print(f"[batch] complete orthogonal decomposition: factored in {t5 - t4:.2f} s", file=sys.stderr, flush=True)
     return {"obstacles": count, "distinct_blocks": nblk, "blocks_GB": gbytes, "qr_flops": flops,
             "fill_ms": tm["fill"], "qr_ms": tm["qr"], "trunc_ms": tm["svd"],
             "fill_qr_tflops": flops / ((tm["fill"] + tm["qr"]) * 1e-3) / 1e12,
             "qr_tflops": flops / (tm["qr"] * 1e-3) / 1e12,
-            "build_wall_s": t1 - t0, "factor_wall_s": t2 - t1, "mean_rank_fraction":
+            "fill_roofline": {"bound": "alu", "kernel": "fill_batch_kernel (all bodies, one persistent launch)",
+                              "achieved": fflops / (tm["fill"] * 1e-3) / 1e12, "peak": PEAK_FP64,
+                              "unit": "TFLOP/s", "frac": fflops / (tm["fill"] * 1e-3) / 1e12 / PEAK_FP64,
+                              "flops": fflops,
+                              "flops_counted": "per (m, j) pair: (q/2+1) kernel samples at 20 flops (rsqrt and "
+                                               "sincos as one each) + 4 (q/2+1)(P/2+1) for the cosine sums"},
+            "build_wall_s": t1 - t0, "factor_wall_s": t2 - t1,
+            "cod": {"trunc_ms": tmc["svd"], "qr_ms": tmc["qr"], "factor_wall_s": t5 - t4},
+            "mean_rank_fraction":
                 float(np.mean([r / b.N for b, r in zip([bb for bb in bodies for _ in range(bb.P // 2 + 1)],
                                                        ranks)])),
             "workload": "seeded obstacles (seed 3): a U[0.2,0.4], eps U[0,0.15], j U{2..5}, N U{100..600}, "

@@ -195,6 +195,14 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                  const double *src, int S, const double2 *sigma, const double2 *w,
                  double2 *out, double2 *partial, hipStream_t s);
 int nsum_splits(const NsumPlan &plan, int S);
+// Both plans' stored, mirror-paired fields in one launch (the surface and
+// the wall sums of an iteration read the same strengths): true if both are
+// stored for these sources and paired.  partial buffers: nsum_splits(plan,
+// S) * nrhs * ntarget_pad each, separate for the two plans.
+bool nsum_pair_fusable(const NsumPlan &a, const NsumPlan &b, double k, const double *src, int S, int nrhs);
+void launch_nsum_pair(const NsumPlan &pa, const double2 *wa, double2 *outa, double2 *parta, const NsumPlan &pb,
+                      const double2 *wb, double2 *outb, double2 *partb, int nrhs, int S, const double2 *sigma,
+                      hipStream_t s);
 // Fill plan.dense for the sources src (S of them); false (and nothing
 // allocated) if it would take more than max_bytes or leave under 2 GiB free.
 bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,

@@ -341,19 +341,38 @@ __global__ __launch_bounds__(256) void nsum_dense_kernel(int ntp, const NsumGrou
 // its mirror on the same wall.  The grid runs over the stored tiles only
 // (tiles[], those with the most images first, so that a launch ends on short
 // workgroups).
+// One stored field of a launch of the mirror form: its plan's device arrays,
+// weights, source slices and output (see nsum_dense_mirror_mfma_kernel).
+struct DenseView {
+  int ntp, ntiles, nsplit;
+  const NsumGroup *groups;
+  const int *tile_group;
+  const size_t *koff;
+  const int *tiles;
+  const double2 *dense, *wts;
+  double2 *out;
+};
+
 template <int NR>
-__global__ __launch_bounds__(256, NR == 8 ? 4 : 2) void nsum_dense_mirror_mfma_kernel(int ntp, const NsumGroup *__restrict__ groups,
-                                                                     const int *__restrict__ tile_group,
-                                                                     const size_t *__restrict__ koff,
-                                                                     const int *__restrict__ tiles,
-                                                                     const double2 *__restrict__ dense, int nrhs,
-                                                                     int S, const double2 *__restrict__ sigT,
-                                                                     const double2 *__restrict__ wts, int nsplit,
-                                                                     double2 *__restrict__ out) {
+__global__ __launch_bounds__(256, NR == 8 ? 4 : 2) void nsum_dense_mirror_mfma_kernel(DenseView va, DenseView vb,
+                                                                     int nrhs, int S,
+                                                                     const double2 *__restrict__ sigT) {
   static_assert(NR == 8 || NR == 16, "two NR columns in blocks of 16");
   constexpr int RB = 4, CB = 2 * NR / 16, KU = 2;   // KU steps of 4 sources per batch of loads
   extern __shared__ double shm[];
-  const int tile = tiles[blockIdx.x], split = blockIdx.y;   // stored tiles only
+  // the first va.ntiles workgroups of x serve the first field, the rest the
+  // second (the surface and the wall sums of one iteration in one launch)
+  const bool second = (int)blockIdx.x >= va.ntiles;
+  const DenseView &V = second ? vb : va;
+  if ((int)blockIdx.y >= V.nsplit) return;
+  const int ntp = V.ntp, nsplit = V.nsplit;
+  const NsumGroup *__restrict__ groups = V.groups;
+  const size_t *__restrict__ koff = V.koff;
+  const double2 *__restrict__ dense = V.dense;
+  const double2 *__restrict__ wts = V.wts;
+  double2 *__restrict__ out = V.out;
+  const int tile = V.tiles[second ? blockIdx.x - va.ntiles : blockIdx.x], split = blockIdx.y;   // stored tiles only
+  const int *__restrict__ tile_group = V.tile_group;
   const int gi = tile_group[tile];
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -508,6 +527,21 @@ bool plan_mirrored(const NsumPlan &plan, bool dense) {
   return all;
 }
 
+DenseView dense_view(const NsumPlan &plan, const double2 *w, int nsplit, double2 *dst) {
+  DenseView v{};
+  v.ntp = plan.ntarget_pad;
+  v.ntiles = plan.ndense_tiles;
+  v.nsplit = nsplit;
+  v.groups = plan.grp.as<NsumGroup>();
+  v.tile_group = plan.tile_group.as<int>();
+  v.koff = plan.koff.as<size_t>();
+  v.tiles = plan.dense_tiles.as<int>();
+  v.dense = plan.dense.as<double2>();
+  v.wts = w;
+  v.out = dst;
+  return v;
+}
+
 template <int NR>
 void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *sigma, const double2 *w,
                          int nsplit, double2 *dst, hipStream_t s) {
@@ -519,10 +553,9 @@ void launch_nsum_dense_t(const NsumPlan &plan, int nrhs, int S, const double2 *s
   if (plan_mirrored(plan, true)) {
     MFS_REQUIRE(NR == 8 || NR == 16, "neighbour sum: the mirror form runs with 8 or 16 right-hand sides");
     MFS_REQUIRE(plan.ndense_tiles > 0, "neighbour sum: stored tiles of the paired field missing");
+    const DenseView va = dense_view(plan, w, nsplit, dst), vb{};
     hipLaunchKernelGGL((nsum_dense_mirror_mfma_kernel<NR == 16 ? 16 : 8>), dim3(plan.ndense_tiles, nsplit),
-                       dim3(256), (size_t)4 * NR * 64 * sizeof(double2), s, plan.ntarget_pad,
-                       plan.grp.as<NsumGroup>(), plan.tile_group.as<int>(), plan.koff.as<size_t>(),
-                       plan.dense_tiles.as<int>(), plan.dense.as<double2>(), nrhs, S, sigT, w, nsplit, dst);
+                       dim3(256), (size_t)4 * NR * 64 * sizeof(double2), s, va, vb, nrhs, S, sigT);
   }
   else
     hipLaunchKernelGGL(nsum_dense_kernel<NR>, dim3(plan.ntarget_pad / 64, nsplit), dim3(256), sh, s,
@@ -602,6 +635,45 @@ void launch_nsum(const NsumPlan &plan, int nrhs, double k, double ex, double ey,
                        0, s, nsplit, nrhs, plan.ntarget_pad, partial, out);
     HIP_CHECK(hipGetLastError());
   }
+}
+
+bool nsum_pair_fusable(const NsumPlan &a, const NsumPlan &b, double k, const double *src, int S, int nrhs) {
+  auto stored = [&](const NsumPlan &p) {
+    return p.dense.p && p.dense_src == src && p.dense_S == S && p.dense_k == k && plan_mirrored(p, true) &&
+           p.ndense_tiles > 0;
+  };
+  return nrhs >= 1 && nrhs <= MAXR && stored(a) && stored(b);
+}
+
+void launch_nsum_pair(const NsumPlan &pa, const double2 *wa, double2 *outa, double2 *parta, const NsumPlan &pb,
+                      const double2 *wb, double2 *outb, double2 *partb, int nrhs, int S, const double2 *sigma,
+                      hipStream_t s) {
+  const int na = nsum_splits(pa, S), nb = nsum_splits(pb, S);
+  double2 *da = na == 1 ? outa : parta, *db = nb == 1 ? outb : partb;
+  const int NR = nrhs <= 8 ? 8 : 16;
+  double2 *sigT = pa.sigT.as<double2>();
+  const long n = (long)S * NR;
+  hipLaunchKernelGGL(sig_transpose_kernel, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, s,
+                     nrhs, NR, S, sigma, sigT);
+  const DenseView va = dense_view(pa, wa, na, da), vb = dense_view(pb, wb, nb, db);
+  const dim3 grid(pa.ndense_tiles + pb.ndense_tiles, std::max(na, nb));
+  const size_t sh = (size_t)4 * NR * 64 * sizeof(double2);
+  if (NR == 8)
+    hipLaunchKernelGGL(nsum_dense_mirror_mfma_kernel<8>, grid, dim3(256), sh, s, va, vb, nrhs, S, sigT);
+  else
+    hipLaunchKernelGGL(nsum_dense_mirror_mfma_kernel<16>, grid, dim3(256), sh, s, va, vb, nrhs, S, sigT);
+  HIP_CHECK(hipGetLastError());
+  if (na > 1) {
+    const long m = (long)nrhs * pa.ntarget_pad;
+    hipLaunchKernelGGL(nsum_reduce, dim3((unsigned)std::min<long>(2048, (m + 255) / 256)), dim3(256), 0, s, na,
+                       nrhs, pa.ntarget_pad, parta, outa);
+  }
+  if (nb > 1) {
+    const long m = (long)nrhs * pb.ntarget_pad;
+    hipLaunchKernelGGL(nsum_reduce, dim3((unsigned)std::min<long>(2048, (m + 255) / 256)), dim3(256), 0, s, nb,
+                       nrhs, pb.ntarget_pad, partb, outb);
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 bool nsum_build_dense(NsumPlan &plan, double k, double ex, double ey, const double *src, int S,

@@ -53,7 +53,7 @@ struct Solver {
   std::shared_ptr<NearLowRank> lowrank;
   DevBuf LRW;
   // work
-  DevBuf V, Z, XIN, C, SIG, GS, GH, WR, CY, XI, PART, YW, H1, SC;
+  DevBuf V, Z, XIN, C, SIG, GS, GH, WR, CY, XI, PART, PART2, YW, H1, SC;
   int nsplit_s = 1, nsplit_w = 1;
   // timing: events around every neighbour-sum launch, the dense bytes each streamed
   std::vector<hipEvent_t> nsum_ev;
@@ -220,6 +220,9 @@ struct Solver {
     XI.alloc((size_t)W * NQmax * sizeof(double2));
     const size_t part = std::max((size_t)nsplit_s * W * psurf.ntarget_pad, (size_t)nsplit_w * W * pwalls.ntarget_pad);
     PART.alloc(part * sizeof(double2));
+    // the wall sums' slices when they run in the surface sums' launch
+    if (nsum_pair_fusable(psurf, pwalls, b.k, b.src_P.as<double>(), P * N, W))
+      PART2.alloc((size_t)nsplit_w * W * pwalls.ntarget_pad * sizeof(double2));
     YW.alloc(std::max((size_t)b.nd * 2 * W * Nc, (size_t)W * NQmax) * sizeof(double2));
     H1.alloc((size_t)W * (maxit + 2) * 2 * sizeof(double2));
     SC.alloc((size_t)W * sizeof(double));
@@ -357,6 +360,26 @@ struct Solver {
     }
   }
 
+  // the surface sums into GS and the wall sums into WR in one launch over
+  // both stored fields, timed like one neighbour sum (bytes: both fields)
+  void nsum_surface_and_walls() {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_nsum) {
+      HIP_CHECK(hipEventCreate(&e0));
+      HIP_CHECK(hipEventCreate(&e1));
+      HIP_CHECK(hipEventRecord(e0, s));
+    }
+    launch_nsum_pair(psurf, wsurf.as<double2>(), GS.as<double2>(), PART.as<double2>(), pwalls,
+                     wwalls.as<double2>(), WR.as<double2>(), PART2.as<double2>(), W, P * N, SIG.as<double2>(), s);
+    if (time_nsum) {
+      HIP_CHECK(hipEventRecord(e1, s));
+      nsum_ev.push_back(e0);
+      nsum_ev.push_back(e1);
+      nsum_bytes.push_back((double)(psurf.dense_bytes + pwalls.dense_bytes));
+      nsum_alg_bytes.push_back((double)(psurf.dense_alg_bytes + pwalls.dense_alg_bytes));
+    }
+  }
+
   // the surface sums of the point strengths in SIG from the low-rank image
   // blocks, timed like the direct sums (bytes: the factors streamed)
   void surface_sum_lowrank(double2 *out) {
@@ -392,7 +415,11 @@ struct Solver {
   void apply_op(const double2 *x, double2 *out) {
     pinv_A0(x, C.as<double2>());
     launch_point_strengths(W, P, P, N, C.as<double2>(), SIG.as<double2>(), s, Nc);
-    if (lowrank) surface_sum_lowrank(GS.as<double2>());
+    // both stored fields in one launch when they can (the wall rows read the
+    // same strengths), else the surface sums now and the wall sums below
+    const bool fused = !lowrank && PART2.p && nsum_pair_fusable(psurf, pwalls, b.k, b.src_P.as<double>(), P * N, W);
+    if (fused) nsum_surface_and_walls();
+    else if (lowrank) surface_sum_lowrank(GS.as<double2>());
     else nsum(psurf, wsurf, GS.as<double2>());
     if (!b.trans()) {
       launch_dft_ld(W, P, M, GS.as<double2>(), psurf.ntarget_pad, GH.as<double2>(), -1, 1.0 / P, s, M);
@@ -405,7 +432,7 @@ struct Solver {
     }
     launch_axpby_op(W, MP, x, GH.as<double2>(), nullptr, out, s);
     // the wall rows reuse SIG computed above
-    nsum(pwalls, wwalls, WR.as<double2>());
+    if (!fused) nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
     PinvJob j{};
     j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
