@@ -12,11 +12,11 @@
 // and A'_{-n} = A'_n: only n = 0..P/2 are computed.
 //
 // Layout: one workgroup per tile of 64 (m, j) pairs (m fastest, so stores
-// of A[n][j][m] are coalesced).  The q/2+1 nodes are processed in chunks of
-// 32: the 4 waves evaluate g for the tile into LDS, then each thread folds
-// the chunk into its P/2+1 (strided by 4) mode accumulators using the
-// cosine weights staged from a per-operator table.  FP64 VALU bound: one
-// rsqrt and one sincos per kernel sample.
+// of A[n][j][m] are coalesced), a wave per 16 pairs.  The q/2+1 nodes are
+// processed in chunks of 32 whose cosine weights are staged in LDS from a
+// per-operator table; each lane evaluates the sample of its pair at one
+// node of every 4-node step (one rsqrt and one sincos) and the fold onto
+// the P/2+1 modes runs on the FP64 matrix cores (fill_tile).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -26,7 +26,6 @@ namespace {
 
 constexpr int TP = 64;    // (m, j) pairs per workgroup
 constexpr int LC = 32;    // trapezoid nodes per LDS chunk
-constexpr int MAXS = 26;  // accumulators per thread: P/2 + 1 <= 4 * MAXS
 
 // tab[l][0..nd-1] = c_l cos(2 pi n l / q) / q with c_0 = c_{q/2} = 1, else 2;
 // tab[l][nd] = cos(2 pi l / q).  Argument reduction is exact (integer n l mod q).
@@ -62,14 +61,23 @@ struct FillJob {
   long tile0;      // first tile of this job in the batch's tile list
 };
 
-// Tile `tile` (64 (m, j) pairs) of job J; all 256 threads take part.
-__device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double *wt) {
+// Tile `tile` (64 (m, j) pairs) of job J; all 256 threads take part.  The
+// fold onto the modes is a real-by-complex product on the FP64 matrix
+// cores: D[n][p] = sum_l W[n][l] g_l(p) with W[n][l] the weight
+// c_l cos(2 pi n l / q) / q of the table and g_l(p) the kernel sample of pair
+// p at node l, formed by each lane for its own pair (wave w: pairs
+// 16 w .. 16 w + 15) and node (4 per step), so a sample feeds one product
+// per 16-mode block and real or imaginary part.  The weights come from the
+// table chunk staged in LDS; the output (lane group: 16 consecutive pairs of
+// one mode) is stored in 256-byte pieces.
+constexpr int FB = 7;   // 16-mode blocks: nd <= 104 (the table chunk's row)
+__device__ void fill_tile(const FillJob &J, long tile, double *wt) {
   const int M = J.M, N = J.N, q = J.q, nd = J.nd, ldA = J.ldA;
   const double k = J.k;
   const int tid = threadIdx.x;
-  const int pl = tid & 63;
-  const int grp = tid >> 6;   // wave index: uniform within a wave
-  const long pair = tile * TP + pl;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const long pair = tile * TP + 16 * wv + l16;
   const bool valid = pair < (long)M * N;
   const int m = valid ? (int)(pair % M) : 0;
   const int j = valid ? (int)(pair / M) : 0;
@@ -82,17 +90,22 @@ __device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double
   const double inv4pi = 0.25 / kPi;
   const int L = q / 2 + 1;
   const int ld = nd + 1;
+  const int nmb = (nd + 15) / 16;   // uniform over the workgroup
 
-  double2 acc[MAXS];
+  dx4 re[FB], im[FB];
 #pragma unroll
-  for (int s = 0; s < MAXS; ++s) acc[s] = cz(0.0, 0.0);
+  for (int b = 0; b < FB; ++b) {
+    re[b] = dx4{0.0, 0.0, 0.0, 0.0};
+    im[b] = re[b];
+  }
 
   for (int l0 = 0; l0 < L; l0 += LC) {
     const int lc = min(LC, L - l0);
     __syncthreads();
     for (int idx = tid; idx < lc * ld; idx += 256) wt[idx] = J.tab[(size_t)l0 * ld + idx];
     __syncthreads();
-    for (int ll = grp; ll < LC; ll += 4) {
+    for (int kk = 0; kk < lc; kk += 4) {
+      const int ll = kk + k4;
       double2 g = cz(0.0, 0.0);
       if (ll < lc && valid) {
         const double c = wt[ll * ld + nd];
@@ -112,28 +125,29 @@ __device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double
           g = cz(t * fma(-cs, invR, -sn * k), t * fma(cs, k, -sn * invR));
         }
       }
-      gs[ll][pl] = g;
-    }
-    __syncthreads();
-    for (int ll = 0; ll < lc; ++ll) {
-      const double2 g = gs[ll][pl];
-      const double *w = wt + ll * ld;
+      // A[n][l] = W (lane l16 + 16 k4 holds mode 16 b + l16, node ll);
+      // B[l][p] = g (lane l16 + 16 k4 holds node ll, pair l16)
 #pragma unroll
-      for (int s = 0; s < MAXS; ++s) {
-        const int n = grp + 4 * s;
-        if (n < nd) {
-          const double c = w[n];
-          acc[s].x = fma(c, g.x, acc[s].x);
-          acc[s].y = fma(c, g.y, acc[s].y);
+      for (int b = 0; b < FB; ++b) {
+        if (b < nmb) {
+          const int n = 16 * b + l16;
+          const double w = (ll < lc && n < nd) ? wt[ll * ld + n] : 0.0;
+          re[b] = mfma_f64(w, g.x, re[b]);
+          im[b] = mfma_f64(w, g.y, im[b]);
         }
       }
     }
   }
   if (valid) {
+    // lane l16 + 16 k4 holds D[n = 16 b + k4 + 4 v][pair l16] in element v
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const int n = grp + 4 * s;
-      if (n < nd) J.A[((size_t)n * J.ncols + j) * ldA + m] = acc[s];
+    for (int b = 0; b < FB; ++b) {
+      if (b >= nmb) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = 16 * b + k4 + 4 * v;
+        if (n < nd) J.A[((size_t)n * J.ncols + j) * ldA + m] = cz(re[b][v], im[b][v]);
+      }
     }
   }
 }
@@ -144,7 +158,6 @@ __device__ void fill_tile(const FillJob &J, long tile, double2 (*gs)[TP], double
 // tiles).  Every workgroup leaves once the counter passes ntiles.
 __global__ __launch_bounds__(256) void fill_batch_kernel(const FillJob *__restrict__ jobs, int njobs,
                                                          long ntiles, unsigned long long *__restrict__ counter) {
-  __shared__ double2 gs[LC][TP];
   __shared__ double wt[LC * 105];
   __shared__ long s_tile;
   __shared__ int s_job;
@@ -166,7 +179,7 @@ __global__ __launch_bounds__(256) void fill_batch_kernel(const FillJob *__restri
     __syncthreads();   // s_tile / s_job read by all before thread 0 overwrites them
     if (t >= ntiles) return;
     const FillJob J = jobs[jb];
-    fill_tile(J, t - J.tile0, gs, wt);
+    fill_tile(J, t - J.tile0, wt);
   }
 }
 
@@ -241,7 +254,7 @@ void launch_fill_all(const std::vector<BodyData *> &bodies, hipStream_t s) {
   long tiles = 0;
   for (int o = 0; o < nb; ++o) {
     BodyData &b = *bodies[order[o]];
-    MFS_REQUIRE(b.nd <= 4 * MAXS, "P/2+1 exceeds the fill kernel's mode capacity (P <= 206)");
+    MFS_REQUIRE(b.nd <= 104, "P/2+1 exceeds the fill kernel's mode capacity (P <= 206)");
     const int L = b.q / 2 + 1;
     tabs[o].alloc((size_t)L * (b.nd + 1) * sizeof(double));
     hipLaunchKernelGGL(fill_table_kernel, dim3(cdiv(L * (b.nd + 1), 256)), dim3(256), 0, s, b.q, b.nd,
