@@ -36,7 +36,9 @@ namespace {
 constexpr int CH = 256;     // rows per workgroup in the panel column step
 constexpr int KR = 256;     // rows per workgroup of V^H Y (split-K slice)
 constexpr int KS = 16;      // rows per LDS stage in V^H Y
-constexpr int YT = 128;     // columns of Y per workgroup in V^H Y
+// columns of Y per workgroup in V^H Y: 128, or 64 for 64-column panels (four
+// 16 x 16 tiles a wave, 2 waves/SIMD, instead of eight at 1)
+template <int NB> constexpr int yt_of() { return NB == 64 ? 64 : 128; }
 constexpr int WT = 64;      // columns per workgroup in W2 and in the update
 constexpr int UR = 64;      // rows per workgroup in the update
 
@@ -363,6 +365,7 @@ template <int NB>
 __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0, int which,
                                                       int withV, int cend, double2 *__restrict__ P, int ldp,
                                                       int nkcmax) {
+  constexpr int YT = yt_of<NB>();
   constexpr int CB = YT / 16;                 // 16-column blocks of the tile
   constexpr int TPW = (NB / 16) * CB / 4;     // 16 x 16 tiles per wave
   static_assert(TPW >= 1 && TPW <= CB && CB % TPW == 0, "a wave's tiles share one row block");
@@ -652,7 +655,7 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
   const int ny = (withV ? NB : 0) + ncols_max;
   const int nkc = cdiv(std::max(mmax - k0, 1), KR);
   if (ny > 0)
-    hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
+    hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, yt_of<NB>()), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
                        cend, w.P.as<double2>(), w.ldp, w.nkcmax);
   if (build_t)
     hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,

@@ -347,6 +347,29 @@ def test_qr_panel_widths(mfs, ctx, small_oracle, monkeypatch, nb):
     assert e < 1e-13
 
 
+@pytest.mark.parametrize("form", ["blocked", "unblocked"])
+def test_pivoted_qr_forms(mfs, ctx, monkeypatch, form):
+    """Both forms of the column-pivoted QR of the triangles (blocked: panels
+    of 32 with the updates deferred and the norms downdated; unblocked: one
+    column step at a time, norms recomputed), forced on the small periodic
+    body and on the k = 10 body (its 200-column blocks need 7 panels):
+    singular values against LAPACK on the GPU's own blocks, 1e-13 of the
+    largest; the same kept ranks either way."""
+    monkeypatch.setenv("MFS_QRCP", form)
+    for b in (W.small_periodic().body, W.periodic_k10(1).body):
+        op = make_op(mfs, ctx, b)
+        blocks = op.blocks().cpu().numpy().transpose(0, 2, 1)
+        ranks = op.factor_modes(1e-10)
+        sv = op.singular_values(0)
+        e = 0.0
+        for n in range(blocks.shape[0]):
+            s_own = np.linalg.svd(blocks[n], compute_uv=False)
+            e = max(e, float(np.max(np.abs(sv[n][: s_own.size] - s_own)) / s_own[0]))
+            assert abs(int(ranks[n]) - int(np.sum(s_own > 1e-10 * s_own[0]))) <= 1, n
+        log(f"[qrcp {form}] N={b.N} P={b.P}: singular values vs LAPACK {e:.2e}")
+        assert e < 1e-13
+
+
 def test_cod_operator_fields(mfs, ctx, monkeypatch):
     """The one-body factorisation with the truncated complete orthogonal
     decomposition (MFS_OPINV=cod: pivoted QR of the triangle, cut at the
