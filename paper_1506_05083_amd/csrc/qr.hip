@@ -18,7 +18,7 @@
 //   bqr_vhy_kernel   P = V^H [V | C], split over 256-row slices (partials);
 //   bqr_t_kernel     T from the V^H V part (forward, columnwise);
 //   bqr_w2_kernel    W2 = op(T) (V^H C), the slices summed;
-//   bqr_update       C -= V W2, 64 x 64 tiles, 4 x 4 outputs per thread.
+//   bqr_update       C -= V W2 on the matrix cores.
 // The same three apply kernels with T in place of T^H, run over the panels
 // in reverse, form U = Q [U_R; 0] for the explicit left singular vectors.
 #include <cmath>
@@ -36,11 +36,16 @@ namespace {
 constexpr int CH = 256;     // rows per workgroup in the panel column step
 constexpr int KR = 256;     // rows per workgroup of V^H Y (split-K slice)
 constexpr int KS = 16;      // rows per LDS stage in V^H Y
-// columns of Y per workgroup in V^H Y: 128, or 64 for 64-column panels (four
-// 16 x 16 tiles a wave, 2 waves/SIMD, instead of eight at 1)
-template <int NB> constexpr int yt_of() { return NB == 64 ? 64 : 128; }
+// V^H Y tiles: YT columns of Y a workgroup, a wave IB x CB blocks of 16 x 16
+// of the NB x YT tile, OCC waves a SIMD, DB: LDS stages double-buffered (one
+// barrier a stage).  Measured on 8 matrices 4608 x 1275: 64-column panels
+// 54 TFLOP/s (43 with one 16-row block of V^H and four column blocks a wave
+// and the fragments loaded per product), 32: 43 (33), 16: 3.8 TB/s of Y.
+template <int NB> struct VhyShape;
+template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0; };
+template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1; };
+template <> struct VhyShape<16> { static constexpr int YT = 64, IB = 1, CB = 1, OCC = 4, DB = 1; };
 constexpr int WT = 64;      // columns per workgroup in W2 and in the update
-constexpr int UR = 64;      // rows per workgroup in the update
 
 // element r of Householder vector i of the panel starting at column k0
 __device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
@@ -355,20 +360,21 @@ __device__ inline double2 yel(const MatDesc &d, int k0, int nv, const double2 *B
 
 // P[mat][kc][i][c] = sum over rows of slice kc of conj(V[r][i]) Y[r][c],
 // Y = [V | B] (withV) or B, on the FP64 matrix cores.  The slice's rows are
-// staged through LDS KS at a time (coalesced loads down the columns); a
-// 16 x 16 tile of P is one v_mfma_f64_16x16x4f64 chain per real product
-// (four per complex one), the NB x YT tile of the workgroup split over its
-// four waves so that a wave keeps one 16-row block of V^H: NB = 64, one
-// block and 8 column blocks a wave; 32, 4; 16, 2.  cend (which = 0): the
-// trailing columns end before matrix column cend.
+// staged through LDS KS at a time (coalesced loads down the columns, the
+// next stage's loads issued before the current stage's products); a 16 x 16
+// tile of P is one v_mfma_f64_16x16x4f64 chain per real product (four per
+// complex one), the NB x YT tile of the workgroup split over its four waves
+// as VhyShape says.  cend (which = 0): the trailing columns end before
+// matrix column cend.
 template <int NB>
-__global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0, int which,
-                                                      int withV, int cend, double2 *__restrict__ P, int ldp,
-                                                      int nkcmax) {
-  constexpr int YT = yt_of<NB>();
-  constexpr int CB = YT / 16;                 // 16-column blocks of the tile
-  constexpr int TPW = (NB / 16) * CB / 4;     // 16 x 16 tiles per wave
-  static_assert(TPW >= 1 && TPW <= CB && CB % TPW == 0, "a wave's tiles share one row block");
+__global__ __launch_bounds__(256, VhyShape<NB>::OCC) void bqr_vhy_kernel(const MatDesc *__restrict__ descs, int k0,
+                                                                        int which, int withV, int cend,
+                                                                        double2 *__restrict__ P, int ldp,
+                                                                        int nkcmax) {
+  using S = VhyShape<NB>;
+  constexpr int YT = S::YT, IB = S::IB, CB = S::CB, DB = S::DB;
+  constexpr int NWI = NB / 16 / IB;   // waves along the rows of P
+  static_assert(NWI * (YT / 16 / CB) == 4, "four waves cover the tile");
   const MatDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -383,19 +389,19 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
   const int rbeg = k0 + blockIdx.y * KR;
   if (rbeg >= d.m) return;
   const int rend = min(d.m, rbeg + KR);
-  __shared__ double2 Vs[KS][NB + 1];
-  __shared__ double2 Ys[KS][YT + 1];
+  __shared__ double2 Vs[DB + 1][KS][NB + 1];
+  __shared__ double2 Ys[DB + 1][KS][YT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, k4 = lane >> 4;
-  const int ib = (wv * TPW) / CB, cb0 = (wv * TPW) % CB;
-  dx4 re[TPW], im[TPW];
+  const int wi = wv % NWI, wc = wv / NWI;
+  dx4 re[IB][CB], im[IB][CB];
 #pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    re[u] = dx4{0.0, 0.0, 0.0, 0.0};
-    im[u] = re[u];
-  }
-  // stage r0's rows in registers (coalesced down the columns); the next
-  // stage's loads are issued before the current stage's products
+  for (int u = 0; u < IB; ++u)
+#pragma unroll
+    for (int v = 0; v < CB; ++v) {
+      re[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+      im[u][v] = re[u][v];
+    }
   double2 vv[KS * NB / 256], yy[KS * YT / 256];
   auto load_stage = [&](int r0) {
 #pragma unroll
@@ -410,44 +416,72 @@ __global__ __launch_bounds__(256) void bqr_vhy_kernel(const MatDesc *__restrict_
       yy[u] = yel(d, k0, nv, B, ldb, ny, r0 + rr, c0 + cc, rend);
     }
   };
-  load_stage(rbeg);
-  for (int r0 = rbeg; r0 < rend; r0 += KS) {
+  auto store_stage = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < KS * NB / 256; ++u) {
       const int idx = tid + 256 * u;
-      Vs[idx % KS][idx / KS] = vv[u];
+      Vs[buf][idx % KS][idx / KS] = vv[u];
     }
 #pragma unroll
     for (int u = 0; u < KS * YT / 256; ++u) {
       const int idx = tid + 256 * u;
-      Ys[idx % KS][idx / KS] = yy[u];
+      Ys[buf][idx % KS][idx / KS] = yy[u];
     }
-    __syncthreads();
-    if (r0 + KS < rend) load_stage(r0 + KS);
+  };
+  auto products = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
       // A[i][k] = conj(V[row k][col i]) (lane l16 + 16 k4 holds A[l16][k4]),
       // B[k][c] = Y[row k][col c]
-      const double2 a = Vs[kk + k4][16 * ib + l16];
+      double2 a[IB], y[CB];
 #pragma unroll
-      for (int u = 0; u < TPW; ++u) {
-        const double2 y = Ys[kk + k4][16 * (cb0 + u) + l16];
-        re[u] = mfma_f64(a.x, y.x, re[u]);
-        re[u] = mfma_f64(a.y, y.y, re[u]);
-        im[u] = mfma_f64(a.x, y.y, im[u]);
-        im[u] = mfma_f64(-a.y, y.x, im[u]);
-      }
+      for (int u = 0; u < IB; ++u) a[u] = Vs[buf][kk + k4][16 * (wi * IB + u) + l16];
+#pragma unroll
+      for (int v = 0; v < CB; ++v) y[v] = Ys[buf][kk + k4][16 * (wc * CB + v) + l16];
+#pragma unroll
+      for (int u = 0; u < IB; ++u)
+#pragma unroll
+        for (int v = 0; v < CB; ++v) {
+          re[u][v] = mfma_f64(a[u].x, y[v].x, re[u][v]);
+          re[u][v] = mfma_f64(a[u].y, y[v].y, re[u][v]);
+          im[u][v] = mfma_f64(a[u].x, y[v].y, im[u][v]);
+          im[u][v] = mfma_f64(-a[u].y, y[v].x, im[u][v]);
+        }
     }
+  };
+  load_stage(rbeg);
+  if (DB) {
+    int buf = 0;
+    store_stage(0);
     __syncthreads();
+    for (int r0 = rbeg; r0 < rend; r0 += KS) {
+      const bool more = r0 + KS < rend;
+      if (more) load_stage(r0 + KS);
+      products(buf);
+      if (more) store_stage(buf ^ 1);   // the other buffer: read by no wave since the last barrier
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int r0 = rbeg; r0 < rend; r0 += KS) {
+      store_stage(0);
+      __syncthreads();
+      if (r0 + KS < rend) load_stage(r0 + KS);
+      products(0);
+      __syncthreads();
+    }
   }
-  // lane l16 + 16 k4 holds P[16 ib + k4 + 4 v][column block's l16] in element v
+  // lane l16 + 16 k4 holds P[16 (wi IB + u) + k4 + 4 e][column block's l16] in element e
   double2 *out = P + ((size_t)blockIdx.z * nkcmax + blockIdx.y) * NB * ldp;
 #pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    const int c = c0 + 16 * (cb0 + u) + l16;
+  for (int v = 0; v < CB; ++v) {
+    const int c = c0 + 16 * (wc * CB + v) + l16;
     if (c < ny) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(size_t)(16 * ib + k4 + 4 * v) * ldp + c] = cz(re[u][v], im[u][v]);
+      for (int u = 0; u < IB; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          out[(size_t)(16 * (wi * IB + u) + k4 + 4 * e) * ldp + c] = cz(re[u][v][e], im[u][v][e]);
     }
   }
 }
@@ -564,18 +598,27 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
   }
 }
 
-// B[r][c] -= sum_i V[r][i] W2[i][c], rows r >= k0, on the FP64 matrix cores,
-// formed transposed so that a fragment row of the product is a column of B
-// (16 consecutive rows per lane group: 256-byte segments):
-// D[c][r] = sum_i W2[i][c] V[r][i].  Workgroup: a 64 x 64 tile of B; wave
-// w takes its columns c0 + 16 w .. + 15 and all 64 rows (four 16-row
-// blocks, four real products each per 4-step of i).  V and W2 come
-// straight from global memory (L2: every wave and every column tile of the
-// panel reads the same V).  cend (which = 0): the trailing columns end
-// before matrix column cend.
+// C -= V W2 on the FP64 matrix cores, in transposed orientation (D = W2^T
+// V^T, so that a lane's outputs run down a column: 256-byte stores).  A wave
+// updates 2 x 2 tiles of 16 x 16 (32 rows x 32 columns), each a real and an
+// imaginary accumulator, and loads the next k-step's fragments of W2 and V
+// while it multiplies the current ones; the four waves of a workgroup stack
+// along the rows (128 x 32), three workgroups a CU.  (Measured on 8 matrices
+// 4608 x 1275 with 64-column panels: 51 TFLOP/s, against 40 for 32 x 64
+// wave tiles at two waves a SIMD and 26 for one 16-column block a wave.)
+// cend (which = 0): the trailing columns end before matrix column cend.
+struct UpdShape {
+  static constexpr int RB = 2;              // 16-row blocks a wave
+  static constexpr int CB = 2;              // 16-column blocks a wave
+  static constexpr int UR = 4 * 16 * RB;    // rows of a workgroup tile (waves along the rows)
+  static constexpr int UC = 16 * CB;        // columns of a workgroup tile
+};
+
 template <int NB>
-__global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restrict__ descs, int k0, int which,
-                                                         int cend, const double2 *__restrict__ W2, int ldw) {
+__global__ __launch_bounds__(256, 3) void bqr_update_kernel(const MatDesc *__restrict__ descs, int k0, int which,
+                                                            int cend, const double2 *__restrict__ W2, int ldw) {
+  using S = UpdShape;
+  constexpr int RB = S::RB, CB = S::CB;
   const MatDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -583,53 +626,74 @@ __global__ __launch_bounds__(256) void bqr_update_kernel(const MatDesc *__restri
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
   if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
-  const int c0 = blockIdx.y * WT;
-  if (c0 >= nb_cols) return;
-  const int r0 = k0 + blockIdx.x * UR;
-  if (r0 >= d.m) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, k4 = lane >> 4;
-  const int cw = c0 + 16 * wv;   // this wave's first column (no barriers: an idle wave may leave)
-  if (cw >= nb_cols) return;
+  // this wave's first row and column (no barriers: an idle wave may leave)
+  const int rw = k0 + blockIdx.y * S::UR + wv * 16 * RB;
+  const int cw = blockIdx.x * S::UC;
+  if (rw >= d.m || cw >= nb_cols) return;
+  const int ncb = min(CB, (nb_cols - cw + 15) / 16);   // column blocks holding columns (wave-uniform)
+  const int nrb = min(RB, (d.m - rw + 15) / 16);       // row blocks holding rows
   const double2 *w2 = W2 + (size_t)blockIdx.z * NB * ldw;
-  constexpr int RB = UR / 16;
-  dx4 re[RB], im[RB];
+  dx4 re[RB][CB], im[RB][CB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    re[rb] = dx4{0.0, 0.0, 0.0, 0.0};
-    im[rb] = re[rb];
-  }
-#pragma unroll 4
-  for (int ks = 0; ks < NB / 4; ++ks) {
-    const int i = 4 * ks + k4;
-    // A[c][i] = W2[i][c] (lane l16 + 16 k4 holds A[l16][k4]); B[i][r] = V[r][i]
-    const double2 a = ld_or0(w2, (size_t)i * ldw + cw + l16, cw + l16 < nb_cols);
-    double2 v[RB];
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) v[rb] = vel(d, k0, i, r0 + 16 * rb + l16);   // zero for rows >= m
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      re[rb] = mfma_f64(a.x, v[rb].x, re[rb]);
-      re[rb] = mfma_f64(-a.y, v[rb].y, re[rb]);
-      im[rb] = mfma_f64(a.x, v[rb].y, im[rb]);
-      im[rb] = mfma_f64(a.y, v[rb].x, im[rb]);
+    for (int cb = 0; cb < CB; ++cb) {
+      re[rb][cb] = dx4{0.0, 0.0, 0.0, 0.0};
+      im[rb][cb] = re[rb][cb];
     }
+  // A[c][i] = W2[i][c] (lane l16 + 16 k4 holds A[l16][k4]); B[i][r] = V[r][i]
+  auto load = [&](int ks, double2 (&a)[CB], double2 (&v)[RB]) {
+    const int i = 4 * ks + k4;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int c = cw + 16 * cb + l16;
+      a[cb] = ld_or0(w2, (size_t)i * ldw + c, c < nb_cols);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) v[rb] = vel(d, k0, i, rw + 16 * rb + l16);   // zero for rows >= m
+  };
+  auto mma = [&](const double2 (&a)[CB], const double2 (&v)[RB]) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (rb >= nrb || cb >= ncb) continue;   // wave-uniform: a block with no rows or no columns
+        re[rb][cb] = mfma_f64(a[cb].x, v[rb].x, re[rb][cb]);
+        re[rb][cb] = mfma_f64(-a[cb].y, v[rb].y, re[rb][cb]);
+        im[rb][cb] = mfma_f64(a[cb].x, v[rb].y, im[rb][cb]);
+        im[rb][cb] = mfma_f64(a[cb].y, v[rb].x, im[rb][cb]);
+      }
+  };
+  static_assert(NB % 8 == 0, "k-steps in pairs");
+  double2 a0[CB], v0[RB], a1[CB], v1[RB];
+  load(0, a0, v0);
+#pragma unroll
+  for (int ks = 0; ks < NB / 4; ks += 2) {
+    load(ks + 1, a1, v1);
+    mma(a0, v0);
+    if (ks + 2 < NB / 4) load(ks + 2, a0, v0);
+    mma(a1, v1);
   }
-  // lane l16 + 16 k4 holds D[k4 + 4 e][l16] in element e: column cw + k4 + 4 e, row r0 + 16 rb + l16
+  // lane l16 + 16 k4 holds D[k4 + 4 e][l16] in element e of tile (rb, cb):
+  // column cw + 16 cb + k4 + 4 e, row rw + 16 rb + l16
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int c = cw + k4 + 4 * e;
-    if (c >= nb_cols) continue;
-    double2 *col = B + (size_t)c * ldb;
+  for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int r = r0 + 16 * rb + l16;
-      if (r < d.m) {
-        const double2 x = col[r];
-        col[r] = cz(x.x - re[rb][e], x.y - im[rb][e]);
+    for (int e = 0; e < 4; ++e) {
+      const int c = cw + 16 * cb + k4 + 4 * e;
+      if (c >= nb_cols) continue;
+      double2 *col = B + (size_t)c * ldb;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int r = rw + 16 * rb + l16;
+        if (r < d.m) {
+          const double2 x = col[r];
+          col[r] = cz(x.x - re[rb][cb][e], x.y - im[rb][cb][e]);
+        }
       }
     }
-  }
 }
 
 struct ApplyWork {
@@ -655,7 +719,7 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
   const int ny = (withV ? NB : 0) + ncols_max;
   const int nkc = cdiv(std::max(mmax - k0, 1), KR);
   if (ny > 0)
-    hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, yt_of<NB>()), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
+    hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, VhyShape<NB>::YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
                        cend, w.P.as<double2>(), w.ldp, w.nkcmax);
   if (build_t)
     hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
@@ -663,7 +727,8 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
   if (ncols_max > 0) {
     hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
                        withV, trans, cend, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw, Tx);
-    hipLaunchKernelGGL(bqr_update_kernel<NB>, dim3(cdiv(std::max(mmax - k0, 1), UR), cdiv(ncols_max, WT), nmat),
+    hipLaunchKernelGGL(bqr_update_kernel<NB>,
+                       dim3(cdiv(ncols_max, UpdShape::UC), cdiv(std::max(mmax - k0, 1), UpdShape::UR), nmat),
                        dim3(256), 0, s, descs, k0, which, cend, w.W2.as<double2>(), w.ldw);
   }
   HIP_CHECK(hipGetLastError());
