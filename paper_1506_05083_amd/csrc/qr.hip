@@ -486,51 +486,81 @@ __global__ __launch_bounds__(256, VhyShape<NB>::OCC) void bqr_vhy_kernel(const M
   }
 }
 
-// T of the panel (forward, columnwise): T[i][i] = tau_i,
-// T[0:i, i] = -tau_i T[0:i, 0:i] (V^H V)[0:i, i]; V^H V from the slices of P.
-// Written to the matrix's T of panel k0 / NB, or to Tx[mat] if Tx is set
-// (an inner panel's T, needed only until its update is done).
+// T of the panel (forward, columnwise): H_0 ... H_{NB-1} = I - V T V^H.
+// Diagonal blocks of 16 by the column recurrence T[i][i] = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] (V^H V)[0:i, i], one wave a block, the
+// blocks side by side (16 steps for any NB); then adjacent blocks of h = 16, 32
+// joined as T12 = -T1 (V1^H V2) T2 (the product of two block reflectors).
+// V^H V from the slices of P.  Written to the matrix's T of panel k0 / NB,
+// or to Tx[mat] if Tx is set (an inner panel's T, needed only until its
+// update is done).
 template <int NB>
 __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ descs, int k0,
                                                     const double2 *__restrict__ P, int ldp, int nkcmax,
                                                     double2 *__restrict__ Tx) {
+  static_assert(NB % 16 == 0 && NB <= 64, "diagonal blocks of 16, one wave each");
   const MatDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
   const int nkc = (d.m - k0 + KR - 1) / KR;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ double2 gram[NB][NB + 1];
   __shared__ double2 Tsh[NB][NB + 1];
-  __shared__ double2 tmp[NB];
+  __shared__ double2 X[NB / 2][NB / 2 + 1];
   const double2 *base = P + (size_t)blockIdx.x * nkcmax * NB * ldp;
   {
+    // strict upper part, summed over the slices (consecutive threads along a row of P)
     double2 t[NB * NB / 256];
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) t[u] = cz(0.0, 0.0);
     for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
       for (int u = 0; u < NB * NB / 256; ++u) {
-        const int idx = tid + 256 * u, g = idx % NB, i = idx / NB;
+        const int idx = tid + 256 * u, i = idx % NB, g = idx / NB;
         t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + g) * ldp + i, g < i && i < nbp));
       }
     }
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) {
       const int idx = tid + 256 * u;
-      gram[idx % NB][idx / NB] = t[u];
+      gram[idx / NB][idx % NB] = t[u];
     }
+    for (int idx = tid; idx < NB * (NB + 1); idx += 256) Tsh[idx / (NB + 1)][idx % (NB + 1)] = cz(0.0, 0.0);
   }
   __syncthreads();
-  for (int i = 0; i < nbp; ++i) {
-    const double2 ti = d.tau[k0 + i];
-    if (tid < i) tmp[tid] = cmul(cz(-ti.x, -ti.y), gram[tid][i]);
+  // diagonal blocks, all at once: wave w < NB / 16 takes block w (lane l: row 16 w + l)
+  __shared__ double2 tmp[NB];
+  const bool blk = wv < NB / 16 && lane < 16;
+  const int o = 16 * wv;
+  for (int i = 0; i < 16; ++i) {
+    const int ci = o + i;
+    const double2 ti = blk && ci < nbp ? d.tau[k0 + ci] : cz(0.0, 0.0);
+    if (blk && lane < i) tmp[o + lane] = cmul(cz(-ti.x, -ti.y), gram[o + lane][ci]);
     __syncthreads();
-    if (tid < i) {
+    if (blk && lane < i) {
       double2 acc = cz(0.0, 0.0);
-      for (int g = tid; g < i; ++g) cfma(acc, Tsh[tid][g], tmp[g]);
-      Tsh[tid][i] = acc;
+      for (int g = lane; g < i; ++g) cfma(acc, Tsh[o + lane][o + g], tmp[o + g]);
+      Tsh[o + lane][ci] = acc;
     }
-    if (tid == i) Tsh[i][i] = ti;
+    if (blk && lane == i) Tsh[ci][ci] = ti;
+    __syncthreads();
+  }
+  for (int h = 16; h < NB; h *= 2) {
+    // pairs (o, o + h), o = 2 h p: X = G12 T2, then T12 = -T1 X
+    const int npair = NB / (2 * h), nout = npair * h * h;
+    for (int idx = tid; idx < nout; idx += 256) {
+      const int p = idx / (h * h), r = (idx / h) % h, c = idx % h, o = 2 * h * p;
+      double2 acc = cz(0.0, 0.0);
+      for (int g = 0; g <= c; ++g) cfma(acc, gram[o + r][o + h + g], Tsh[o + h + g][o + h + c]);
+      X[p * h + r][c] = acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nout; idx += 256) {
+      const int p = idx / (h * h), r = (idx / h) % h, c = idx % h, o = 2 * h * p;
+      double2 acc = cz(0.0, 0.0);
+      for (int g = r; g < h; ++g) cfma(acc, Tsh[o + r][o + g], X[p * h + g][c]);
+      Tsh[o + r][o + h + c] = cz(-acc.x, -acc.y);
+    }
     __syncthreads();
   }
   double2 *T = Tx ? Tx + (size_t)blockIdx.x * NB * NB : d.T + (size_t)(k0 / NB) * NB * NB;
