@@ -7,10 +7,12 @@
 // from HBM once per call.  Mode 1 (periodizing matrix Q): one matrix per
 // right-hand side.
 //
-// stage 1: Y[mat][c][i] = sum_m conj(U[m][i]) x_c[m], 64 rows of Y per
-//          workgroup, 16-row chunks of U and X staged through LDS;
-// stage 2: out_c[jj] = sum_i W[jj][i] Y[c][i], 64 output rows per workgroup,
-//          W streamed with coalesced column reads.
+// stage 1: Y[mat][c][i] = sum_m conj(U[m][i]) x_c[m], 16 rows of Y a
+//          workgroup, 48-row chunks of U and X staged through LDS;
+// stage 2: out_c[jj] = sum_i W[jj][i] Y[c][i], 16 output rows a workgroup,
+//          64-column chunks of W and Y staged through LDS.
+// (Small blocks, e.g. 33 modes of 240 x 200: many narrow workgroups and few
+// chunks, so that the call is not a chain of dependent load latencies.)
 // Mode 1 has a single right-hand side per matrix, so both stages are
 // matrix-vector products bound by streaming U and W from HBM: stage 1 gives
 // every column of U its own wave (a dot product with x), stage 2 gives every
@@ -21,7 +23,10 @@ namespace mfs {
 namespace {
 
 constexpr int MAXC = 32;  // columns per call (2 * nrhs for mode 0)
-constexpr int KC = 16;    // reduction chunk
+constexpr int S1I = 16;   // stage 1: columns of U a workgroup
+constexpr int KC1 = 48;   // stage 1: rows of U and x a chunk
+constexpr int S2R = 16;   // stage 2: output rows a workgroup
+constexpr int KC2 = 64;   // stage 2: columns of W a chunk
 
 __device__ inline int ncols_of(const PinvJob &j, int mat) {
   if (j.mode == 1) return 1;
@@ -41,33 +46,35 @@ __global__ __launch_bounds__(256) void pinv_stage1(PinvJob j) {
   const int mat = blockIdx.y;
   const MatDesc d = j.descs[mat];
   const int r = d.rank[0];
-  const int i0 = blockIdx.x * 64;
+  const int i0 = blockIdx.x * S1I;
   if (i0 >= r) return;
   const int nc = ncols_of(j, mat);
-  __shared__ double2 Us[KC][65];
-  __shared__ double2 Xs[KC][MAXC + 1];
+  __shared__ double2 Us[S1I][KC1 + 1];
+  __shared__ double2 Xs[MAXC][KC1 + 1];
   const int tid = threadIdx.x;
-  const int ii = tid & 63, cg = tid >> 6;
-  double2 acc[MAXC / 4];
+  const int ii = tid % S1I, cg = tid / S1I;   // column i0 + ii of U, right-hand sides cg + 16 t
+  double2 acc[MAXC / 16];
 #pragma unroll
-  for (int t = 0; t < MAXC / 4; ++t) acc[t] = cz(0.0, 0.0);
-  for (int m0 = 0; m0 < d.m; m0 += KC) {
-    for (int idx = tid; idx < KC * 64; idx += 256) {
-      const int mm = idx % KC, c = idx / KC;
+  for (int t = 0; t < MAXC / 16; ++t) acc[t] = cz(0.0, 0.0);
+  for (int m0 = 0; m0 < d.m; m0 += KC1) {
+    // coalesced down the columns of U and of the right-hand sides
+    for (int idx = tid; idx < KC1 * S1I; idx += 256) {
+      const int mm = idx % KC1, c = idx / KC1;
       const int m = m0 + mm, i = i0 + c;
-      Us[mm][c] = (m < d.m && i < r) ? d.u[(size_t)i * d.lda + m] : cz(0.0, 0.0);
+      Us[c][mm] = (m < d.m && i < r) ? d.u[(size_t)i * d.lda + m] : cz(0.0, 0.0);
     }
-    for (int idx = tid; idx < KC * MAXC; idx += 256) {
-      const int mm = idx % KC, c = idx / KC;
+    for (int idx = tid; idx < KC1 * nc; idx += 256) {
+      const int mm = idx % KC1, c = idx / KC1;
       const int m = m0 + mm;
-      Xs[mm][c] = (m < d.m && c < nc) ? j.x[col_offset(j, mat, c, d.m, j.ldx) + m] : cz(0.0, 0.0);
+      Xs[c][mm] = m < d.m ? j.x[col_offset(j, mat, c, d.m, j.ldx) + m] : cz(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll 4
-    for (int mm = 0; mm < KC; ++mm) {
-      const double2 u = Us[mm][ii];
+    for (int mm = 0; mm < KC1; ++mm) {
+      const double2 u = Us[ii][mm];
 #pragma unroll
-      for (int t = 0; t < MAXC / 4; ++t) cfmac(acc[t], u, Xs[mm][cg + 4 * t]);
+      for (int t = 0; t < MAXC / 16; ++t)
+        if (cg + 16 * t < nc) cfmac(acc[t], u, Xs[cg + 16 * t][mm]);
     }
     __syncthreads();
   }
@@ -75,8 +82,8 @@ __global__ __launch_bounds__(256) void pinv_stage1(PinvJob j) {
   if (i < r) {
     double2 *y = j.ywork + (size_t)mat * j.maxcols * j.maxr;
 #pragma unroll
-    for (int t = 0; t < MAXC / 4; ++t) {
-      const int c = cg + 4 * t;
+    for (int t = 0; t < MAXC / 16; ++t) {
+      const int c = cg + 16 * t;
       if (c < nc) y[(size_t)c * j.maxr + i] = acc[t];
     }
   }
@@ -88,37 +95,42 @@ __global__ __launch_bounds__(256) void pinv_stage2(PinvJob j) {
   const int r = d.rank[0];
   const int nc = ncols_of(j, mat);
   const int n = d.n;
-  const int jj0 = blockIdx.x * 64;
+  const int jj0 = blockIdx.x * S2R;
   if (jj0 >= n) return;
-  __shared__ double2 Ys[MAXC][65];
+  __shared__ double2 Ws[KC2][S2R + 1];
+  __shared__ double2 Ys[MAXC][KC2 + 1];
   const int tid = threadIdx.x;
-  const int jr = tid & 63, cg = tid >> 6;
-  const int row = jj0 + jr;
-  double2 acc[MAXC / 4];
+  const int jr = tid % S2R, cg = tid / S2R;   // output row jj0 + jr, right-hand sides cg + 16 t
+  double2 acc[MAXC / 16];
 #pragma unroll
-  for (int t = 0; t < MAXC / 4; ++t) acc[t] = cz(0.0, 0.0);
+  for (int t = 0; t < MAXC / 16; ++t) acc[t] = cz(0.0, 0.0);
   const double2 *y = j.ywork + (size_t)mat * j.maxcols * j.maxr;
-  for (int i0 = 0; i0 < r; i0 += 64) {
-    for (int idx = tid; idx < MAXC * 64; idx += 256) {
-      const int ii = idx % 64, c = idx / 64;
+  for (int i0 = 0; i0 < r; i0 += KC2) {
+    for (int idx = tid; idx < KC2 * S2R; idx += 256) {
+      const int rr = idx % S2R, ii = idx / S2R;
+      const int i = i0 + ii, row = jj0 + rr;
+      Ws[ii][rr] = (i < r && row < n) ? d.w[(size_t)i * d.ldg + row] : cz(0.0, 0.0);
+    }
+    for (int idx = tid; idx < KC2 * nc; idx += 256) {
+      const int ii = idx % KC2, c = idx / KC2;
       const int i = i0 + ii;
-      Ys[c][ii] = (i < r && c < nc) ? y[(size_t)c * j.maxr + i] : cz(0.0, 0.0);
+      Ys[c][ii] = i < r ? y[(size_t)c * j.maxr + i] : cz(0.0, 0.0);
     }
     __syncthreads();
-    const int iend = min(64, r - i0);
-    if (row < n) {
-      for (int ii = 0; ii < iend; ++ii) {
-        const double2 w = d.w[(size_t)(i0 + ii) * d.ldg + row];
+#pragma unroll 4
+    for (int ii = 0; ii < KC2; ++ii) {
+      const double2 w = Ws[ii][jr];
 #pragma unroll
-        for (int t = 0; t < MAXC / 4; ++t) cfma(acc[t], w, Ys[cg + 4 * t][ii]);
-      }
+      for (int t = 0; t < MAXC / 16; ++t)
+        if (cg + 16 * t < nc) cfma(acc[t], w, Ys[cg + 16 * t][ii]);
     }
     __syncthreads();
   }
+  const int row = jj0 + jr;
   if (row < n) {
 #pragma unroll
-    for (int t = 0; t < MAXC / 4; ++t) {
-      const int c = cg + 4 * t;
+    for (int t = 0; t < MAXC / 16; ++t) {
+      const int c = cg + 16 * t;
       if (c < nc) j.out[col_offset(j, mat, c, n, j.ldo) + row] = acc[t];
     }
   }
@@ -191,9 +203,9 @@ void launch_pinv_apply(const PinvJob &j, hipStream_t s) {
     HIP_CHECK(hipGetLastError());
     return;
   }
-  hipLaunchKernelGGL(pinv_stage1, dim3(cdiv(j.maxr, 64), j.nmat), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(pinv_stage1, dim3(cdiv(j.maxr, S1I), j.nmat), dim3(256), 0, s, j);
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(pinv_stage2, dim3(cdiv(j.maxn, 64), j.nmat), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(pinv_stage2, dim3(cdiv(j.maxn, S2R), j.nmat), dim3(256), 0, s, j);
   HIP_CHECK(hipGetLastError());
 }
 

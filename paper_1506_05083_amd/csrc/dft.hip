@@ -45,12 +45,19 @@ __global__ __launch_bounds__(256) void dft_kernel(int Pin, int Pout, int Q, int 
   const int x = x0 + xx;
   for (int o = threadIdx.x / XT; o < Pout; o += blockDim.x / XT) {
     double2 acc = cz(0.0, 0.0);
+    // ph = (ni(i) o) mod Q, stepped by o (o < Q) and set afresh where ni(i)
+    // turns negative (the first negative mode of in_modes)
+    const int ohalf = in_modes ? Pin / 2 + 1 : Pin;
+    const int oq = o % Q;
+    int ph = 0;
     for (int i = 0; i < Pin; ++i) {
-      int ni = i;
-      if (in_modes && 2 * i > Pin) ni = i - Pin;
-      long ph = ((long)ni * o) % Q;
-      if (ph < 0) ph += Q;
+      if (i == ohalf) {
+        long t = ((long)(i - Pin) * o) % Q;
+        ph = (int)(t < 0 ? t + Q : t);
+      }
       cfma(acc, tile[i * XT + xx], tw[ph]);
+      ph += oq;
+      if (ph >= Q) ph -= Q;
     }
     if (x < X) out[(size_t)r * ld_out + (size_t)o * ldo + x] = cscale(acc, scale);
   }
