@@ -403,32 +403,21 @@ __global__ __launch_bounds__(TI) void trinv_diag_kernel(const MatDesc *__restric
     for (int c = 0; c < nb; ++c) x.a[(size_t)(j0 + c) * x.lda + j0 + t] = Xs[c][t];
 }
 
-// blocks (i, i + d) of every matrix: workgroup (i, matrix), 256 threads, a
-// 4 x 4 tile of the 64 x 64 block per thread (rows ty + 16 a, columns
-// tx + 16 b)
-__global__ __launch_bounds__(256) void trinv_off_kernel(const MatDesc *__restrict__ rd,
-                                                        const MatDesc *__restrict__ xd, int d) {
-  const MatDesc r = rd[blockIdx.y], x = xd[blockIdx.y];
-  const int n = x.n;
-  const int i0 = blockIdx.x * TI, j0 = (blockIdx.x + d) * TI;
-  if (j0 >= n) return;
-  const int ni = TI, nj = min(TI, n - j0);   // row block i is whole (it precedes j)
+// acc += sum over k in [kbeg, kend) of R[i0 + rows, k] X[k, j0 + cols] (a
+// 4 x 4 tile of the 64 x 64 block per thread: rows ty + 16 a, columns
+// tx + 16 b), TK values of k at a time through LDS, both operands read
+// down their columns
+__device__ inline void trinv_accum(const MatDesc &r, const MatDesc &x, int i0, int j0, int nj, int kbeg,
+                                   int kend, double2 (&acc)[4][4], double2 (*As)[TI], double2 (*Bs)[TI]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  __shared__ double2 As[TK][TI];
-  __shared__ double2 Bs[TK][TI];
-  double2 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
-  // T = sum_k R[i rows, k] X[k, j cols] over k in [i0 + TI, j0 + nj)
-  const int kend = j0 + nj;
-  for (int k0 = i0 + TI; k0 < kend; k0 += TK) {
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
     for (int e = tid; e < TK * TI; e += 256) {
       const int kk = e / TI, q = e % TI;
       const int k = k0 + kk;
       As[kk][q] = (k < kend) ? r.a[(size_t)k * r.lda + i0 + q] : cz(0.0, 0.0);
-      Bs[kk][q] = (k < kend && q < nj) ? x.a[(size_t)(j0 + q) * x.lda + k] : cz(0.0, 0.0);
+      const int kb = e % TK, qb = e / TK;
+      const int k2 = k0 + kb;
+      Bs[kb][qb] = (k2 < kend && qb < nj) ? x.a[(size_t)(j0 + qb) * x.lda + k2] : cz(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll 4
@@ -445,19 +434,19 @@ __global__ __launch_bounds__(256) void trinv_off_kernel(const MatDesc *__restric
     }
     __syncthreads();
   }
-  // X_ij = -X_ii T: T through LDS, X_ii in chunks of TK columns
-  __shared__ double2 Ts[TI][TI + 1];   // [row][column]
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) Ts[ty + 16 * a][tx + 16 * b] = acc[a][b];
-  __syncthreads();
+}
+
+// X_ij = -X_ii T with T in Ts ([row][column], complete): X_ii in chunks of
+// TK columns through As
+__device__ inline void trinv_finish(const MatDesc &x, int i0, int j0, int nj, double2 (*Ts)[TI + 1],
+                                    double2 (*As)[TI]) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double2 out[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) out[a][b] = cz(0.0, 0.0);
-  for (int k0 = 0; k0 < ni; k0 += TK) {
+  for (int k0 = 0; k0 < TI; k0 += TK) {
     for (int e = tid; e < TK * TI; e += 256) {
       const int kk = e / TI, q = e % TI;
       As[kk][q] = x.a[(size_t)(i0 + k0 + kk) * x.lda + i0 + q];   // X_ii[q][k0 + kk]
@@ -484,6 +473,101 @@ __global__ __launch_bounds__(256) void trinv_off_kernel(const MatDesc *__restric
       const int col = tx + 16 * b;
       if (col < nj) x.a[(size_t)(j0 + col) * x.lda + i0 + ty + 16 * a] = cz(-out[a][b].x, -out[a][b].y);
     }
+}
+
+// blocks (i, i + d) of every matrix, the whole sum in one workgroup (i, matrix)
+__global__ __launch_bounds__(256) void trinv_off_kernel(const MatDesc *__restrict__ rd,
+                                                        const MatDesc *__restrict__ xd, int d) {
+  const MatDesc r = rd[blockIdx.y], x = xd[blockIdx.y];
+  const int n = x.n;
+  const int i0 = blockIdx.x * TI, j0 = (blockIdx.x + d) * TI;
+  if (j0 >= n) return;
+  const int nj = min(TI, n - j0);   // row block i is whole (it precedes j)
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ double2 As[TK][TI];
+  __shared__ double2 Bs[TK][TI];
+  __shared__ double2 Ts[TI][TI + 1];
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
+  trinv_accum(r, x, i0, j0, nj, i0 + TI, j0 + nj, acc, As, Bs);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Ts[ty + 16 * a][tx + 16 * b] = acc[a][b];
+  __syncthreads();
+  trinv_finish(x, i0, j0, nj, Ts, As);
+}
+
+// Far from the diagonal the sum over k is split: workgroup (chunk, i,
+// matrix) sums KSPL block columns of it into its slot of P, then
+// trinv_fin_kernel adds the slots and multiplies by -X_ii.  P slot of
+// (matrix, i, chunk): ((mat (nblk - d) + i) nch + chunk) TI^2.
+constexpr int KSPL = 4;
+__global__ __launch_bounds__(256) void trinv_part_kernel(const MatDesc *__restrict__ rd,
+                                                         const MatDesc *__restrict__ xd, int d, int nblk,
+                                                         int nch, double2 *__restrict__ P) {
+  const MatDesc r = rd[blockIdx.z], x = xd[blockIdx.z];
+  const int n = x.n;
+  const int i = blockIdx.y, i0 = i * TI, j0 = (i + d) * TI;
+  if (j0 >= n) return;
+  const int nj = min(TI, n - j0);
+  const int kbeg = i0 + TI + blockIdx.x * KSPL * TI, kend = min(kbeg + KSPL * TI, j0 + nj);
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ double2 As[TK][TI];
+  __shared__ double2 Bs[TK][TI];
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cz(0.0, 0.0);
+  trinv_accum(r, x, i0, j0, nj, kbeg, kend, acc, As, Bs);   // kbeg < kend: chunks cover d blocks
+  double2 *slot = P + (((size_t)blockIdx.z * (nblk - d) + i) * nch + blockIdx.x) * TI * TI;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) slot[(size_t)(ty + 16 * a) * TI + tx + 16 * b] = acc[a][b];
+}
+
+__global__ __launch_bounds__(256) void trinv_fin_kernel(const MatDesc *__restrict__ xd, int d, int nblk, int nch,
+                                                        const double2 *__restrict__ P) {
+  const MatDesc x = xd[blockIdx.y];
+  const int n = x.n;
+  const int i = blockIdx.x, i0 = i * TI, j0 = (i + d) * TI;
+  if (j0 >= n) return;
+  const int nj = min(TI, n - j0);
+  __shared__ double2 As[TK][TI];
+  __shared__ double2 Ts[TI][TI + 1];
+  const double2 *slots = P + ((size_t)blockIdx.y * (nblk - d) + i) * nch * TI * TI;
+  for (int e = threadIdx.x; e < TI * TI; e += 256) {
+    double2 t = cz(0.0, 0.0);
+    for (int c = 0; c < nch; ++c) t = cadd(t, slots[(size_t)c * TI * TI + e]);
+    Ts[e / TI][e % TI] = t;
+  }
+  __syncthreads();
+  trinv_finish(x, i0, j0, nj, Ts, As);
+}
+
+// The blocks off the diagonal of X = R^{-1} (diagonal blocks done), one
+// block distance d after the other: up to KSPL blocks from the diagonal one
+// workgroup a block, farther with the sum split over KSPL-block chunks.
+void trinv_offdiag(const MatDesc *rd, const MatDesc *xd, int W, int nblk, hipStream_t s) {
+  size_t pslots = 0;
+  for (int d = KSPL + 1; d < nblk; ++d) pslots = std::max(pslots, (size_t)(nblk - d) * cdiv(d, KSPL));
+  DevBuf P(pslots * W * TI * TI * sizeof(double2));
+  for (int d = 1; d < nblk; ++d) {
+    if (d <= KSPL) {
+      hipLaunchKernelGGL(trinv_off_kernel, dim3(nblk - d, W), dim3(256), 0, s, rd, xd, d);
+    } else {
+      const int nch = cdiv(d, KSPL);
+      hipLaunchKernelGGL(trinv_part_kernel, dim3(nch, nblk - d, W), dim3(256), 0, s, rd, xd, d, nblk, nch,
+                         P.as<double2>());
+      hipLaunchKernelGGL(trinv_fin_kernel, dim3(nblk - d, W), dim3(256), 0, s, xd, d, nblk, nch, P.as<double2>());
+    }
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 // out[w][j] = (sum_{i<=j} |R_ij|^2, sum_{i<=j} |X_ij|^2): one wave per column
@@ -626,9 +710,8 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
   launch_zero(xa.as<double2>(), (long)(tx / sizeof(double2)), s);
   const int nblk = cdiv(n2max, TI);
   hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk, W), dim3(TI), 0, s, g.d_qc.as<MatDesc>(), dx.as<MatDesc>());
-  for (int d = 1; d < nblk; ++d)
-    hipLaunchKernelGGL(trinv_off_kernel, dim3(nblk - d, W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
-                       dx.as<MatDesc>(), d);
+  trinv_offdiag(g.d_qc.as<MatDesc>(), dx.as<MatDesc>(), W, nblk, s);
+
   DevBuf nrm((size_t)W * n2max * sizeof(double2));
   hipLaunchKernelGGL(trinv_norm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_qc.as<MatDesc>(),
                      dx.as<MatDesc>(), nrm.as<double2>(), n2max);
@@ -971,9 +1054,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     launch_zero(xa.as<double2>(), (long)(tx / sizeof(double2)), s);
     const int nblk = cdiv(rmax, TI);
     hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk, W), dim3(TI), 0, s, g.d_lq.as<MatDesc>(), dx.as<MatDesc>());
-    for (int d = 1; d < nblk; ++d)
-      hipLaunchKernelGGL(trinv_off_kernel, dim3(nblk - d, W), dim3(256), 0, s, g.d_lq.as<MatDesc>(),
-                         dx.as<MatDesc>(), d);
+    trinv_offdiag(g.d_lq.as<MatDesc>(), dx.as<MatDesc>(), W, nblk, s);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));   // hx goes out of scope
   } else {
