@@ -312,6 +312,20 @@ __global__ __launch_bounds__(256) void qrcp_update_kernel(const MatDesc *__restr
   if (lane == 0) norms[(size_t)blockIdx.y * ld + c] = sqrt(s);
 }
 
+}  // namespace
+
+// One step of the column-pivoted QR above on a batch (the pivot and its
+// reflector, then the update of the columns after it with their norms).
+void launch_qrcp_step(const MatDesc *descs, int W, int nmax, int k, double *norms, int *piv, int ld,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(qrcp_pivot_kernel, dim3(W), dim3(PK), 0, s, descs, k, norms, piv, ld);
+  if (k + 1 < nmax)
+    hipLaunchKernelGGL(qrcp_update_kernel, dim3(cdiv(nmax - k - 1, 4), W), dim3(256), 0, s, descs, k, norms, ld);
+  HIP_CHECK(hipGetLastError());
+}
+
+namespace {
+
 // Compact-WY T factor of every 32-column panel of reflectors (forward,
 // columnwise): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V^H v_i.
 __global__ __launch_bounds__(256) void build_t_kernel(const MatDesc *__restrict__ descs) {
@@ -922,15 +936,22 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     DevBuf qn((size_t)W * nmax * sizeof(double));
     hipLaunchKernelGGL(colnorm_kernel, dim3(cdiv(n2max, 4), W), dim3(256), 0, s, g.d_rq.as<MatDesc>(),
                        qn.as<double>(), nmax);
-    // Blocked (panels of 32, qrcp.hip) for triangles of 1024 columns and
-    // more, where streaming the trailing block dominates (the large
-    // periodizer: 33 -> 12 s for 8 triangles of 10805 columns); below, the
-    // column-at-a-time form (every step updates the whole trailing block and
-    // recomputes the norms exactly), which the batch's triangles of up to
-    // 600 columns run as fast.  MFS_QRCP=blocked or unblocked decides.
+    // The pivots of each 32-column block chosen on a Gaussian sketch
+    // (qrcp_sketch.hip): A is read once per block, not per column (the
+    // large periodizer's 8 triangles of 10805 columns: 7.3 -> 3.0 s per
+    // incidence; the 256-obstacle batch's triangles: truncation 10.3 ->
+    // 8.8 s).  Small batches of narrow triangles (the k = 10 body's 33 of
+    // 200 columns: 2.3 ms slower sketched) take the column-at-a-time form,
+    // whose steps are short launches there.  MFS_QRCP=sketched, blocked
+    // (the deterministic panel form: panels of 32, updates deferred, norms
+    // downdated, qrcp.hip) or unblocked (every step updating the whole
+    // trailing block) decides.
     const char *qe = std::getenv("MFS_QRCP");
-    const bool blocked = qe ? std::string(qe) == "blocked" : n2max >= 1024;
-    if (!blocked) {
+    const bool big = n2max >= 256 || (size_t)W * n2max * n2max >= ((size_t)1 << 24);
+    const std::string form = qe ? std::string(qe) : (big ? "sketched" : "unblocked");
+    if (form == "sketched") {
+      qrcp_sketched(g.d_rq.as<MatDesc>(), g.h_rq, g.piv.as<int>(), nmax, s);
+    } else if (form != "blocked") {
       for (int k = 0; k < n2max; ++k) {
         hipLaunchKernelGGL(qrcp_pivot_kernel, dim3(W), dim3(PK), 0, s, g.d_rq.as<MatDesc>(), k, qn.as<double>(),
                            g.piv.as<int>(), nmax);

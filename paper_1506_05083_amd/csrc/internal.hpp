@@ -130,6 +130,23 @@ JacStats jac_run(const MatDesc *descs, const std::vector<MatDesc> &h, int init_m
 // panels of nb = 16, 32 or 64 columns (each matrix's T holds cdiv(n, nb)
 // nb x nb factors)
 void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s, int nb = kQRNB);
+// Column-pivoted QR steps and forms (gpinv.hip, qrcp.hip, qrcp_sketch.hip):
+// the triangles of descs in place (R above the diagonal, reflectors below,
+// tau), piv[w][i] the original column at position i (identity on entry).
+void launch_qrcp_step(const MatDesc *descs, int W, int nmax, int k, double *norms, int *piv, int ld,
+                      hipStream_t s);
+void qrcp_sketched(const MatDesc *descs, const std::vector<MatDesc> &h, int *piv, int ld, hipStream_t s);
+// The same QR (panels of 32) one panel at a time: panel(K0) factors columns
+// [K0, K0 + 32) of every matrix and updates the columns after them.
+struct QRPanels32 {
+  struct Impl;
+  Impl *impl;
+  QRPanels32(const MatDesc *descs, const std::vector<MatDesc> &h);
+  ~QRPanels32();
+  QRPanels32(const QRPanels32 &) = delete;
+  QRPanels32 &operator=(const QRPanels32 &) = delete;
+  void panel(int K0, hipStream_t s);
+};
 // the panel width for a batch like h: measured once per size class and GPU
 // model (see qr.hip), or MFS_QR_NB
 int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s);

@@ -795,28 +795,32 @@ struct PanelWork {
 // matrix keeps and whose trailing update is one pass over the matrix)
 // factored as NB / 16 inner panels of 16 columns, each applied only to the
 // rest of its NB-column panel (its T in a scratch buffer).  NB = 16 is the
-// plain one-level form.
+// plain one-level form.  One panel at a time (panel(K0)), so that a caller
+// may act between panels (the sketched pivoted QR moves columns).
 template <int NB>
-void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
-  constexpr int NI = PanelWork::NI;
+struct BlockedQR {
+  static constexpr int NI = PanelWork::NI;
   static_assert(NB % NI == 0, "outer panels are whole inner panels");
-  int nmax = 0, mmax = 0;
-  for (const auto &d : h) {
-    nmax = std::max(nmax, d.n);
-    mmax = std::max(mmax, d.m);
-  }
-  const int nmat = (int)h.size();
-  if (nmax == 0 || nmat == 0) return;
+  const MatDesc *descs = nullptr;
+  int nmat = 0, nmax = 0, mmax = 0;
   PanelWork pw;
-  pw.size(nmat, mmax);
   ApplyWork w, wi;
-  w.size(nmat, mmax, nmax, NB);
   DevBuf tx;
-  if (NB > NI) {
-    wi.size(nmat, mmax, NB - NI, NI);
-    tx.alloc((size_t)nmat * NI * NI * sizeof(double2));
+  BlockedQR(const MatDesc *d, const std::vector<MatDesc> &h) : descs(d), nmat((int)h.size()) {
+    for (const auto &m : h) {
+      nmax = std::max(nmax, m.n);
+      mmax = std::max(mmax, m.m);
+    }
+    if (nmax == 0 || nmat == 0) return;
+    pw.size(nmat, mmax);
+    w.size(nmat, mmax, nmax, NB);
+    if (NB > NI) {
+      wi.size(nmat, mmax, NB - NI, NI);
+      tx.alloc((size_t)nmat * NI * NI * sizeof(double2));
+    }
   }
-  for (int K0 = 0; K0 < nmax; K0 += NB) {
+  // the panel of columns [K0, K0 + NB) and its update of the columns after it
+  void panel(int K0, hipStream_t s) {
     for (int k0 = K0; k0 < std::min(K0 + NB, nmax); k0 += NI) {
       pw.factor(descs, nmat, mmax, nmax, k0, s);
       const int rest = std::min(K0 + NB, nmax) - (k0 + NI);   // inner columns still to update
@@ -825,6 +829,12 @@ void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_
     }
     apply_panel<NB>(descs, nmat, mmax, std::max(0, nmax - K0 - NB), K0, 0, 1, 1, w, true, s);
   }
+};
+
+template <int NB>
+void qr_factor_t(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s) {
+  BlockedQR<NB> q(descs, h);
+  for (int K0 = 0; K0 < q.nmax; K0 += NB) q.panel(K0, s);
 }
 
 template <int NB>
@@ -988,6 +998,16 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
   tune_store(key, best);
   return best;
 }
+
+// One 32-column panel at a time (the panel width of the pivoted QR's T
+// factors), for callers that act between panels.
+struct QRPanels32::Impl {
+  BlockedQR<32> q;
+  Impl(const MatDesc *d, const std::vector<MatDesc> &h) : q(d, h) {}
+};
+QRPanels32::QRPanels32(const MatDesc *descs, const std::vector<MatDesc> &h) : impl(new Impl(descs, h)) {}
+QRPanels32::~QRPanels32() { delete impl; }
+void QRPanels32::panel(int K0, hipStream_t s) { impl->q.panel(K0, s); }
 
 void qr_factor(const MatDesc *descs, const std::vector<MatDesc> &h, hipStream_t s, int nb) {
   switch (nb) {

@@ -176,6 +176,18 @@ def test_large_cod_matches_svd(large, monkeypatch):
         f"eps_flux {a.eps_flux:.2e} / {b.eps_flux:.2e}")
     assert ea < 1e-9 and eb < 1e-9 and eu < 1e-9
     assert a.eps_flux < 1e-9 and b.eps_flux < 1e-9
+    # the same decomposition with the sketch-pivoted QR of the triangle
+    monkeypatch.setenv("MFS_QPINV", "cod")
+    monkeypatch.setenv("MFS_QRCP", "sketched")
+    res_k, tm_k = mfs.solve_incident(ctx, op, L, waves, **kw)
+    k = res_k[0]
+    ka = np.max(np.abs(k.a - b.a)) / np.max(np.abs(b.a))
+    kb = np.max(np.abs(k.b - b.b)) / np.max(np.abs(b.b))
+    ku = np.linalg.norm(k.field - b.field) / np.linalg.norm(b.field)
+    log(f"[large cod sketched] periodizer {tm_k['periodizer'] / 1e3:.1f} s (kept {k.q_rank}); against the SVD: "
+        f"a {ka:.2e} b {kb:.2e} u {ku:.2e}; eps_flux {k.eps_flux:.2e}")
+    assert ka < 1e-9 and kb < 1e-9 and ku < 1e-9
+    assert k.eps_flux < 1e-9
 
 
 def test_large_transmission_one_wave(large):

@@ -347,11 +347,13 @@ def test_qr_panel_widths(mfs, ctx, small_oracle, monkeypatch, nb):
     assert e < 1e-13
 
 
-@pytest.mark.parametrize("form", ["blocked", "unblocked"])
+@pytest.mark.parametrize("form", ["blocked", "unblocked", "sketched"])
 def test_pivoted_qr_forms(mfs, ctx, monkeypatch, form):
-    """Both forms of the column-pivoted QR of the triangles (blocked: panels
-    of 32 with the updates deferred and the norms downdated; unblocked: one
-    column step at a time, norms recomputed), forced on the small periodic
+    """The three forms of the column-pivoted QR of the triangles (blocked:
+    panels of 32 with the updates deferred and the norms downdated;
+    unblocked: one column step at a time, norms recomputed; sketched: the
+    pivots of each 32-column block chosen on a Gaussian sketch, the block
+    factored unpivoted and the rest updated once), forced on the small periodic
     body and on the k = 10 body (its 200-column blocks need 7 panels):
     singular values against LAPACK on the GPU's own blocks, 1e-13 of the
     largest; the same kept ranks either way."""
@@ -370,15 +372,19 @@ def test_pivoted_qr_forms(mfs, ctx, monkeypatch, form):
         assert e < 1e-13
 
 
-def test_cod_operator_fields(mfs, ctx, monkeypatch):
+@pytest.mark.parametrize("qrcp", ["default", "sketched"])
+def test_cod_operator_fields(mfs, ctx, monkeypatch, qrcp):
     """The one-body factorisation with the truncated complete orthogonal
     decomposition (MFS_OPINV=cod: pivoted QR of the triangle, cut at the
     trailing Frobenius norm, inverse of the LQ factor) in place of the Jacobi
     SVD, on rank-deficient bodies (the k = 10 body and two of the batch's):
     the free-space field against the oracle's truncated-SVD solution, 1e-10;
     the coefficients differ (the kept ranks are not the SVD's) but the field
-    the method computes does not."""
+    the method computes does not.  Also with the sketch-pivoted QR, whose
+    pivots are not the deterministic ones."""
     monkeypatch.setenv("MFS_OPINV", "cod")
+    if qrcp != "default":
+        monkeypatch.setenv("MFS_QRCP", qrcp)
     bodies = [W.periodic_k10(1).body] + W.batch_obstacles(2)
     tg = W.fibonacci_sphere(24, 2.0)
     for i, b in enumerate(bodies):
