@@ -45,7 +45,7 @@ template <int NB> struct VhyShape;
 template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0; };
 template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1; };
 template <> struct VhyShape<16> { static constexpr int YT = 64, IB = 1, CB = 1, OCC = 4, DB = 1; };
-constexpr int WT = 64;      // columns per workgroup in W2 and in the update
+constexpr int W2T = 16;     // columns per workgroup in W2 (the slices' sum spread over more workgroups)
 
 // element r of Householder vector i of the panel starting at column k0
 __device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
@@ -585,37 +585,37 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
   if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
-  const int c0 = blockIdx.x * WT;
+  const int c0 = blockIdx.x * W2T;
   if (c0 >= nb_cols) return;
   const int nv = withV ? NB : 0;
   const int nkc = (d.m - k0 + KR - 1) / KR;
   __shared__ double2 Ts[NB][NB + 1];
-  __shared__ double2 Ws[NB][WT + 1];
+  __shared__ double2 Ws[NB][W2T + 1];
   const int tid = threadIdx.x;
   const double2 *T = Tx ? Tx + (size_t)blockIdx.y * NB * NB : d.T + (size_t)(k0 / NB) * NB * NB;
   for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = T[idx];
   const double2 *base = P + (size_t)blockIdx.y * nkcmax * NB * ldp;
   {
-    double2 t[NB * WT / 256];
+    double2 t[NB * W2T / 256];
 #pragma unroll
-    for (int u = 0; u < NB * WT / 256; ++u) t[u] = cz(0.0, 0.0);
+    for (int u = 0; u < NB * W2T / 256; ++u) t[u] = cz(0.0, 0.0);
     for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
-      for (int u = 0; u < NB * WT / 256; ++u) {
-        const int idx = tid + 256 * u, cc = idx % WT, i = idx / WT;
+      for (int u = 0; u < NB * W2T / 256; ++u) {
+        const int idx = tid + 256 * u, cc = idx % W2T, i = idx / W2T;
         t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + i) * ldp + nv + c0 + cc, c0 + cc < nb_cols));
       }
     }
 #pragma unroll
-    for (int u = 0; u < NB * WT / 256; ++u) {
+    for (int u = 0; u < NB * W2T / 256; ++u) {
       const int idx = tid + 256 * u;
-      Ws[idx / WT][idx % WT] = t[u];
+      Ws[idx / W2T][idx % W2T] = t[u];
     }
   }
   __syncthreads();
   double2 *out = W2 + (size_t)blockIdx.y * NB * ldw;
-  for (int idx = tid; idx < NB * WT; idx += 256) {
-    const int cc = idx % WT, i = idx / WT;
+  for (int idx = tid; idx < NB * W2T; idx += 256) {
+    const int cc = idx % W2T, i = idx / W2T;
     const int c = c0 + cc;
     if (c >= nb_cols) continue;
     double2 acc = cz(0.0, 0.0);
@@ -755,7 +755,7 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
     hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
                        w.nkcmax, Tx);
   if (ncols_max > 0) {
-    hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, WT), nmat), dim3(256), 0, s, descs, k0, which,
+    hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, W2T), nmat), dim3(256), 0, s, descs, k0, which,
                        withV, trans, cend, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw, Tx);
     hipLaunchKernelGGL(bqr_update_kernel<NB>,
                        dim3(cdiv(ncols_max, UpdShape::UC), cdiv(std::max(mmax - k0, 1), UpdShape::UR), nmat),
