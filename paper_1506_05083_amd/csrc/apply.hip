@@ -192,6 +192,241 @@ __global__ __launch_bounds__(64 * S2W) void pinv_gemv_kernel(PinvJob j) {
   }
 }
 
+// Column sums of a lane-distributed block: every lane holds v[0..NB) (its
+// row's terms of NB columns); on return lane l holds in v[0] the sum over
+// all 64 lanes of column l % NB.  Plain sums over the lane bits above
+// log2(NB), then a butterfly over the others that halves the values a lane
+// keeps at each stage (63 exchanges for 64 columns instead of 6 a column).
+// The stages are template recursions so that every index is a constant
+// (the array stays in registers).
+template <int O, int NB>
+__device__ inline void plain_stages(double2 (&v)[NB]) {
+  if constexpr (O >= NB) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      v[j].x += __shfl_xor(v[j].x, O, 64);
+      v[j].y += __shfl_xor(v[j].y, O, 64);
+    }
+    plain_stages<O / 2, NB>(v);
+  }
+}
+template <int H, int NB>
+__device__ inline void butterfly_stages(double2 (&v)[NB], int lane) {
+  if constexpr (H >= 1) {
+    const bool hi = (lane & H) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double2 send = hi ? v[j] : v[j + H], keep = hi ? v[j + H] : v[j];
+      v[j] = cz(keep.x + __shfl_xor(send.x, H, 64), keep.y + __shfl_xor(send.y, H, 64));
+    }
+    butterfly_stages<H / 2, NB>(v, lane);
+  }
+}
+template <int NB>
+__device__ inline void lane_column_sums(double2 (&v)[NB], int lane) {
+  plain_stages<32, NB>(v);
+  butterfly_stages<NB / 2, NB>(v, lane);
+}
+
+constexpr int QHR = 128;   // rows a workgroup in the reflector apply
+
+// V[r][k0 .. k0 + N) of the panel at k0 (unit diagonal, zeros above it and
+// past the last column): N loads issued together, masked ones reading the
+// matrix's first element
+template <int N>
+__device__ inline void vpanel(const MatDesc &d, int r, bool live, int k0, double2 (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int c = k0 + i;
+    v[i] = ld_or0(d.a, (size_t)(c < d.n ? c : 0) * d.lda + (live ? r : 0), live && c < d.n && r > c);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (live && r == k0 + i && k0 + i < d.n) v[i] = cz(1.0, 0.0);
+}
+
+// Q^H x for matrices kept as their Householder QR (reflectors below the
+// diagonal, the compact-WY T of every NB-column panel): Q^H = H_n^H ... H_1^H
+// applied panel after panel, x <- x - V T^H (V^H x).  Launch p (workgroup:
+// QHR rows of one matrix) finishes panel p - 1 (the slices' partial sums of
+// V^H x added, times T^H, subtracted from its rows) and forms panel p's
+// partial sums over its rows; the launch after the last panel writes
+// y = (Q^H x)[0, n) to the apply's work vector.  The slices' partials are
+// double-buffered by panel parity: [2][mat][slice][NB].
+template <int NB>
+__global__ __launch_bounds__(QHR) void qh_panel_kernel(const MatDesc *__restrict__ descs, int p, int npan,
+                                                       const double2 *__restrict__ xin, int ldx,
+                                                       double2 *__restrict__ xw, double2 *__restrict__ part,
+                                                       int nslmax, double2 *__restrict__ y, int ldy) {
+  const MatDesc d = descs[blockIdx.y];
+  const int slice = blockIdx.x, r0 = slice * QHR;
+  if (r0 >= d.m) return;
+  const int nsl = (d.m + QHR - 1) / QHR;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = r0 + tid;
+  const bool live = r < d.m;
+  double2 xr = live ? (p == 0 ? xin : xw)[(size_t)blockIdx.y * ldx + r] : cz(0.0, 0.0);
+  __shared__ double2 ws[NB], tv[NB];
+  __shared__ double2 red[QHR / 64][NB];
+  __shared__ double2 sred[QHR];
+  __shared__ double2 Ts[NB][NB + 1];
+  // V[r][k0 + i .. + 16) of the panel at k0: 16 loads issued together (masked
+  // ones read the matrix's first element), then the unit diagonal and zeros
+  auto vload = [&](int k0, int i0, double2 (&v)[16]) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int c = k0 + i0 + i;
+      v[i] = ld_or0(d.a, (size_t)(c < d.n ? c : 0) * d.lda + (live ? r : 0), live && c < d.n && r > c);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (live && r == k0 + i0 + i && k0 + i0 + i < d.n) v[i] = cz(1.0, 0.0);
+  };
+  if constexpr (NB <= 32) {
+    // both panels' reflectors loaded at once, before the partials' sum
+    const int kp = (p - 1) * NB, k0 = p * NB;
+    const bool fin = p > 0 && kp < d.n, par = p < npan && k0 < d.n;
+    double2 vp[NB], vc[NB];
+    if (fin) vpanel<NB>(d, r, live, kp, vp);
+    if (par) vpanel<NB>(d, r, live, k0, vc);
+    if (fin) {
+      const double2 *pin = part + ((size_t)((p - 1) & 1) * gridDim.y + blockIdx.y) * nslmax * NB;
+      constexpr int G = QHR / NB;
+      {
+        const int i = tid % NB, g0 = tid / NB;
+        double2 t = cz(0.0, 0.0);
+#pragma unroll 4
+        for (int sl = g0; sl < nsl; sl += G) t = cadd(t, pin[(size_t)sl * NB + i]);
+        sred[tid] = t;   // [g0][i]
+      }
+      const double2 *T = d.T + (size_t)(kp / NB) * NB * NB;   // column-major, upper
+      for (int e = tid; e < NB * NB; e += QHR) Ts[e / NB][e % NB] = T[e];   // Ts[i][h] = T[h][i]
+      __syncthreads();
+      if (tid < NB) {
+        double2 t = sred[tid];
+#pragma unroll
+        for (int g = 1; g < G; ++g) t = cadd(t, sred[g * NB + tid]);
+        ws[tid] = t;
+      }
+      __syncthreads();
+      if (tid < NB) {
+        double2 t = cz(0.0, 0.0);
+        for (int h = 0; h <= tid; ++h) cfmac(t, Ts[tid][h], ws[h]);   // (T^H w)_i
+        tv[tid] = t;
+      }
+      __syncthreads();
+      if (live && r >= kp) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) xr = csub(xr, cmul(vp[i], tv[i]));
+      }
+    }
+    if (par) {
+      double2 *pout = part + ((size_t)(p & 1) * gridDim.y + blockIdx.y) * nslmax * NB + (size_t)slice * NB;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const double2 v = vc[i];
+        vc[i] = cz(0.0, 0.0);
+        cfmac(vc[i], v, xr);   // conj(V[r][i]) x[r]
+      }
+      lane_column_sums<NB>(vc, lane);
+      if (lane < NB) red[wv][lane] = vc[0];
+      __syncthreads();
+      if (tid < NB) {
+        double2 t = red[0][tid];
+#pragma unroll
+        for (int w = 1; w < QHR / 64; ++w) t = cadd(t, red[w][tid]);
+        pout[tid] = t;
+      }
+    }
+  } else {
+    if (p > 0) {
+      const int kp = (p - 1) * NB;
+      if (kp < d.n) {
+        const double2 *pin = part + ((size_t)((p - 1) & 1) * gridDim.y + blockIdx.y) * nslmax * NB;
+        // the slices' partials summed by every thread (column tid % NB, every
+        // G-th slice, loads in flight together), then across the G groups;
+        // T staged through LDS alongside
+        constexpr int G = QHR / NB;
+        {
+          const int i = tid % NB, g0 = tid / NB;
+          double2 t = cz(0.0, 0.0);
+  #pragma unroll 4
+          for (int sl = g0; sl < nsl; sl += G) t = cadd(t, pin[(size_t)sl * NB + i]);
+          sred[tid] = t;   // [g0][i]
+        }
+        const double2 *T = d.T + (size_t)(kp / NB) * NB * NB;   // column-major, upper
+        for (int e = tid; e < NB * NB; e += QHR) Ts[e / NB][e % NB] = T[e];   // Ts[i][h] = T[h][i]
+        __syncthreads();
+        if (tid < NB) {
+          double2 t = sred[tid];
+  #pragma unroll
+          for (int g = 1; g < G; ++g) t = cadd(t, sred[g * NB + tid]);
+          ws[tid] = t;
+        }
+        __syncthreads();
+        if (tid < NB) {
+          double2 t = cz(0.0, 0.0);
+          for (int h = 0; h <= tid; ++h) cfmac(t, Ts[tid][h], ws[h]);   // (T^H w)_i
+          tv[tid] = t;
+        }
+        __syncthreads();
+        if (live && r >= kp) {
+          for (int i0 = 0; i0 < NB; i0 += 16) {
+            double2 v[16];
+            vload(kp, i0, v);
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) xr = csub(xr, cmul(v[i], tv[i0 + i]));
+          }
+        }
+      }
+    }
+    if (p < npan) {
+      const int k0 = p * NB;
+      double2 *pout = part + ((size_t)(p & 1) * gridDim.y + blockIdx.y) * nslmax * NB + (size_t)slice * NB;
+      if (k0 < d.n) {
+        constexpr int HB = NB < 32 ? NB : 32;   // columns summed together (registers)
+  #pragma unroll
+        for (int h0 = 0; h0 < NB; h0 += HB) {
+          double2 v[HB];
+  #pragma unroll
+          for (int i0 = 0; i0 < HB; i0 += 16) {
+            double2 vv[16];
+            vload(k0, h0 + i0, vv);
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              v[i0 + i] = cz(0.0, 0.0);
+              cfmac(v[i0 + i], vv[i], xr);   // conj(V[r][i]) x[r]
+            }
+          }
+          lane_column_sums<HB>(v, lane);
+          if (lane < HB) red[wv][h0 + lane] = v[0];
+        }
+        __syncthreads();
+        if (tid < NB) {
+          double2 t = red[0][tid];
+  #pragma unroll
+          for (int w = 1; w < QHR / 64; ++w) t = cadd(t, red[w][tid]);
+          pout[tid] = t;
+        }
+      }
+    }
+  }
+  if (live) {
+    if (p < npan) xw[(size_t)blockIdx.y * ldx + r] = xr;
+    else if (r < d.n) y[(size_t)blockIdx.y * ldy + r] = xr;
+  }
+}
+
+template <int NB>
+void qh_apply_t(const MatDesc *descs, int nmat, int mmax, int nmax, const double2 *x, int ldx, double2 *xw,
+                double2 *part, int nslmax, double2 *y, int ldy, hipStream_t s) {
+  const int npan = cdiv(nmax, NB);
+  for (int p = 0; p <= npan; ++p)
+    hipLaunchKernelGGL(qh_panel_kernel<NB>, dim3(cdiv(mmax, QHR), nmat), dim3(QHR), 0, s, descs, p, npan, x, ldx,
+                       xw, part, nslmax, y, ldy);
+  HIP_CHECK(hipGetLastError());
+}
+
 }  // namespace
 
 void launch_pinv_apply(const PinvJob &j, hipStream_t s) {
@@ -206,6 +441,32 @@ void launch_pinv_apply(const PinvJob &j, hipStream_t s) {
   hipLaunchKernelGGL(pinv_stage1, dim3(cdiv(j.maxr, S1I), j.nmat), dim3(256), 0, s, j);
   HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(pinv_stage2, dim3(cdiv(j.maxn, S2R), j.nmat), dim3(256), 0, s, j);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace mfs
+
+namespace mfs {
+
+size_t qh_apply_work(int nmat, int mmax, int ldx) {
+  return ((size_t)nmat * ldx + 2 * (size_t)nmat * cdiv(mmax, QHR) * 64) * sizeof(double2);
+}
+
+void launch_qh_apply(const MatDesc *descs, int nmat, int mmax, int nmax, int nb, const double2 *x, int ldx,
+                     double2 *work, double2 *y, int ldy, hipStream_t s) {
+  double2 *xw = work, *part = work + (size_t)nmat * ldx;
+  const int nslmax = cdiv(mmax, QHR);
+  switch (nb) {
+    case 16: qh_apply_t<16>(descs, nmat, mmax, nmax, x, ldx, xw, part, nslmax, y, ldy, s); break;
+    case 32: qh_apply_t<32>(descs, nmat, mmax, nmax, x, ldx, xw, part, nslmax, y, ldy, s); break;
+    case 64: qh_apply_t<64>(descs, nmat, mmax, nmax, x, ldx, xw, part, nslmax, y, ldy, s); break;
+    default: MFS_THROW(MFS_EINVAL, "reflector apply: panel width must be 16, 32 or 64");
+  }
+}
+
+void launch_pinv_apply_w(const PinvJob &j, hipStream_t s) {
+  MFS_REQUIRE(j.mode == 1, "W-only apply is the one-matrix-per-rhs form");
+  hipLaunchKernelGGL(pinv_gemv_kernel, dim3(cdiv(j.maxn, 64), j.nmat), dim3(64 * S2W), 0, s, j);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -700,7 +700,7 @@ static bool use_cod(bool equilibrate, bool pivot, int n2max) {
 // W = D P R^{-1} are formed and true is returned.  Otherwise (some matrix of
 // the batch may need truncating) nothing is kept and false is returned.
 static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, double rel_cutoff,
-                        const double *cscl, const std::vector<MatDesc> &in, hipStream_t s) {
+                        const double *cscl, const std::vector<MatDesc> &in, hipStream_t s, bool keep_reflectors) {
   const int W = (int)n2.size();
   const int n2max = *std::max_element(n2.begin(), n2.end());
   int *flags = g.small.as<int>();
@@ -752,9 +752,12 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
   g.jacobi_launches = 0;
   g.jacobi_unconverged = 0;
   HIP_CHECK(hipMemcpyAsync(flags + W, n2.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(identity_u_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_qc.as<MatDesc>());
-  HIP_CHECK(hipGetLastError());
-  qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s, true, g.qr_nb);
+  g.reflect = keep_reflectors;
+  if (!keep_reflectors) {
+    hipLaunchKernelGGL(identity_u_kernel, dim3(n2max, W), dim3(256), 0, s, g.d_qc.as<MatDesc>());
+    HIP_CHECK(hipGetLastError());
+    qr_form_u(g.d_qc.as<MatDesc>(), g.h_qc, n2max, s, true, g.qr_nb);
+  }
   g.h_fin.resize(W);
   std::vector<size_t> of(W);
   {
@@ -768,7 +771,7 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
   for (int w = 0; w < W; ++w) {
     MatDesc d{};
     d.m = in[w].m; d.n = in[w].n; d.lda = g.h_qc[w].lda;
-    d.u = g.h_qc[w].u;
+    d.u = keep_reflectors ? nullptr : g.h_qc[w].u;
     d.w = arena_at(g.fin_w, of[w]);
     d.ldg = round_up(in[w].n, 16);
     d.rank = flags + W + w;
@@ -783,11 +786,12 @@ static bool direct_pinv(GradedPinv &g, const std::vector<int> &n2, int nmax, dou
 }
 
 void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
-                 hipStream_t s, bool equilibrate) {
+                 hipStream_t s, bool equilibrate, bool keep_reflectors) {
   const int W = (int)in.size();
   int nmax = 0, mmax = 0;
   for (auto &d : in) { nmax = std::max(nmax, d.n); mmax = std::max(mmax, d.m); }
   g.direct = false;
+  g.reflect = false;
   g.jacobi_unconverged = 0;
   upload_descs(g.d_in, in, s);
   // 1. column norms, selection and ordering
@@ -904,7 +908,7 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
     HIP_CHECK(hipMemcpyAsync(g.piv.p, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));
   }
-  if (equilibrate && direct_pinv(g, n2, nmax, rel_cutoff, cscl, in, s)) return;
+  if (equilibrate && direct_pinv(g, n2, nmax, rel_cutoff, cscl, in, s, keep_reflectors)) return;
   if (pivot) {
     g.h_rq.resize(W);
     {

@@ -20,6 +20,7 @@ struct GradedPinv {
   hipEvent_t ev_qr_done = nullptr;   // if set, recorded after the unpivoted blocked QR
   bool pivoted = false;              // the triangle went through the pivoted QR
   bool direct = false;               // every singular value kept: U = Q_1, W = D P R^{-1} (no SVD)
+  bool reflect = false;              // direct, with U = Q_1 applied from the QR's reflectors (d_qc) instead of formed
   bool cod = false;                  // truncated complete orthogonal decomposition in place of the SVD
   int qr_nb = kQRNB;                 // panel width of the QR of the ordered columns
   double jacobi_ms = 0.0;            // Jacobi sweeps: time, launches, algorithmic bytes and flops
@@ -38,10 +39,16 @@ struct GradedPinv {
   // free the factorisation's work, keeping what the apply reads (U in
   // qc_fac, W in fin_w, the kept ranks in small)
   void release_work() {
-    d_in.release(); d_qc.release(); d_rq.release(); d_rqu.release(); d_lq.release();
+    d_in.release(); d_rq.release(); d_rqu.release(); d_lq.release();
     perm.release(); piv.release(); colscale.release();
-    qc_a.release(); rq_a.release(); rq_fac.release(); lq_a.release(); lq_fac.release();
+    rq_a.release(); rq_fac.release(); lq_a.release(); lq_fac.release();
+    if (!reflect) {
+      d_qc.release();
+      qc_a.release();
+    }
   }
+  // the QR'd matrices whose reflectors stand for U (reflect)
+  const MatDesc *qr_descs() const { return d_qc.as<MatDesc>(); }
   // singular values of every matrix, [W][ldo] (descending, zero past n);
   // before release_work.  Blocking.
   void singular_values(int ldo, std::vector<double> &out, hipStream_t s) const;
@@ -54,8 +61,10 @@ struct GradedPinv {
 // equilibrate: factor A D instead of A, D scaling every kept column to unit
 // norm, so that the relative cutoff judges linear dependence rather than
 // column size; W then holds D V S^+ and the pseudoinverse is D (A D)^+.
+// keep_reflectors: when every singular value is kept (the direct form), U =
+// Q_1 is not formed; the QR's reflectors stay for launch_qh_apply (g.reflect).
 void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutoff, int pivot_min_cols,
-                 hipStream_t s, bool equilibrate = false);
+                 hipStream_t s, bool equilibrate = false, bool keep_reflectors = false);
 
 // Widest periodizer triangle factored without the pivoted QR (measured:
 // 1257 columns at k = 10 gain nothing from it, 9701 at k = 2 pi 13 gain 30%).

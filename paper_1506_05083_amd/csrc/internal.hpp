@@ -163,6 +163,14 @@ struct PinvJob {
   double2 *ywork;   // [nmat][maxcols][maxr]
 };
 void launch_pinv_apply(const PinvJob &j, hipStream_t s);
+// mode 1, second stage only: out = W y with y already in j.ywork
+void launch_pinv_apply_w(const PinvJob &j, hipStream_t s);
+// y[mat][0, n) = (Q^H x)[0, n) for matrices kept as their Householder QR
+// (descs: reflectors below the diagonal, T of every nb-column panel), x
+// [mat][ldx]; work: qh_apply_work bytes
+size_t qh_apply_work(int nmat, int mmax, int ldx);
+void launch_qh_apply(const MatDesc *descs, int nmat, int mmax, int nmax, int nb, const double2 *x, int ldx,
+                     double2 *work, double2 *y, int ldy, hipStream_t s);
 
 // ------------------------------------------------------- neighbour sums
 // Targets are grouped; every group shares an image list and per-rhs weights.

@@ -513,6 +513,7 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
     double2 t[NB * NB / 256];
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) t[u] = cz(0.0, 0.0);
+#pragma unroll 4
     for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
       for (int u = 0; u < NB * NB / 256; ++u) {
@@ -599,6 +600,7 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
     double2 t[NB * W2T / 256];
 #pragma unroll
     for (int u = 0; u < NB * W2T / 256; ++u) t[u] = cz(0.0, 0.0);
+#pragma unroll 6
     for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
       for (int u = 0; u < NB * W2T / 256; ++u) {

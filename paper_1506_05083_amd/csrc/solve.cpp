@@ -90,6 +90,14 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
     hipStream_t s = op->stream;
     const int W = nwaves;
     Solver S(op, b, *lat, W, maxit, s);
+    // MFS_QPINV_REFLECT=1: a full-rank Q is applied from its QR's
+    // reflectors, panel by panel, instead of forming U = Q_1 (measured on the
+    // k = 10 workload: 31 us a panel launch, 41 launches an apply at 32-column
+    // panels, more than forming U once and streaming it: not the default)
+    {
+      const char *e = std::getenv("MFS_QPINV_REFLECT");
+      S.qreflect = e && std::string(e) == "1";
+    }
     // host per-wave data
     S.al.resize(W); S.be.resize(W); S.kv.resize(3 * W); S.orders.resize(W);
     bool cap_ok = true;

@@ -44,6 +44,8 @@ struct Solver {
   std::vector<MatDesc> h_qdescs;
   std::vector<int> qrank;
   GradedPinv gp;
+  bool qreflect = false;            // let a full-rank Q keep its QR's reflectors instead of forming U = Q_1
+  DevBuf QHW;                       // work of the reflector apply
   const MatDesc *qdesc = nullptr;   // Q^+ factors of every wave (default: gp's)
   size_t near_limit = SIZE_MAX;     // bound on the stored near field besides the operator's
   // plans
@@ -137,7 +139,8 @@ struct Solver {
     // Q's columns equilibrated: the harmonics of high degree are smaller than
     // the low ones by far more than the cutoff on the walls, and would
     // otherwise be dropped whatever their use
-    graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s, true);
+    graded_pinv(gp, h_qdescs, rel_cutoff, kQPivotMinCols, s, true, qreflect);
+    if (gp.reflect) QHW.alloc(qh_apply_work(W, rows, rows));
     qrank = gp.kept;
     progress("periodizer: factored (%s; Jacobi %.0f ms, %d launches)",
              gp.direct ? "full rank, no SVD"
@@ -229,6 +232,23 @@ struct Solver {
   }
 
   const MatDesc *qpinv_descs() const { return qdesc ? qdesc : gp.apply_descs(); }
+
+  // XI = Q^+ CY for every wave: U^H then W, or, when the factorisation kept
+  // the QR's reflectors in place of U = Q_1 (the direct form), Q^H from the
+  // reflectors panel by panel, then W
+  void apply_qpinv() {
+    PinvJob j{};
+    j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
+    j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
+    j.descs = qpinv_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
+    if (!qdesc && gp.reflect) {
+      launch_qh_apply(gp.qr_descs(), W, rows, NQmax, gp.qr_nb, CY.as<double2>(), rows, QHW.as<double2>(),
+                      YW.as<double2>(), NQmax, s);
+      launch_pinv_apply_w(j, s);
+    } else {
+      launch_pinv_apply(j, s);
+    }
+  }
 
   // phase weights of the neighbour sums from al, be (after a wave changes)
   void upload_weights() {
@@ -404,11 +424,7 @@ struct Solver {
     launch_point_strengths(W, P, P, N, cmodes, SIG.as<double2>(), s, Nc);
     nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
-    PinvJob j{};
-    j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
-    j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
-    j.descs = qpinv_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
-    launch_pinv_apply(j, s);
+    apply_qpinv();
   }
 
   // out = (I + A_else A_0^+ - B Q^+ C A_0^+) x
@@ -434,11 +450,7 @@ struct Solver {
     // the wall rows reuse SIG computed above
     if (!fused) nsum(pwalls, wwalls, WR.as<double2>());
     launch_combine_walls(W, lat.M1 * lat.M1, WR.as<double2>(), CY.as<double2>(), s);
-    PinvJob j{};
-    j.mode = 1; j.nmat = W; j.P = P; j.nrhs = 1; j.ldx = rows; j.ldo = NQmax; j.maxcols = 1;
-    j.maxr = NQmax; j.maxm = rows; j.maxn = NQmax;
-    j.descs = qpinv_descs(); j.x = CY.as<double2>(); j.out = XI.as<double2>(); j.ywork = YW.as<double2>();
-    launch_pinv_apply(j, s);
+    apply_qpinv();
     if (!b.trans()) {
       launch_bapply(W, P, M, lat.p, Bvals.as<double2>(), XI.as<double2>(), NQmax, out, s, M);
     } else {

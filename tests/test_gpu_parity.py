@@ -372,6 +372,30 @@ def test_pivoted_qr_forms(mfs, ctx, monkeypatch, form):
         assert e < 1e-13
 
 
+def test_qpinv_reflectors_match_formed_u(mfs, ctx, monkeypatch):
+    """The full-rank periodizer's Q^+ applied from its QR's reflectors (panel
+    by panel, MFS_QPINV_REFLECT=1) against the default with U = Q_1 formed,
+    k = 10 workload, two incidences: Bragg amplitudes and fields to 1e-12."""
+    pr = W.periodic_k10(2)
+    b = pr.body
+    op = make_op(mfs, ctx, b)
+    op.factor_modes(1e-10)
+    L = _lat(mfs, pr.lattice)
+    waves = [(w.theta, w.phi) for w in pr.waves]
+    kw = dict(tol=1e-12, maxit=pr.maxit, targets=pr.targets, q_field=pr.q_field)
+    monkeypatch.setenv("MFS_QPINV_REFLECT", "1")
+    res_r = mfs.solve_incident(ctx, op, L, waves, **kw)
+    monkeypatch.delenv("MFS_QPINV_REFLECT", raising=False)
+    res_u = mfs.solve_incident(ctx, op, L, waves, **kw)
+    for a, c in zip(res_r, res_u):
+        assert a.q_rank == a.nq_cols == c.q_rank   # the direct (full-rank) form
+        ea = np.max(np.abs(a.a - c.a)) / np.max(np.abs(c.a))
+        eb = np.max(np.abs(a.b - c.b)) / np.max(np.abs(c.b))
+        eu = np.linalg.norm(a.field - c.field) / np.linalg.norm(c.field)
+        log(f"[qpinv reflectors] a {ea:.2e} b {eb:.2e} u {eu:.2e}, eps_flux {a.eps_flux:.2e} / {c.eps_flux:.2e}")
+        assert ea < 1e-12 and eb < 1e-12 and eu < 1e-12
+
+
 @pytest.mark.parametrize("qrcp", ["default", "sketched"])
 def test_cod_operator_fields(mfs, ctx, monkeypatch, qrcp):
     """The one-body factorisation with the truncated complete orthogonal
