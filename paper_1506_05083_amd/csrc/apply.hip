@@ -192,44 +192,6 @@ __global__ __launch_bounds__(64 * S2W) void pinv_gemv_kernel(PinvJob j) {
   }
 }
 
-// Column sums of a lane-distributed block: every lane holds v[0..NB) (its
-// row's terms of NB columns); on return lane l holds in v[0] the sum over
-// all 64 lanes of column l % NB.  Plain sums over the lane bits above
-// log2(NB), then a butterfly over the others that halves the values a lane
-// keeps at each stage (63 exchanges for 64 columns instead of 6 a column).
-// The stages are template recursions so that every index is a constant
-// (the array stays in registers).
-template <int O, int NB>
-__device__ inline void plain_stages(double2 (&v)[NB]) {
-  if constexpr (O >= NB) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      v[j].x += __shfl_xor(v[j].x, O, 64);
-      v[j].y += __shfl_xor(v[j].y, O, 64);
-    }
-    plain_stages<O / 2, NB>(v);
-  }
-}
-template <int H, int NB>
-__device__ inline void butterfly_stages(double2 (&v)[NB], int lane) {
-  if constexpr (H >= 1) {
-    const bool hi = (lane & H) != 0;
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-      const double2 send = hi ? v[j] : v[j + H], keep = hi ? v[j + H] : v[j];
-      v[j] = cz(keep.x + __shfl_xor(send.x, H, 64), keep.y + __shfl_xor(send.y, H, 64));
-    }
-    butterfly_stages<H / 2, NB>(v, lane);
-  }
-}
-template <int NB>
-__device__ inline void lane_column_sums(double2 (&v)[NB], int lane) {
-  plain_stages<32, NB>(v);
-  butterfly_stages<NB / 2, NB>(v, lane);
-}
-
-constexpr int QHR = 128;   // rows a workgroup in the reflector apply
-
 // V[r][k0 .. k0 + N) of the panel at k0 (unit diagonal, zeros above it and
 // past the last column): N loads issued together, masked ones reading the
 // matrix's first element
