@@ -867,11 +867,21 @@ void qr_form_u_t(const MatDesc *descs, const std::vector<MatDesc> &h, int maxran
 // update over the matrix (one per panel): which wins depends on the
 // matrices' shape and the GPU.  The first batch of a size class (the number
 // of rows and of columns, each rounded to a half octave) on a GPU model
-// times the QR of up to 8 of its matrices with every width and keeps the
+// times the QR of up to 8 of its matrices with every width, followed by the
+// formation of U from the identity that every caller does next (64-wide
+// reflectors: a narrower QR leaves their T to be rebuilt), and keeps the
 // fastest; later batches of that class reuse it.  MFS_QR_NB = 16, 32 or 64
 // fixes the width; MFS_QR_TUNE_FILE names a file that keeps the choices
 // across processes (one "key width" line per class).
 namespace {
+
+// U = the first n columns of the identity (the tuner's U formation)
+__global__ void tune_identity_kernel(const MatDesc *__restrict__ descs) {
+  const MatDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.n) return;
+  for (int r = threadIdx.x; r < d.m; r += blockDim.x) d.u[(size_t)c * d.ldu + r] = cz(r == c ? 1.0 : 0.0, 0.0);
+}
 
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
@@ -916,6 +926,9 @@ void tune_store(const std::string &key, int nb) {   // g_tune_mu held
 
 }  // namespace
 
+void qr_form_u(const MatDesc *descs, const std::vector<MatDesc> &h, int maxrank, hipStream_t s,
+               bool from_identity, int nb);
+
 int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
   if (const char *e = std::getenv("MFS_QR_NB")) {
     const int nb = std::atoi(e);
@@ -956,8 +969,9 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
   for (int i : idx) {
     const MatDesc &d = h[i];
     off.push_back(tot);
-    // a, tau, and T for the widest panel (cdiv(n, 16) panels of 64 x 64 bound every width)
-    tot += ((size_t)d.lda * d.n + d.n + (size_t)cdiv(d.n, 16) * 64 * 64 + 16) * sizeof(double2);
+    // a, tau, T for the widest panel (cdiv(n, 16) panels of 64 x 64 bound
+    // every width), and U (lda x n) formed from the identity
+    tot += ((size_t)2 * d.lda * d.n + d.n + (size_t)cdiv(d.n, 16) * 64 * 64 + 16) * sizeof(double2);
   }
   DevBuf buf(tot), dd;
   for (size_t k = 0; k < idx.size(); ++k) {
@@ -967,7 +981,19 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
     c.a = p; c.m = d.m; c.n = d.n; c.lda = d.lda;
     c.tau = p + (size_t)d.lda * d.n;
     c.T = c.tau + d.n;
+    c.u = c.T + (size_t)cdiv(d.n, 16) * 64 * 64;
+    c.ldu = d.lda;
     hc.push_back(c);
+  }
+  DevBuf ranks(hc.size() * sizeof(int));
+  {
+    std::vector<int> rk(hc.size());
+    for (size_t k = 0; k < hc.size(); ++k) {
+      rk[k] = hc[k].n;
+      hc[k].rank = ranks.as<int>() + k;
+    }
+    HIP_CHECK(hipMemcpyAsync(ranks.p, rk.data(), rk.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));   // rk goes out of scope
   }
   dd.alloc(hc.size() * sizeof(MatDesc));
   HIP_CHECK(hipMemcpyAsync(dd.p, hc.data(), hc.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s));
@@ -985,8 +1011,10 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
       for (size_t k = 0; k < idx.size(); ++k)
         HIP_CHECK(hipMemcpyAsync(hc[k].a, h[idx[k]].a, (size_t)hc[k].lda * hc[k].n * sizeof(double2),
                                  hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(tune_identity_kernel, dim3(nmax, (int)hc.size()), dim3(256), 0, s, dd.as<MatDesc>());
       HIP_CHECK(hipEventRecord(e0, s));
       qr_factor(dd.as<MatDesc>(), hc, s, nb);
+      qr_form_u(dd.as<MatDesc>(), hc, nmax, s, true, nb);
       HIP_CHECK(hipEventRecord(e1, s));
       HIP_CHECK(hipEventSynchronize(e1));
       HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
