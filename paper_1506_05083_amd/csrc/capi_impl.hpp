@@ -67,5 +67,8 @@ void check_apply_args(const mfs_op *op, int nrhs, const void *in, int in_layout,
 void launch_zero(double2 *p, long n, hipStream_t s);
 void launch_scale(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd,
                   const double *sdev, hipStream_t s);
+// the same into dst and dst2 (ld2 apart per wave) at once
+void launch_scale2(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd, double2 *dst2,
+                   size_t ld2, const double *sdev, hipStream_t s);
 
 }  // namespace mfs

@@ -57,6 +57,18 @@ __global__ void scale_kernel(int n, const double2 *__restrict__ src, size_t lds,
   dst[w * ldd + t] = cscale(src[w * lds + t], s[w]);
 }
 
+// dst[w][t] = dst2[w][t] = src[w][t] * s[w] (the next Krylov vector into the
+// basis and into the operator's input at once)
+__global__ void scale2_kernel(int n, const double2 *__restrict__ src, size_t lds, double2 *__restrict__ dst,
+                              size_t ldd, double2 *__restrict__ dst2, size_t ld2, const double *__restrict__ s) {
+  const int w = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double2 v = cscale(src[w * lds + t], s[w]);
+  dst[w * ldd + t] = v;
+  dst2[w * ld2 + t] = v;
+}
+
 __global__ void zero2_kernel(double2 *p, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     p[i] = cz(0.0, 0.0);
@@ -97,6 +109,12 @@ void launch_axpby_op(int nw, int n, const double2 *x, const double2 *g, const do
 void launch_scale(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd,
                   const double *sdev, hipStream_t s) {
   hipLaunchKernelGGL(scale_kernel, dim3(cdiv(n, 256), nw), dim3(256), 0, s, n, src, lds, dst, ldd, sdev);
+  HIP_CHECK(hipGetLastError());
+}
+
+void launch_scale2(int nw, int n, const double2 *src, size_t lds, double2 *dst, size_t ldd, double2 *dst2,
+                   size_t ld2, const double *sdev, hipStream_t s) {
+  hipLaunchKernelGGL(scale2_kernel, dim3(cdiv(n, 256), nw), dim3(256), 0, s, n, src, lds, dst, ldd, dst2, ld2, sdev);
   HIP_CHECK(hipGetLastError());
 }
 

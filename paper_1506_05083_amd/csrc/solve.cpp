@@ -16,6 +16,8 @@
 #include <complex>
 #include <vector>
 
+#include <string>
+
 #include "solver.hpp"
 
 namespace mfs {
@@ -70,6 +72,25 @@ void apply_solution_layouts(const mfs_op *op, const BodyData &b, int nrhs, const
 }  // namespace mfs
 
 using namespace mfs;
+
+namespace {
+// pinned host memory (hipHostMalloc), freed on every way out
+struct PinnedBuf {
+  void *p = nullptr;
+  explicit PinnedBuf(size_t n) {
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{MFS_ENOMEM, "hipHostMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  PinnedBuf(const PinnedBuf &) = delete;
+  PinnedBuf &operator=(const PinnedBuf &) = delete;
+};
+}  // namespace
 
 extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t body, const mfs_lattice *lat,
                                          int32_t nwaves, const mfs_wave *waves, double tol, int32_t maxit,
@@ -139,18 +160,21 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
     double2 *Zb = S.Z.as<double2>();
     double2 *Hd = S.H1.as<double2>();
     double *SCd = S.SC.as<double>();
-    std::vector<double2> hbuf((size_t)W * (maxit + 2) * 2);
+    // host side of the per-iteration exchange in pinned memory (DMA copies, no staging)
+    PinnedBuf hpin((size_t)W * (maxit + 2) * 2 * sizeof(double2) + (size_t)W * sizeof(double));
+    double2 *hbuf = static_cast<double2 *>(hpin.p);
+    double *scale = reinterpret_cast<double *>(hbuf + (size_t)W * (maxit + 2) * 2);
     // ||f||
     launch_dots(W, 1, MP, FH.as<double2>(), (size_t)MP, 0, FH.as<double2>(), Hd, s);
-    HIP_CHECK(hipMemcpyAsync(hbuf.data(), Hd, W * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(hbuf, Hd, W * sizeof(double2), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    std::vector<double> beta0(W), scale(W);
+    std::vector<double> beta0(W);
     for (int w = 0; w < W; ++w) {
       beta0[w] = std::sqrt(std::max(hbuf[w].x, 0.0));
       scale[w] = beta0[w] > 0 ? 1.0 / beta0[w] : 0.0;
     }
-    upload(SCd, scale.data(), W * sizeof(double), s);
-    launch_scale(W, MP, FH.as<double2>(), MP, V, ldw, SCd, s);
+    upload(SCd, scale, W * sizeof(double), s);
+    launch_scale2(W, MP, FH.as<double2>(), MP, V, ldw, S.XIN.as<double2>(), MP, SCd, s);
     std::vector<std::vector<cplx>> H(W, std::vector<cplx>((size_t)(maxit + 1) * maxit, 0.0));
     std::vector<std::vector<double>> cs(W, std::vector<double>(maxit, 0.0));
     std::vector<std::vector<cplx>> sn(W, std::vector<cplx>(maxit, 0.0)), g(W, std::vector<cplx>(maxit + 1, 0.0));
@@ -175,11 +199,8 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
     bool any_active = false;
     for (int w = 0; w < W; ++w) any_active |= active[w] != 0;
     for (int j = 0; j < maxit && any_active; ++j) {
-      const double2 *vj = V + (size_t)j * MP;
-      // z = Op(v_j): v_j of wave w is at V + w*ldw + j*MP; Op works on [W][MP] so gather
-      HIP_CHECK(hipMemcpy2DAsync(Zb, MP * sizeof(double2), vj, ldw * sizeof(double2), MP * sizeof(double2), W,
-                                 hipMemcpyDeviceToDevice, s));
-      HIP_CHECK(hipMemcpyAsync(S.XIN.p, Zb, (size_t)W * MP * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      // z = Op(v_j): v_j of every wave is in XIN as well ([W][MP], written
+      // with the basis vector)
       S.apply_op(S.XIN.as<double2>(), Zb);
       // CGS2
       const int nv = j + 1;
@@ -190,7 +211,7 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
       launch_update(W, nv, MP, V, ldw, MP, Zb, h2, nv, s);
       double2 *hn = h2 + (size_t)W * nv;
       launch_dots(W, 1, MP, Zb, (size_t)MP, 0, Zb, hn, s);
-      HIP_CHECK(hipMemcpyAsync(hbuf.data(), Hd, (size_t)W * (2 * nv + 1) * sizeof(double2),
+      HIP_CHECK(hipMemcpyAsync(hbuf, Hd, (size_t)W * (2 * nv + 1) * sizeof(double2),
                                hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
       any_active = false;
@@ -240,8 +261,8 @@ extern "C" mfs_status mfs_solve_incident(mfs_ctx *ctx, const mfs_op *op, int32_t
         progress("GMRES iteration %d: largest relative residual %.2e", j + 1, worst);
       }
       if (any_active) {
-        upload(SCd, scale.data(), W * sizeof(double), s);
-        launch_scale(W, MP, Zb, MP, V + (size_t)(j + 1) * MP, ldw, SCd, s);
+        upload(SCd, scale, W * sizeof(double), s);
+        launch_scale2(W, MP, Zb, MP, V + (size_t)(j + 1) * MP, ldw, S.XIN.as<double2>(), MP, SCd, s);
       }
     }
     bool notconv = false;
