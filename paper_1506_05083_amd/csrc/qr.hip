@@ -21,6 +21,7 @@
 //   bqr_update       C -= V W2 on the matrix cores.
 // The same three apply kernels with T in place of T^H, run over the panels
 // in reverse, form U = Q [U_R; 0] for the explicit left singular vectors.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -963,26 +964,35 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
     }
     idx.resize(keep);
   }
+  // a sample matrix of more than 2^25 elements (one matrix only) is timed on
+  // its leading block of about 2^25 elements, same aspect ratio
+  std::vector<int> sm(idx.size()), sn(idx.size()), sld(idx.size());
+  for (size_t k = 0; k < idx.size(); ++k) {
+    const MatDesc &d = h[idx[k]];
+    const double f = std::min(1.0, std::sqrt((double)((size_t)1 << 25) / ((double)d.m * d.n)));
+    sn[k] = std::max(1, std::min(d.n, (int)(d.n * f)));
+    sm[k] = std::max(sn[k], std::min(d.m, (int)(d.m * f)));
+    sld[k] = f < 1.0 ? round_up(sm[k], 16) : d.lda;
+  }
+  const int snmax = *std::max_element(sn.begin(), sn.end());
   std::vector<MatDesc> hc;
   std::vector<size_t> off;
   size_t tot = 0;
-  for (int i : idx) {
-    const MatDesc &d = h[i];
+  for (size_t k = 0; k < idx.size(); ++k) {
     off.push_back(tot);
     // a, tau, T for the widest panel (cdiv(n, 16) panels of 64 x 64 bound
     // every width), and U (lda x n) formed from the identity
-    tot += ((size_t)2 * d.lda * d.n + d.n + (size_t)cdiv(d.n, 16) * 64 * 64 + 16) * sizeof(double2);
+    tot += ((size_t)2 * sld[k] * sn[k] + sn[k] + (size_t)cdiv(sn[k], 16) * 64 * 64 + 16) * sizeof(double2);
   }
   DevBuf buf(tot), dd;
   for (size_t k = 0; k < idx.size(); ++k) {
-    const MatDesc &d = h[idx[k]];
     MatDesc c{};
     double2 *p = reinterpret_cast<double2 *>(static_cast<char *>(buf.p) + off[k]);
-    c.a = p; c.m = d.m; c.n = d.n; c.lda = d.lda;
-    c.tau = p + (size_t)d.lda * d.n;
-    c.T = c.tau + d.n;
-    c.u = c.T + (size_t)cdiv(d.n, 16) * 64 * 64;
-    c.ldu = d.lda;
+    c.a = p; c.m = sm[k]; c.n = sn[k]; c.lda = sld[k];
+    c.tau = p + (size_t)c.lda * c.n;
+    c.T = c.tau + c.n;
+    c.u = c.T + (size_t)cdiv(c.n, 16) * 64 * 64;
+    c.ldu = c.lda;
     hc.push_back(c);
   }
   DevBuf ranks(hc.size() * sizeof(int));
@@ -1009,12 +1019,13 @@ int qr_tuned_nb(const std::vector<MatDesc> &h, hipStream_t s) {
     // enough (50 ms) for the load to be lost in it
     for (int rep = 0; rep < 2 && (rep == 0 || ms < 50.f); ++rep) {
       for (size_t k = 0; k < idx.size(); ++k)
-        HIP_CHECK(hipMemcpyAsync(hc[k].a, h[idx[k]].a, (size_t)hc[k].lda * hc[k].n * sizeof(double2),
-                                 hipMemcpyDeviceToDevice, s));
-      hipLaunchKernelGGL(tune_identity_kernel, dim3(nmax, (int)hc.size()), dim3(256), 0, s, dd.as<MatDesc>());
+        HIP_CHECK(hipMemcpy2DAsync(hc[k].a, (size_t)hc[k].lda * sizeof(double2), h[idx[k]].a,
+                                   (size_t)h[idx[k]].lda * sizeof(double2), (size_t)hc[k].m * sizeof(double2),
+                                   hc[k].n, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(tune_identity_kernel, dim3(snmax, (int)hc.size()), dim3(256), 0, s, dd.as<MatDesc>());
       HIP_CHECK(hipEventRecord(e0, s));
       qr_factor(dd.as<MatDesc>(), hc, s, nb);
-      qr_form_u(dd.as<MatDesc>(), hc, nmax, s, true, nb);
+      qr_form_u(dd.as<MatDesc>(), hc, snmax, s, true, nb);
       HIP_CHECK(hipEventRecord(e1, s));
       HIP_CHECK(hipEventSynchronize(e1));
       HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
