@@ -46,7 +46,8 @@ template <int NB> struct VhyShape;
 template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0; };
 template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1; };
 template <> struct VhyShape<16> { static constexpr int YT = 64, IB = 1, CB = 1, OCC = 4, DB = 1; };
-constexpr int W2T = 16;     // columns per workgroup in W2 (the slices' sum spread over more workgroups)
+constexpr int W2T = 16;     // columns per W2 tile (the slices' sum spread over more workgroups)
+constexpr int W2WG = 8192;  // workgroups a W2 launch aims at; beyond it a workgroup takes several tiles
 
 // element r of Householder vector i of the panel starting at column k0
 __device__ inline double2 vel(const MatDesc &d, int k0, int i, int r) {
@@ -574,12 +575,22 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
 
 // W2[mat][i][c] = sum_h op(T)[i][h] W[h][c], W = V^H B summed over the slices;
 // op(T) = T^H (trans, QR) or T; T from Tx[mat] if Tx is set (bqr_t_kernel).
+// T is upper triangular: a workgroup stages its triangle once in LDS (packed
+// by columns, entry (r, c) at c (c + 1) / 2 + r, half of the square's LDS, so
+// three workgroups share a CU) and then takes W2T-column tiles gridDim.x
+// apart, so that a batch of many small matrices stages each T once per
+// several tiles instead of once per tile.  A thread holds one column of the
+// tile and the NB / 16 rows g, g + 16, ... and accumulates them side by side.
+// (256-obstacle batch, 64-column panels: 1.65 ms a launch with the square T
+// staged per 16-column tile at one workgroup a CU and one output at a time.)
 template <int NB>
-__global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__ descs, int k0, int which,
+__global__ __launch_bounds__(256, 3) void bqr_w2_kernel(const MatDesc *__restrict__ descs, int k0, int which,
                                                      int withV, int trans, int cend,
                                                      const double2 *__restrict__ P, int ldp, int nkcmax,
                                                      double2 *__restrict__ W2, int ldw,
                                                      const double2 *__restrict__ Tx) {
+  static_assert(W2T == 16 && NB % 16 == 0, "a thread: one column of the tile, rows 16 apart");
+  constexpr int R = NB / 16;
   const MatDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
@@ -587,47 +598,63 @@ __global__ __launch_bounds__(256) void bqr_w2_kernel(const MatDesc *__restrict__
   int ldb, nb_cols;
   y_source(d, k0, nbp, which, B, ldb, nb_cols);
   if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
-  const int c0 = blockIdx.x * W2T;
-  if (c0 >= nb_cols) return;
+  if ((int)blockIdx.x * W2T >= nb_cols) return;
   const int nv = withV ? NB : 0;
   const int nkc = (d.m - k0 + KR - 1) / KR;
-  __shared__ double2 Ts[NB][NB + 1];
+  __shared__ double2 Tp[NB * (NB + 1) / 2];
   __shared__ double2 Ws[NB][W2T + 1];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, cc = tid % W2T, g = tid / W2T;
   const double2 *T = Tx ? Tx + (size_t)blockIdx.y * NB * NB : d.T + (size_t)(k0 / NB) * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = T[idx];
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    if (r <= c) Tp[c * (c + 1) / 2 + r] = T[idx];
+  }
   const double2 *base = P + (size_t)blockIdx.y * nkcmax * NB * ldp;
-  {
-    double2 t[NB * W2T / 256];
+  double2 *out = W2 + (size_t)blockIdx.y * NB * ldw;
+  for (int c0 = blockIdx.x * W2T; c0 < nb_cols; c0 += gridDim.x * W2T) {
+    const int c = c0 + cc;
+    const bool live = c < nb_cols;
+    double2 t[R];
 #pragma unroll
-    for (int u = 0; u < NB * W2T / 256; ++u) t[u] = cz(0.0, 0.0);
+    for (int u = 0; u < R; ++u) t[u] = cz(0.0, 0.0);
 #pragma unroll 6
     for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
-      for (int u = 0; u < NB * W2T / 256; ++u) {
-        const int idx = tid + 256 * u, cc = idx % W2T, i = idx / W2T;
-        t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + i) * ldp + nv + c0 + cc, c0 + cc < nb_cols));
+      for (int u = 0; u < R; ++u)
+        t[u] = cadd(t[u], ld_or0(base, ((size_t)kc * NB + g + 16 * u) * ldp + nv + c, live));
+    }
+    __syncthreads();   // Tp staged; the previous tile's products are done with Ws
+#pragma unroll
+    for (int u = 0; u < R; ++u) Ws[g + 16 * u][cc] = t[u];
+    __syncthreads();
+    double2 acc[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) acc[u] = cz(0.0, 0.0);
+    if (trans) {
+#pragma unroll 4
+      for (int h = 0; h < NB; ++h) {
+        const double2 w = Ws[h][cc];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int i = g + 16 * u;
+          if (h <= i) cfmac(acc[u], Tp[i * (i + 1) / 2 + h], w);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int h = 0; h < NB; ++h) {
+        const double2 w = Ws[h][cc];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int i = g + 16 * u;
+          if (h >= i) cfma(acc[u], Tp[h * (h + 1) / 2 + i], w);
+        }
       }
     }
+    if (live) {
 #pragma unroll
-    for (int u = 0; u < NB * W2T / 256; ++u) {
-      const int idx = tid + 256 * u;
-      Ws[idx / W2T][idx % W2T] = t[u];
+      for (int u = 0; u < R; ++u) out[(size_t)(g + 16 * u) * ldw + c] = acc[u];
     }
-  }
-  __syncthreads();
-  double2 *out = W2 + (size_t)blockIdx.y * NB * ldw;
-  for (int idx = tid; idx < NB * W2T; idx += 256) {
-    const int cc = idx % W2T, i = idx / W2T;
-    const int c = c0 + cc;
-    if (c >= nb_cols) continue;
-    double2 acc = cz(0.0, 0.0);
-    if (trans) {
-      for (int h = 0; h <= i; ++h) cfmac(acc, Ts[h][i], Ws[h][cc]);
-    } else {
-      for (int h = i; h < NB; ++h) cfma(acc, Ts[i][h], Ws[h][cc]);
-    }
-    out[(size_t)i * ldw + c] = acc;
   }
 }
 
@@ -758,7 +785,8 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
     hipLaunchKernelGGL(bqr_t_kernel<NB>, dim3(nmat), dim3(256), 0, s, descs, k0, w.P.as<double2>(), w.ldp,
                        w.nkcmax, Tx);
   if (ncols_max > 0) {
-    hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(cdiv(ncols_max, W2T), nmat), dim3(256), 0, s, descs, k0, which,
+    const int w2x = std::min(cdiv(ncols_max, W2T), std::max(1, cdiv(W2WG, nmat)));
+    hipLaunchKernelGGL(bqr_w2_kernel<NB>, dim3(w2x, nmat), dim3(256), 0, s, descs, k0, which,
                        withV, trans, cend, w.P.as<double2>(), w.ldp, w.nkcmax, w.W2.as<double2>(), w.ldw, Tx);
     hipLaunchKernelGGL(bqr_update_kernel<NB>,
                        dim3(cdiv(ncols_max, UpdShape::UC), cdiv(std::max(mmax - k0, 1), UpdShape::UR), nmat),
