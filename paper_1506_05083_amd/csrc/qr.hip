@@ -15,7 +15,7 @@
 //     partial sums of step s + 1.
 // The trailing matrix is updated with the compact-WY form
 // C <- (I - V T V^H)^H C = C - V T^H (V^H C):
-//   bqr_vhy_kernel   P = V^H [V | C], split over 256-row slices (partials);
+//   bqr_vhy_kernel   P = V^H [V | C], split over row slices (partials);
 //   bqr_t_kernel     T from the V^H V part (forward, columnwise);
 //   bqr_w2_kernel    W2 = op(T) (V^H C), the slices summed;
 //   bqr_update       C -= V W2 on the matrix cores.
@@ -35,17 +35,19 @@ namespace mfs {
 namespace {
 
 constexpr int CH = 256;     // rows per workgroup in the panel column step
-constexpr int KR = 256;     // rows per workgroup of V^H Y (split-K slice)
+constexpr int KRMIN = 256;  // fewest rows of a V^H Y split-K slice (sizes the partials' buffer)
 constexpr int KS = 16;      // rows per LDS stage in V^H Y
 // V^H Y tiles: YT columns of Y a workgroup, a wave IB x CB blocks of 16 x 16
 // of the NB x YT tile, OCC waves a SIMD, DB: LDS stages double-buffered (one
-// barrier a stage).  Measured on 8 matrices 4608 x 1275: 64-column panels
+// barrier a stage), KR rows a workgroup (one split-K slice: each slice writes
+// an NB-row partial of P that W2 and T read back, so the 64-wide panels take
+// 512-row slices to halve that traffic).  Measured on 8 matrices 4608 x 1275: 64-column panels
 // 54 TFLOP/s (43 with one 16-row block of V^H and four column blocks a wave
 // and the fragments loaded per product), 32: 43 (33), 16: 3.8 TB/s of Y.
 template <int NB> struct VhyShape;
-template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0; };
-template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1; };
-template <> struct VhyShape<16> { static constexpr int YT = 64, IB = 1, CB = 1, OCC = 4, DB = 1; };
+template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0, KR = 512; };
+template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1, KR = 256; };
+template <> struct VhyShape<16> { static constexpr int YT = 64, IB = 1, CB = 1, OCC = 4, DB = 1, KR = 256; };
 constexpr int W2T = 16;     // columns per W2 tile (the slices' sum spread over more workgroups)
 constexpr int W2WG = 8192;  // workgroups a W2 launch aims at; beyond it a workgroup takes several tiles
 
@@ -374,7 +376,8 @@ __global__ __launch_bounds__(256, VhyShape<NB>::OCC) void bqr_vhy_kernel(const M
                                                                         double2 *__restrict__ P, int ldp,
                                                                         int nkcmax) {
   using S = VhyShape<NB>;
-  constexpr int YT = S::YT, IB = S::IB, CB = S::CB, DB = S::DB;
+  constexpr int YT = S::YT, IB = S::IB, CB = S::CB, DB = S::DB, KR = S::KR;
+  static_assert(KR >= KRMIN && KR % KS == 0, "a slice is whole LDS stages");
   constexpr int NWI = NB / 16 / IB;   // waves along the rows of P
   static_assert(NWI * (YT / 16 / CB) == 4, "four waves cover the tile");
   const MatDesc d = descs[blockIdx.z];
@@ -504,6 +507,7 @@ __global__ __launch_bounds__(256) void bqr_t_kernel(const MatDesc *__restrict__ 
   const MatDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int nbp = min(NB, d.n - k0);
+  constexpr int KR = VhyShape<NB>::KR;
   const int nkc = (d.m - k0 + KR - 1) / KR;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ double2 gram[NB][NB + 1];
@@ -600,6 +604,7 @@ __global__ __launch_bounds__(256, 3) void bqr_w2_kernel(const MatDesc *__restric
   if (which == 0) nb_cols = min(nb_cols, cend - (k0 + nbp));
   if ((int)blockIdx.x * W2T >= nb_cols) return;
   const int nv = withV ? NB : 0;
+  constexpr int KR = VhyShape<NB>::KR;
   const int nkc = (d.m - k0 + KR - 1) / KR;
   __shared__ double2 Tp[NB * (NB + 1) / 2];
   __shared__ double2 Ws[NB][W2T + 1];
@@ -762,7 +767,7 @@ struct ApplyWork {
   void size(int nmat, int mmax, int ncols, int nb) {
     ldp = nb + ncols;
     ldw = std::max(ncols, 1);
-    nkcmax = cdiv(std::max(mmax, 1), KR);
+    nkcmax = cdiv(std::max(mmax, 1), KRMIN);
     P.alloc((size_t)nmat * nkcmax * nb * ldp * sizeof(double2));
     W2.alloc((size_t)nmat * nb * ldw * sizeof(double2));
   }
@@ -777,7 +782,7 @@ void apply_panel(const MatDesc *descs, int nmat, int mmax, int ncols_max, int k0
                  int trans, ApplyWork &w, bool build_t, hipStream_t s, int cend = kNoEnd,
                  double2 *Tx = nullptr) {
   const int ny = (withV ? NB : 0) + ncols_max;
-  const int nkc = cdiv(std::max(mmax - k0, 1), KR);
+  const int nkc = cdiv(std::max(mmax - k0, 1), VhyShape<NB>::KR);
   if (ny > 0)
     hipLaunchKernelGGL(bqr_vhy_kernel<NB>, dim3(cdiv(ny, VhyShape<NB>::YT), nkc, nmat), dim3(256), 0, s, descs, k0, which, withV,
                        cend, w.P.as<double2>(), w.ldp, w.nkcmax);
