@@ -36,6 +36,7 @@
 #include <cmath>
 
 #include <string>
+#include <thread>
 
 #include "gpinv.hpp"
 
@@ -805,28 +806,54 @@ void graded_pinv(GradedPinv &g, const std::vector<MatDesc> &in, double rel_cutof
   std::vector<int> perm((size_t)W * nmax, 0), n2(W), rr(W);
   std::vector<double> scale(equilibrate ? (size_t)W * nmax : 0, 0.0);
   g.maxcol.assign(W, 0.0);
-  for (int w = 0; w < W; ++w) {
-    const int n = in[w].n;
-    const double *nw = hn.data() + (size_t)w * nmax;
-    double mx = 0.0;
-    for (int c = 0; c < n; ++c) mx = std::max(mx, nw[c]);
-    // equilibrated: every kept column scaled to unit norm (the largest is 1);
-    // only columns that vanish, or whose scaling would leave the exponent
-    // range, are dropped
-    g.maxcol[w] = equilibrate ? 1.0 : mx;
-    const double keep_min = equilibrate ? 1e-250 * mx : 1e-15 * mx;
+  // Matrices are independent: a batch of thousands spreads its selection
+  // over host threads (one thread takes tens of milliseconds for the
+  // 256-obstacle build's chunks, while the device waits).  bad[w]: 1 zero
+  // matrix, 2 more columns kept than rows, 3 out of host memory.
+  std::vector<char> bad(W, 0);
+  auto select = [&](int w0, int w1) {
     std::vector<int> idx;
-    for (int c = 0; c < n; ++c)
-      if (nw[c] >= keep_min && nw[c] > 0.0 && mx > 0.0) {
-        idx.push_back(c);
-        if (equilibrate) scale[(size_t)w * nmax + c] = 1.0 / nw[c];
+    for (int w = w0; w < w1; ++w) {
+      try {
+        const int n = in[w].n;
+        const double *nw = hn.data() + (size_t)w * nmax;
+        double mx = 0.0;
+        for (int c = 0; c < n; ++c) mx = std::max(mx, nw[c]);
+        // equilibrated: every kept column scaled to unit norm (the largest is 1);
+        // only columns that vanish, or whose scaling would leave the exponent
+        // range, are dropped
+        g.maxcol[w] = equilibrate ? 1.0 : mx;
+        const double keep_min = equilibrate ? 1e-250 * mx : 1e-15 * mx;
+        idx.clear();
+        for (int c = 0; c < n; ++c)
+          if (nw[c] >= keep_min && nw[c] > 0.0 && mx > 0.0) {
+            idx.push_back(c);
+            if (equilibrate) scale[(size_t)w * nmax + c] = 1.0 / nw[c];
+          }
+        // largest norm first; ties keep their column order
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return nw[x] > nw[y]; });
+        n2[w] = (int)idx.size();
+        if (n2[w] < 1) { bad[w] = 1; continue; }
+        if (n2[w] > in[w].m) { bad[w] = 2; continue; }
+        std::copy(idx.begin(), idx.end(), perm.begin() + (size_t)w * nmax);
+      } catch (const std::bad_alloc &) {
+        bad[w] = 3;
       }
-    // largest norm first; ties keep their column order
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return nw[x] > nw[y]; });
-    n2[w] = (int)idx.size();
-    MFS_REQUIRE(n2[w] >= 1, "graded pseudoinverse: matrix is zero");
-    MFS_REQUIRE(n2[w] <= in[w].m, "graded pseudoinverse: more independent columns than rows");
-    std::copy(idx.begin(), idx.end(), perm.begin() + (size_t)w * nmax);
+    }
+  };
+  const int nth = W >= 256 ? (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  if (nth == 1) {
+    select(0, W);
+  } else {
+    std::vector<std::thread> th;
+    const int per = cdiv(W, nth);
+    for (int w0 = 0; w0 < W; w0 += per) th.emplace_back(select, w0, std::min(W, w0 + per));
+    for (auto &t : th) t.join();
+  }
+  for (int w = 0; w < W; ++w) {
+    MFS_REQUIRE(bad[w] != 1, "graded pseudoinverse: matrix is zero");
+    MFS_REQUIRE(bad[w] != 2, "graded pseudoinverse: more independent columns than rows");
+    if (bad[w] == 3) MFS_THROW(MFS_ENOMEM, "graded pseudoinverse: out of host memory ordering the columns");
   }
   g.perm.alloc(perm.size() * sizeof(int));
   HIP_CHECK(hipMemcpyAsync(g.perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, s));
