@@ -40,10 +40,12 @@ constexpr int KS = 16;      // rows per LDS stage in V^H Y
 // V^H Y tiles: YT columns of Y a workgroup, a wave IB x CB blocks of 16 x 16
 // of the NB x YT tile, OCC waves a SIMD, DB: LDS stages double-buffered (one
 // barrier a stage), KR rows a workgroup (one split-K slice: each slice writes
-// an NB-row partial of P that W2 and T read back, so the 64-wide panels take
-// 512-row slices to halve that traffic).  Measured on 8 matrices 4608 x 1275: 64-column panels
-// 54 TFLOP/s (43 with one 16-row block of V^H and four column blocks a wave
-// and the fragments loaded per product), 32: 43 (33), 16: 3.8 TB/s of Y.
+// an NB-row partial of P that W2 and T read back).  Measured on 8 matrices
+// 4608 x 1275 with 256-row slices: 64-column panels 54 TFLOP/s (43 with one
+// 16-row block of V^H and four column blocks a wave and the fragments loaded
+// per product), 32: 43 (33), 16: 3.8 TB/s of Y.  The 64-wide panels take
+// 512-row slices: on that shape V^H Y is 8% slower and W2 as much faster, on
+// the 25088-row Q of the large cup the QR and U formation gain 2%.
 template <int NB> struct VhyShape;
 template <> struct VhyShape<64> { static constexpr int YT = 64, IB = 2, CB = 2, OCC = 2, DB = 0, KR = 512; };
 template <> struct VhyShape<32> { static constexpr int YT = 64, IB = 1, CB = 2, OCC = 3, DB = 1, KR = 256; };
